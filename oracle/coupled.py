@@ -1,0 +1,120 @@
+"""The IGA-ADS-CRVPINN coupled algorithm (oracle, test infrastructure).
+
+Follows the IGA-ADS-CRVPINN algorithm section of the paper:
+  1. inputs K, phi, sources, viscosities and S^0 as B-spline coefficients;
+  2. pretrain the network on the robust loss with S^0;
+  3. n = 1;
+  4. L2-project the nodal network pressure into the B-spline space;
+  5-6. explicit saturation update (eq. 6), repeated ten times with that pressure;
+  7. retrain the network (100 Adam iterations) with the new saturation;
+  8. stop or continue.
+
+Readings:
+  * step 8 returns to step 4, so every coupled step re-projects the pressure
+    the network has just been trained to;
+  * one coupled step of length dt runs the ten substeps with tau = dt / 10;
+  * the nodal saturation used for alpha is the spline evaluated at the nodes;
+  * Adam moments and step count persist across pretraining and all steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ads, mlp, pressure, wells as wells_mod
+
+
+class Oracle:
+    def __init__(self, dim, n_elem, degree, width, hidden, log_perm, porosity, wells,
+                 theta0, s0_coefs=None, mu_w=1.0, mu_g=0.1, relperm_exp=2.0,
+                 lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, adam_iters=100,
+                 substeps=10, well_radius=0.06):
+        self.dim, self.n_elem, self.r = dim, n_elem, degree
+        self.dims = mlp.layer_dims(dim, width, hidden)
+        self.mu_w, self.mu_g, self.n_exp = mu_w, mu_g, relperm_exp
+        self.adam_iters, self.substeps = adam_iters, substeps
+        self.perm = np.exp(np.asarray(log_perm, dtype=np.float64))
+        self.poro = np.asarray(porosity, dtype=np.float64)
+        self.q_inj, self.q_prod = wells_mod.nodal_sources(wells, n_elem, dim, well_radius)
+        self.q = self.q_inj + self.q_prod
+        self.space = ads.Space(n_elem, degree, dim)
+        nb = self.space.nb
+        self.s = (np.zeros((nb,) * dim) if s0_coefs is None
+                  else np.asarray(s0_coefs, dtype=np.float64).reshape((nb,) * dim).copy())
+        self.theta = np.asarray(theta0, dtype=np.float64).copy()
+        self.adam = mlp.Adam(self.theta.size, lr, beta1, beta2, eps)
+        self.z = mlp.node_inputs(n_elem, dim)
+        self.mask = pressure.interior_mask(n_elem, dim)
+        self.loss_history = []
+        self.refresh()
+
+    # algorithm step 1 / after step 6: alpha from the current saturation
+    def refresh(self):
+        self.s_nodal = self.space.at_nodes(self.s)
+        self.alpha = pressure.alpha_nodal(self.s_nodal, self.perm, self.mu_w,
+                                          self.mu_g, self.n_exp)
+
+    def u_nodal(self, theta=None):
+        th = self.theta if theta is None else theta
+        out = mlp.forward(th, self.dims, self.z)[-1]
+        return self.mask * out.reshape(self.mask.shape)
+
+    def loss_and_grad(self, theta=None):
+        """Robust loss and its gradient with respect to the flat parameters."""
+        th = self.theta if theta is None else theta
+        acts = mlp.forward(th, self.dims, self.z)
+        u = self.mask * acts[-1].reshape(self.mask.shape)
+        res = pressure.residual(u, self.alpha, self.q)
+        q = pressure.gram_solve(res)
+        lval = pressure.loss(res, q)
+        gu = pressure.grad_u(q, self.alpha) * self.mask
+        g = mlp.backward(th, self.dims, acts, gu.ravel())
+        return lval, g
+
+    def loss_grad_logperm(self, theta=None):
+        """dLOSS/dlogK = dLOSS/dalpha * alpha (alpha is linear in K = e^logK)."""
+        th = self.theta if theta is None else theta
+        u = self.u_nodal(th)
+        res = pressure.residual(u, self.alpha, self.q)
+        q = pressure.gram_solve(res)
+        return pressure.grad_alpha(u, q) * self.alpha
+
+    def train(self, iters):
+        for _ in range(iters):
+            lval, g = self.loss_and_grad()
+            self.loss_history.append(lval)
+            self.theta = self.adam.step(self.theta, g)
+
+    def pretrain(self, iters):
+        self.train(iters)
+
+    def project_pressure(self):
+        return ads.project_nodal(self.space, self.u_nodal())
+
+    def step(self, dt):
+        p = self.project_pressure()
+        tau = dt / self.substeps
+        for _ in range(self.substeps):
+            self.s = ads.saturation_substep(self.space, self.s, p, self.perm, self.poro,
+                                            self.q_inj, self.q_prod, tau, self.mu_w,
+                                            self.mu_g, self.n_exp)
+        self.refresh()
+        self.train(self.adam_iters)
+
+    def fields(self):
+        return self.u_nodal(), self.s.copy(), self.space.at_nodes(self.s)
+
+    def direct_pressure(self):
+        return pressure.direct_solve(self.alpha, self.q)
+
+
+def cfl_dt(orc: Oracle, cfl: float = 0.5) -> float:
+    """Step length from a CFL number (the configurations state only "CFL 0.5"):
+    dt = cfl * h_e * phi_min / (max_s lambda_g'(s) * max_p K_p |nabla_+ p0_p|),
+    with p0 the direct solve of the current pressure system and
+    max lambda_g' = n / mu_g for kr_g = s^n on [0, 1]."""
+    p0 = orc.direct_pressure()
+    g = pressure.grad_plus_norm(p0)
+    ne = orc.n_elem
+    kmax = np.max(orc.perm[tuple(slice(0, ne) for _ in range(orc.dim))] * g)
+    dlam = orc.n_exp / orc.mu_g
+    return float(cfl * (1.0 / ne) * orc.poro.min() / (dlam * kmax))

@@ -1,0 +1,71 @@
+"""Pins of the oracle's coupled algorithm on a tiny problem: the parameter
+gradient against central finite differences of the robust loss (whole chain,
+including the boundary mask), the loss against a dense Gram inverse, the
+saturation mass balance over a coupled step, and basic algorithm invariants."""
+import numpy as np
+
+from oracle import Oracle, cfl_dt, pressure
+from paper_2604_20731_amd import inputs
+
+
+def _tiny(**kw):
+    p = inputs.make_problem("tiny", **kw)
+    return p, Oracle(p.dim, p.n_elem, p.degree, p.width, p.hidden, p.log_perm,
+                     p.porosity, p.wells, p.theta0)
+
+
+def test_theta_gradient_matches_central_differences():
+    p, o = _tiny()
+    th = o.theta + 0.05 * np.random.default_rng(0).standard_normal(o.theta.size)
+    _, g = o.loss_and_grad(th)
+    eps = 1e-6
+    for k in np.random.default_rng(1).choice(th.size, size=20, replace=False):
+        e = np.zeros_like(th); e[k] = eps
+        fd = (o.loss_and_grad(th + e)[0] - o.loss_and_grad(th - e)[0]) / (2 * eps)
+        assert abs(g[k] - fd) < 1e-7 * max(1.0, abs(fd)), k
+
+
+def test_loss_equals_dense_gram_form():
+    p, o = _tiny()
+    u = o.u_nodal()
+    res = pressure.residual(u, o.alpha, o.q)
+    g = pressure.gram_matrix(p.n_elem, 2).toarray()
+    dense = float(res.ravel() @ np.linalg.solve(g, res.ravel()))
+    assert abs(o.loss_and_grad()[0] - dense) < 1e-12 * max(1, dense)
+
+
+def test_logperm_gradient_matches_central_differences():
+    p, o = _tiny()
+    g = o.loss_grad_logperm()
+    eps = 1e-6
+    base = o.perm.copy()
+    for k in np.random.default_rng(2).choice(base.size, size=10, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            lk = np.log(base).ravel().copy(); lk[k] += sgn * eps
+            o.perm = np.exp(lk).reshape(base.shape)
+            o.refresh()
+            vals.append(o.loss_and_grad()[0])
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(g.ravel()[k] - fd) < 1e-7 * max(1.0, abs(fd))
+    o.perm = base
+    o.refresh()
+
+
+def test_pretrain_and_step_invariants():
+    wells = np.array([[0.375, 0.5, 1.0], [0.625, 0.375, 0.5]])
+    p, o = _tiny(wells=wells)
+    l0 = o.loss_and_grad()[0]
+    o.pretrain(30)
+    assert o.loss_history[0] == l0 and o.loss_history[-1] < l0
+    dt = cfl_dt(o)
+    assert dt > 0
+    mass0 = float(np.sum(o.space.mass_full() @ o.s.ravel()))
+    o.step(dt)
+    u, s, sn = o.fields()
+    mass1 = float(np.sum(o.space.mass_full() @ s.ravel()))
+    # injectors only, uniform porosity 0.2: the gas volume grows by dt * sum(rate) / phi
+    assert abs((mass1 - mass0) - dt * wells[:, 2].sum() / 0.2) < 1e-12
+    assert np.all(u[0] == 0) and np.all(u[-1] == 0) and np.all(u[:, 0] == 0)
+    assert s.shape == (p.n_elem + 2,) * 2 and sn.shape == (p.n_elem + 1,) * 2
+    assert len(o.loss_history) == 30 + o.adam_iters
