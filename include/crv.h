@@ -1,0 +1,167 @@
+/*
+ * crv.h - C ABI of libcrv, the MI355X (gfx950) hot path of the hybrid
+ * IGA-ADS-CRVPINN CO2-sequestration time step (arXiv 2604.20731).
+ *
+ * The calls follow the paper's statement of the IGA-ADS-CRVPINN algorithm:
+ *   crv_init              step 1: permeability, porosity, wells, viscosities,
+ *                         initial saturation given as B-spline coefficients;
+ *   crv_pretrain_pressure step 2: Adam on the robust loss (eq. 27) with S^0;
+ *   crv_step              steps 4-7: L2 projection of the network pressure,
+ *                         ten explicit saturation substeps (eq. 6 in the
+ *                         Galerkin form of eq. 10-13, mass matrix of eq. 14),
+ *                         retraining of the pressure network;
+ *   crv_get_fields        the pressure map and the saturation.
+ * Further calls expose single pieces of the path (robust loss and its
+ * gradients, Gram and mass solves, projection, substeps) and the training
+ * state, for verification, differentiation and checkpoint/resume.
+ *
+ * Discretisation (readings of the paper, fixed here):
+ *   - unit square/cube, Ne elements per axis; collocation N = Ne, nodes
+ *     x_i = i/N, i = 0..N (eq. 21), (N+1)^d nodes;
+ *   - B-splines of degree r on open uniform knots, nb = Ne + r per axis;
+ *   - pressure -div(alpha grad p) = q, p = 0 on the boundary, gravity zero;
+ *     alpha = K (kr_w(s)/mu_w + kr_g(s)/mu_g), kr_w = (1-s)^n, kr_g = s^n at
+ *     s = clamp(S, 0, 1) (second eq. 23 with Brooks-Corey mobilities);
+ *   - RES_k = a_h(u, delta_k) - (q, delta_k)_h at interior nodes (eq. 24-25),
+ *     G = (delta, delta)_{nabla,h} (eq. 26, no h^-2 factor), LOSS = RES.G^-1 RES;
+ *   - network u = m NN_theta(2x - 1), m = 0 on the boundary, tanh hidden
+ *     layers, linear output.
+ *
+ * Array layouts (all host arrays are float64, C order, x fastest):
+ *   nodal      (N+1)^d        index ((k*(N+1)) + j)*(N+1) + i
+ *   interior   (N-1)^d        node (i,j[,k]) with 1 <= i,j,k <= N-1
+ *   coefs      nb^d           index ((c*nb) + b)*nb + a
+ *   wells      n_wells x 3    rows (x, y, rate); rate > 0 injects gas
+ *   theta      n_params       per layer W (out x in, row-major) then b (out),
+ *                             layers d -> width (x hidden, tanh) -> 1
+ *
+ * Ownership: host input arrays are read during the call and may be freed
+ * afterwards.  The device workspace (d_workspace, ws_bytes) belongs to the
+ * caller, must stay alive until crv_destroy and is never freed by the
+ * library; with d_workspace == NULL the library allocates and owns it.
+ * Output arrays are caller-allocated host buffers of the stated sizes.
+ *
+ * Errors: every call returns a crv_status; no C++ exception crosses the ABI.
+ * crv_last_error() returns a thread-local message for the last failure.
+ * A context is not thread-safe; all its work is ordered on its stream.
+ */
+#ifndef CRV_H
+#define CRV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CRV_OK = 0,
+  CRV_EINVAL = -1,   /* bad configuration, shape, value or argument */
+  CRV_ENOMEM = -2,   /* workspace too small or device allocation failed */
+  CRV_EHIP = -3,     /* HIP runtime error */
+  CRV_ENUMERIC = -4, /* NaN/Inf found in the loss or the saturation */
+  CRV_ESTATE = -5    /* call not allowed in the current state */
+} crv_status;
+
+typedef enum {
+  CRV_PREC_FP32 = 0, /* fields, solves and network in float32 */
+  CRV_PREC_BF16 = 1, /* network products in bf16 on MFMA, float32 accumulate;
+                        everything else float32 */
+  CRV_PREC_FP64 = 2  /* everything in float64 (verification mode) */
+} crv_precision;
+
+typedef struct {
+  int dim;              /* 2 or 3 */
+  int n_elem;           /* Ne per axis, 4 <= Ne <= 1024 (3D: <= 256) */
+  int degree;           /* B-spline degree r: 1, 2 or 3 */
+  int width;            /* hidden width: 16, 32, 64 or 128 */
+  int hidden;           /* number of tanh hidden layers, 1..8 */
+  int precision;        /* crv_precision */
+  double mu_w, mu_g;    /* brine and gas viscosities */
+  double relperm_exp;   /* Brooks-Corey exponent n */
+  double lr, beta1, beta2, eps; /* Adam */
+  int adam_iters;       /* Adam iterations per coupled step (100) */
+  int substeps;         /* saturation substeps per coupled step (10) */
+  double well_radius;   /* well disc radius */
+} crv_config;
+
+typedef struct crv_ctx crv_ctx;
+
+/* Defaults: 2D, Ne 32, r 2, width 32, 3 hidden layers, FP32, mu_w 1,
+ * mu_g 0.1, n 2, Adam lr 1e-4 (the paper's value), beta (0.9, 0.999),
+ * eps 1e-8, 100 iterations and 10 substeps per step, well radius 0.06. */
+crv_status crv_config_default(crv_config* cfg);
+
+/* Number of network parameters for cfg. */
+crv_status crv_param_count(const crv_config* cfg, int64_t* n);
+
+/* Device bytes crv_init needs for cfg (workspace footprint). */
+crv_status crv_workspace_size(const crv_config* cfg, size_t* bytes);
+
+/* Algorithm step 1.  log_perm, porosity: nodal (N+1)^d; porosity > 0.
+ * wells: n_wells x 3; every well disc (3D: vertical cylinder over the
+ * interior z nodes) must cover at least one node and no boundary node.
+ * s0_coefs: nb^d initial saturation coefficients, NULL for zero.
+ * theta0: initial network parameters (crv_param_count values).
+ * stream: a hipStream_t (NULL = default stream).  On success *out holds the
+ * context.  Returns CRV_EINVAL for invalid input, CRV_ENOMEM when ws_bytes
+ * is below crv_workspace_size. */
+crv_status crv_init(const crv_config* cfg, const double* log_perm, const double* porosity,
+                    const double* wells, int n_wells, const double* s0_coefs,
+                    const double* theta0, void* d_workspace, size_t ws_bytes,
+                    void* stream, crv_ctx** out);
+
+/* Algorithm step 2 (and step 7): iters Adam iterations on the robust loss
+ * with the current saturation.  final_loss (nullable) receives the loss of
+ * the last iteration (evaluated before its update).  Blocks until done. */
+crv_status crv_pretrain_pressure(crv_ctx* ctx, int iters, double* final_loss);
+
+/* Algorithm steps 4-7, one coupled step of length dt > 0: project the
+ * network pressure, cfg.substeps substeps of tau = dt/substeps, refresh
+ * alpha from the new saturation, cfg.adam_iters Adam iterations.
+ * Asynchronous on the context's stream; errors of the device work (NaN
+ * saturation) surface as CRV_ENUMERIC at the next synchronising call. */
+crv_status crv_step(crv_ctx* ctx, double dt);
+
+/* Outputs (any may be NULL): p_nodal (N+1)^d network pressure m*NN,
+ * s_coefs nb^d, s_nodal (N+1)^d saturation at the nodes. Synchronises. */
+crv_status crv_get_fields(crv_ctx* ctx, double* p_nodal, double* s_coefs, double* s_nodal);
+
+/* Robust loss of the current parameters and its gradients (differentiation
+ * form): dtheta (n_params) and dlogperm ((N+1)^d), both nullable.  Does not
+ * change the training state. */
+crv_status crv_loss_grad(crv_ctx* ctx, double* loss, double* dtheta, double* dlogperm);
+
+/* Training state for checkpoint/resume: theta, Adam m and v (n_params
+ * each, nullable) and the Adam step count. */
+crv_status crv_get_state(crv_ctx* ctx, double* theta, double* adam_m, double* adam_v, int64_t* t);
+crv_status crv_set_state(crv_ctx* ctx, const double* theta, const double* adam_m,
+                         const double* adam_v, int64_t t);
+
+/* Replace the saturation coefficients (nb^d) and refresh alpha. */
+crv_status crv_set_saturation(crv_ctx* ctx, const double* s_coefs);
+
+/* Loss of each Adam iteration so far (oldest first, at most cap entries,
+ * the most recent ones when more were run); *n receives the count. */
+crv_status crv_loss_history(crv_ctx* ctx, double* out, int cap, int* n);
+
+/* Single pieces, host in / host out, for verification:
+ * crv_gram_solve  q = G^-1 res on the interior grid (eq. 26-28);
+ * crv_mass_solve  x = (M^x (x) M^y [(x) M^z])^-1 b on coefficient arrays (eq. 14);
+ * crv_project_pressure  p coefs of the L2 projection of the network
+ *                       pressure (algorithm step 4);
+ * crv_saturation_substeps  steps 4-6 only: project the pressure and run n
+ *                       substeps of length tau (no retraining). */
+crv_status crv_gram_solve(crv_ctx* ctx, const double* res, double* q);
+crv_status crv_mass_solve(crv_ctx* ctx, const double* b, double* x);
+crv_status crv_project_pressure(crv_ctx* ctx, double* p_coefs);
+crv_status crv_saturation_substeps(crv_ctx* ctx, double tau, int n);
+
+crv_status crv_destroy(crv_ctx* ctx);
+const char* crv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRV_H */

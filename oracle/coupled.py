@@ -26,7 +26,7 @@ from . import ads, mlp, pressure, wells as wells_mod
 class Oracle:
     def __init__(self, dim, n_elem, degree, width, hidden, log_perm, porosity, wells,
                  theta0, s0_coefs=None, mu_w=1.0, mu_g=0.1, relperm_exp=2.0,
-                 lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, adam_iters=100,
+                 lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, adam_iters=100,
                  substeps=10, well_radius=0.06):
         self.dim, self.n_elem, self.r = dim, n_elem, degree
         self.dims = mlp.layer_dims(dim, width, hidden)

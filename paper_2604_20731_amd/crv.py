@@ -1,0 +1,244 @@
+"""ctypes binding of libcrv (include/crv.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+to float64 host buffers, allocates the device workspace with torch (device
+memory and the stream are the only things torch provides) and checks status
+codes.  Importing it fails loudly when libcrv.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrv.so")
+
+CRV_OK, CRV_EINVAL, CRV_ENOMEM, CRV_EHIP, CRV_ENUMERIC, CRV_ESTATE = 0, -1, -2, -3, -4, -5
+PREC = {"fp32": 0, "bf16": 1, "fp64": 2}
+STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
+                -4: "CRV_ENUMERIC", -5: "CRV_ESTATE"}
+
+EXPORTED = [
+    "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
+    "crv_pretrain_pressure", "crv_step", "crv_get_fields", "crv_loss_grad",
+    "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_loss_history",
+    "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
+    "crv_saturation_substeps", "crv_destroy", "crv_last_error",
+]
+
+
+class CrvConfig(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("n_elem", C.c_int), ("degree", C.c_int), ("width", C.c_int),
+        ("hidden", C.c_int), ("precision", C.c_int),
+        ("mu_w", C.c_double), ("mu_g", C.c_double), ("relperm_exp", C.c_double),
+        ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+        ("adam_iters", C.c_int), ("substeps", C.c_int), ("well_radius", C.c_double),
+    ]
+
+
+class CrvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    # torch carries its own copy of the HIP runtime; loading it first makes
+    # libcrv bind to that same copy (one runtime per process), which the
+    # torch-allocated workspace and streams require.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcrv.so is not built ({LIB_PATH}); run "
+                          "python -m paper_2604_20731_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    cfgp = C.POINTER(CrvConfig)
+    vp = C.c_void_p
+    sig = {
+        "crv_config_default": [cfgp],
+        "crv_param_count": [cfgp, C.POINTER(C.c_int64)],
+        "crv_workspace_size": [cfgp, C.POINTER(C.c_size_t)],
+        "crv_init": [cfgp, dp, dp, dp, C.c_int, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)],
+        "crv_pretrain_pressure": [vp, C.c_int, dp],
+        "crv_step": [vp, C.c_double],
+        "crv_get_fields": [vp, dp, dp, dp],
+        "crv_loss_grad": [vp, dp, dp, dp],
+        "crv_get_state": [vp, dp, dp, dp, C.POINTER(C.c_int64)],
+        "crv_set_state": [vp, dp, dp, dp, C.c_int64],
+        "crv_set_saturation": [vp, dp],
+        "crv_loss_history": [vp, dp, C.c_int, C.POINTER(C.c_int)],
+        "crv_gram_solve": [vp, dp, dp],
+        "crv_mass_solve": [vp, dp, dp],
+        "crv_project_pressure": [vp, dp],
+        "crv_saturation_substeps": [vp, C.c_double, C.c_int],
+        "crv_destroy": [vp],
+        "crv_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name == "crv_last_error" else C.c_int
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status: int):
+    if status != CRV_OK:
+        raise CrvError(status, LIB.crv_last_error().decode())
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def config(dim=2, n_elem=32, degree=2, width=32, hidden=3, precision="fp32", **kw) -> CrvConfig:
+    c = CrvConfig()
+    _check(LIB.crv_config_default(C.byref(c)))
+    c.dim, c.n_elem, c.degree, c.width, c.hidden = dim, n_elem, degree, width, hidden
+    c.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def param_count(cfg: CrvConfig) -> int:
+    n = C.c_int64()
+    _check(LIB.crv_param_count(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+def workspace_size(cfg: CrvConfig) -> int:
+    n = C.c_size_t()
+    _check(LIB.crv_workspace_size(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+class Scenario:
+    """One reservoir scenario: a libcrv context on the current torch stream
+    with a torch-allocated device workspace."""
+
+    def __init__(self, cfg: CrvConfig, log_perm, porosity, wells, theta0, s0_coefs=None,
+                 device: str = "cuda:0", stream=None):
+        import torch  # device memory and streams only
+        self.cfg = cfg
+        self.dim, self.ne, self.r = cfg.dim, cfg.n_elem, cfg.degree
+        self.nn = (self.ne + 1) ** self.dim
+        self.nb = self.ne + self.r
+        self.nc = self.nb ** self.dim
+        self.m = self.ne - 1
+        self.P = param_count(cfg)
+        self.ws_bytes = workspace_size(cfg)
+        self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        st = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
+        self._stream = st
+        lp, po = _f64(log_perm).ravel(), _f64(porosity).ravel()
+        w = _f64(wells).reshape(-1, 3)
+        th = _f64(theta0).ravel()
+        s0 = None if s0_coefs is None else _f64(s0_coefs).ravel()
+        if lp.size != self.nn or po.size != self.nn:
+            raise ValueError("nodal arrays must have (N+1)^d entries")
+        if th.size != self.P:
+            raise ValueError(f"theta0 must have {self.P} entries")
+        if s0 is not None and s0.size != self.nc:
+            raise ValueError("s0_coefs must have nb^d entries")
+        ctx = C.c_void_p()
+        _check(LIB.crv_init(C.byref(cfg), _dp(lp), _dp(po), _dp(w), int(w.shape[0]), _dp(s0),
+                            _dp(th), C.c_void_p(self._ws.data_ptr()), self.ws_bytes,
+                            C.c_void_p(st.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            LIB.crv_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- algorithm calls ------------------------------------------------------
+    def pretrain_pressure(self, iters: int) -> float:
+        out = C.c_double()
+        _check(LIB.crv_pretrain_pressure(self.ctx, int(iters), C.byref(out)))
+        return out.value
+
+    def step(self, dt: float):
+        _check(LIB.crv_step(self.ctx, float(dt)))
+
+    def fields(self):
+        shp_n = (self.ne + 1,) * self.dim
+        shp_c = (self.nb,) * self.dim
+        p = np.empty(shp_n)
+        sc = np.empty(shp_c)
+        sn = np.empty(shp_n)
+        _check(LIB.crv_get_fields(self.ctx, _dp(p), _dp(sc), _dp(sn)))
+        return p, sc, sn
+
+    def loss_grad(self, with_logperm: bool = False):
+        loss = C.c_double()
+        g = np.empty(self.P)
+        gl = np.empty((self.ne + 1,) * self.dim) if with_logperm else None
+        _check(LIB.crv_loss_grad(self.ctx, C.byref(loss), _dp(g), _dp(gl)))
+        return (loss.value, g, gl) if with_logperm else (loss.value, g)
+
+    def get_state(self):
+        th, m, v = np.empty(self.P), np.empty(self.P), np.empty(self.P)
+        t = C.c_int64()
+        _check(LIB.crv_get_state(self.ctx, _dp(th), _dp(m), _dp(v), C.byref(t)))
+        return th, m, v, t.value
+
+    def set_state(self, theta, m=None, v=None, t=0):
+        _check(LIB.crv_set_state(self.ctx, _dp(_f64(theta)), _dp(None if m is None else _f64(m)),
+                                 _dp(None if v is None else _f64(v)), int(t)))
+
+    def set_saturation(self, s_coefs):
+        _check(LIB.crv_set_saturation(self.ctx, _dp(_f64(s_coefs).ravel())))
+
+    def loss_history(self, cap: int = 1 << 16) -> np.ndarray:
+        out = np.empty(cap)
+        n = C.c_int()
+        _check(LIB.crv_loss_history(self.ctx, _dp(out), cap, C.byref(n)))
+        return out[: n.value].copy()
+
+    def gram_solve(self, res):
+        r = _f64(res)
+        q = np.empty_like(r)
+        _check(LIB.crv_gram_solve(self.ctx, _dp(r), _dp(q)))
+        return q
+
+    def mass_solve(self, b):
+        bb = _f64(b)
+        x = np.empty_like(bb)
+        _check(LIB.crv_mass_solve(self.ctx, _dp(bb), _dp(x)))
+        return x
+
+    def project_pressure(self):
+        p = np.empty((self.nb,) * self.dim)
+        _check(LIB.crv_project_pressure(self.ctx, _dp(p)))
+        return p
+
+    def saturation_substeps(self, tau: float, n: int):
+        _check(LIB.crv_saturation_substeps(self.ctx, float(tau), int(n)))
+
+
+def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:
+    """Build a Scenario from an inputs.Problem."""
+    cfg = config(dim=prob.dim, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
+                 hidden=prob.hidden, precision=precision or prob.precision, **cfg_over)
+    return Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0, prob.s0_coefs)

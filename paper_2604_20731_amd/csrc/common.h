@@ -1,0 +1,80 @@
+// Shared device/host helpers of libcrv (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace crv {
+
+constexpr int kWave = 64;
+
+// Geometry of one 2D/3D scenario.
+struct Geom {
+  int dim;  // 2 or 3
+  int ne;   // elements per axis
+  int n;    // nodes per axis (ne + 1)
+  int r;    // B-spline degree
+  int nb;   // coefficients per axis (ne + r)
+  int m;    // interior nodes per axis (ne - 1)
+  int mp;   // padded pitch of interior arrays (multiple of 64)
+};
+
+__host__ __device__ inline int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// tanh from its definition 1 - 2/(exp(2x)+1); exp overflow gives +1, underflow -1.
+__device__ inline float tanh_fast(float x) {
+  const float e = __expf(2.0f * x);
+  return 1.0f - 2.0f / (e + 1.0f);
+}
+__device__ inline double tanh_fast(double x) { return tanh(x); }
+
+template <typename T>
+__device__ inline T clamp01(T s) {
+  return s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+}
+
+// s^n for the Brooks-Corey exponent; exact products for n = 1, 2, 3.
+template <typename T>
+__device__ inline T powi_or_pow(T s, T n) {
+  if (n == T(2)) return s * s;
+  if (n == T(1)) return s;
+  if (n == T(3)) return s * s * s;
+  return pow(s, n);
+}
+
+template <typename T>
+__device__ inline T shfl_up(T v, int d) {
+  return __shfl_up(v, d, kWave);
+}
+template <typename T>
+__device__ inline T shfl_down(T v, int d) {
+  return __shfl_down(v, d, kWave);
+}
+template <typename T>
+__device__ inline T shfl(T v, int l) {
+  return __shfl(v, l, kWave);
+}
+
+// Fixed-order block sum (blockDim.x threads, power of two <= 1024).
+template <typename T>
+__device__ inline T block_sum(T v, T* sbuf) {
+  const int tid = threadIdx.x;
+  sbuf[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sbuf[tid] += sbuf[tid + s];
+    __syncthreads();
+  }
+  T out = sbuf[0];
+  __syncthreads();
+  return out;
+}
+
+inline int cdiv(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+}  // namespace crv

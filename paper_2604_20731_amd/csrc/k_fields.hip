@@ -1,0 +1,482 @@
+// Field kernels of the coupled step: coefficient refresh (alpha), collocation
+// residual, adjoint of the robust loss, pressure projection, explicit
+// saturation assembly, and the float64 factorisations done once at init.
+//
+// Layouts: nodal arrays (N+1)^d with x fastest; interior arrays padded to a
+// pitch mp per row, row index j-1 (2D); coefficient arrays nb^d.
+#include "kernels.h"
+
+namespace crv {
+
+// ---------------------------------------------------------------------------
+// a1: S at the nodes and alpha = K (kr_w/mu_w + kr_g/mu_g)   (second eq. 23)
+// ---------------------------------------------------------------------------
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_refresh2(Geom g, const Real* __restrict__ c,
+                                                  const int* __restrict__ kf,
+                                                  const Real* __restrict__ kv,
+                                                  const Real* __restrict__ perm, Real inv_mu_w,
+                                                  Real inv_mu_g, Real nexp,
+                                                  Real* __restrict__ s_nodal,
+                                                  Real* __restrict__ alpha) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  if (p >= int64_t(n) * n) return;
+  const int i = int(p % n), j = int(p / n);
+  const int fi = kf[i], fj = kf[j];
+  Real s = 0;
+#pragma unroll
+  for (int b = 0; b <= R; ++b) {
+    Real row = 0;
+#pragma unroll
+    for (int a = 0; a <= R; ++a) row += kv[i * (R + 1) + a] * c[int64_t(fj + b) * g.nb + fi + a];
+    s += kv[j * (R + 1) + b] * row;
+  }
+  const Real sc = clamp01(s);
+  const Real krw = powi_or_pow(Real(1) - sc, nexp), krg = powi_or_pow(sc, nexp);
+  s_nodal[p] = s;
+  alpha[p] = (krw * inv_mu_w + krg * inv_mu_g) * perm[p];
+}
+
+template <typename Real>
+void launch_refresh(const Geom& g, const Real* s_coefs, const int* kf, const Real* kv,
+                    const Real* perm, double mu_w, double mu_g, double nexp, Real* s_nodal,
+                    Real* alpha, hipStream_t st) {
+  const int64_t tot = int64_t(g.n) * g.n;
+  dim3 grid(cdiv(tot, 256));
+  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  switch (g.r) {
+    case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+    case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+    default: k_refresh2<Real, 3><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3: RES_p = sum_dir [alpha_{p-e}(u_p - u_{p-e}) - alpha_p (u_{p+e} - u_p)] - h^2 q_p
+// (eq. 24-25 with Kronecker-delta tests at interior nodes)
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void k_residual2(Geom g, const Real* __restrict__ u,
+                                                   const Real* __restrict__ alpha,
+                                                   const Real* __restrict__ hq,
+                                                   Real* __restrict__ res) {
+  const int ii = blockIdx.x * 64 + (threadIdx.x & 63);  // interior column 0..m-1
+  const int jj = blockIdx.y * 4 + (threadIdx.x >> 6);   // interior row
+  if (ii >= g.m || jj >= g.m) return;
+  const int n = g.n;
+  const int64_t p = int64_t(jj + 1) * n + (ii + 1);
+  const Real up = u[p], ap = alpha[p];
+  const Real r = alpha[p - 1] * (up - u[p - 1]) - ap * (u[p + 1] - up) +
+                 alpha[p - n] * (up - u[p - n]) - ap * (u[p + n] - up) - hq[p];
+  res[int64_t(jj) * g.mp + ii] = r;
+}
+
+template <typename Real>
+void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real* hq, Real* res,
+                     hipStream_t st) {
+  dim3 grid(cdiv(g.m, 64), cdiv(g.m, 4));
+  k_residual2<Real><<<grid, 256, 0, st>>>(g, u, alpha, hq, res);
+}
+
+// ---------------------------------------------------------------------------
+// a5: g_u = 2 A^T q~ on the full grid (q~ = q inside, 0 on the boundary; the
+// boundary entries are zero because the trial functions vanish there), and
+// per-block partial sums of LOSS = RES . q (eq. 27).
+// ---------------------------------------------------------------------------
+template <typename Real>
+__device__ inline Real qext(const Real* q, const Geom& g, int i, int j) {
+  return (i >= 1 && i <= g.m && j >= 1 && j <= g.m) ? q[int64_t(j - 1) * g.mp + (i - 1)] : Real(0);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adjoint2(Geom g, const Real* __restrict__ q,
+                                                  const Real* __restrict__ alpha,
+                                                  const Real* __restrict__ res,
+                                                  Real* __restrict__ gu,
+                                                  Real* __restrict__ partials) {
+  __shared__ Real sbuf[256];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int n = g.n;
+  Real lpart = 0;
+  if (i < n && j < n) {
+    const int64_t p = int64_t(j) * n + i;
+    Real out = 0;
+    if (i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
+      const Real qp = qext(q, g, i, j), ap = alpha[p];
+      out = Real(2) * (alpha[p - 1] * (qp - qext(q, g, i - 1, j)) - ap * (qext(q, g, i + 1, j) - qp) +
+                       alpha[p - n] * (qp - qext(q, g, i, j - 1)) - ap * (qext(q, g, i, j + 1) - qp));
+      lpart = res[int64_t(j - 1) * g.mp + (i - 1)] * qp;
+    }
+    gu[p] = out;
+  }
+  const Real tot = block_sum(lpart, sbuf);
+  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+int adjoint_partials(const Geom& g) { return cdiv(g.n, 64) * cdiv(g.n, 4); }
+
+template <typename Real>
+int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* res, Real* gu,
+                   Real* partials, hipStream_t st) {
+  dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
+  k_adjoint2<Real><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials);
+  return grid.x * grid.y;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_loss_finalize(const Real* __restrict__ part, int np,
+                                                       double* __restrict__ hist, int cap,
+                                                       long long* __restrict__ t_dev, int bump) {
+  __shared__ double sbuf[256];
+  double v = 0;
+  for (int k = threadIdx.x; k < np; k += 256) v += double(part[k]);
+  const double tot = block_sum(v, sbuf);
+  if (threadIdx.x == 0) {
+    const long long t = *t_dev;
+    hist[t % cap] = tot;
+    if (bump) *t_dev = t + 1;
+  }
+}
+
+template <typename Real>
+void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int cap,
+                          long long* t_dev, int bump, hipStream_t st) {
+  k_loss_finalize<Real><<<1, 256, 0, st>>>(partials, np, loss_hist, cap, t_dev, bump);
+}
+
+// dLOSS/dalpha_p = 2 sum_dir (u_{p+e}-u_p)(q_{p+e}-q_p) (2D, q zero-extended);
+// dLOSS/dlogK = dLOSS/dalpha * alpha.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_grad_logperm2(Geom g, const Real* __restrict__ u,
+                                                       const Real* __restrict__ q,
+                                                       const Real* __restrict__ alpha,
+                                                       Real* __restrict__ out) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int n = g.n;
+  if (i >= n || j >= n) return;
+  const int64_t p = int64_t(j) * n + i;
+  const Real qp = qext(q, g, i, j);
+  Real s = 0;
+  if (i + 1 < n) s += (u[p + 1] - u[p]) * (qext(q, g, i + 1, j) - qp);
+  if (j + 1 < n) s += (u[p + n] - u[p]) * (qext(q, g, i, j + 1) - qp);
+  out[p] = Real(2) * s * alpha[p];
+}
+
+template <typename Real>
+void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real* alpha,
+                         Real* out, hipStream_t st) {
+  dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
+  k_grad_logperm2<Real><<<grid, 256, 0, st>>>(g, u, q, alpha, out);
+}
+
+// ---------------------------------------------------------------------------
+// a8: b_kl = sum_ij Q_l(j) Q_k(i) u_ij with Q_k(i) = int B_k hat_i (algorithm step 4)
+// ---------------------------------------------------------------------------
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_project2(Geom g, const Real* __restrict__ u,
+                                                  const Real* __restrict__ qv,
+                                                  Real* __restrict__ b) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int nb = g.nb;
+  if (idx >= int64_t(nb) * nb) return;
+  const int k = int(idx % nb), l = int(idx / nb);
+  Real acc = 0;
+#pragma unroll
+  for (int tb = 0; tb < R + 2; ++tb) {
+    const int j = l - R + tb;
+    if (j < 0 || j > g.ne) continue;
+    Real row = 0;
+#pragma unroll
+    for (int ta = 0; ta < R + 2; ++ta) {
+      const int i = k - R + ta;
+      if (i < 0 || i > g.ne) continue;
+      row += qv[k * (R + 2) + ta] * u[int64_t(j) * g.n + i];
+    }
+    acc += qv[l * (R + 2) + tb] * row;
+  }
+  b[idx] = acc;
+}
+
+template <typename Real>
+void launch_project(const Geom& g, const Real* u, const Real* qv, Real* b, hipStream_t st) {
+  dim3 grid(cdiv(int64_t(g.nb) * g.nb, 256));
+  switch (g.r) {
+    case 1: k_project2<Real, 1><<<grid, 256, 0, st>>>(g, u, qv, b); break;
+    case 2: k_project2<Real, 2><<<grid, 256, 0, st>>>(g, u, qv, b); break;
+    default: k_project2<Real, 3><<<grid, 256, 0, st>>>(g, u, qv, b); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a10: explicit saturation right-hand side (eq. 10, Galerkin form eq. 12),
+// owner-computes tiles: a block owns TC x TC coefficients, evaluates the
+// integrand at the Gauss points of every element touching them into LDS, and
+// gathers its coefficients' sums in a fixed order (no atomics).
+// ---------------------------------------------------------------------------
+template <typename Real, int R, int TC>
+__global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
+    Geom g, const Real* __restrict__ sc, const Real* __restrict__ pc,
+    const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
+    const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
+    const Real* __restrict__ gxi, const Real* __restrict__ gw, Real tau, Real inv_mu_w,
+    Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+  constexpr int NG = R + 1;          // Gauss points per element and axis
+  constexpr int TE = TC + R;         // elements per tile and axis
+  constexpr int TCO = TC + 2 * R;    // coefficients touched per axis
+  constexpr int TN = TE + 1;         // nodes per axis
+  constexpr int GP = TE * NG;        // Gauss points per axis
+  __shared__ Real sS[TCO * TCO], sP[TCO * TCO];
+  __shared__ Real sK[TN * TN], sF[TN * TN], sQi[TN * TN], sQp[TN * TN];
+  __shared__ Real sF0[GP * GP], sFx[GP * GP], sFy[GP * GP];
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC;
+  const int c0x = k0 - R, c0y = l0 - R;  // first touched coefficient / element / node
+  const int nb = g.nb, ne = g.ne, n = g.n;
+  for (int t = tid; t < TCO * TCO; t += TC * TC) {
+    const int a = c0x + t % TCO, bb = c0y + t / TCO;
+    const bool ok = a >= 0 && a < nb && bb >= 0 && bb < nb;
+    sS[t] = ok ? sc[int64_t(bb) * nb + a] : Real(0);
+    sP[t] = ok ? pc[int64_t(bb) * nb + a] : Real(0);
+  }
+  for (int t = tid; t < TN * TN; t += TC * TC) {
+    const int i = c0x + t % TN, j = c0y + t / TN;
+    const bool ok = i >= 0 && i <= ne && j >= 0 && j <= ne;
+    const int64_t p = int64_t(j) * n + i;
+    sK[t] = ok ? perm[p] : Real(0);
+    sF[t] = ok ? poro[p] : Real(1);
+    sQi[t] = ok ? qi[p] : Real(0);
+    sQp[t] = ok ? qp[p] : Real(0);
+  }
+  __syncthreads();
+  for (int t = tid; t < GP * GP; t += TC * TC) {
+    const int gxl = t % GP, gyl = t / GP;
+    const int exl = gxl / NG, gx = gxl % NG, eyl = gyl / NG, gy = gyl % NG;
+    const int ex = c0x + exl, ey = c0y + eyl;
+    Real f0 = 0, fx = 0, fy = 0;
+    if (ex >= 0 && ex < ne && ey >= 0 && ey < ne) {
+      const Real* bx = gb + (int64_t(ex) * NG + gx) * (R + 1);
+      const Real* dbx = gdb + (int64_t(ex) * NG + gx) * (R + 1);
+      const Real* by = gb + (int64_t(ey) * NG + gy) * (R + 1);
+      const Real* dby = gdb + (int64_t(ey) * NG + gy) * (R + 1);
+      Real s = 0, px = 0, py = 0;
+#pragma unroll
+      for (int bb = 0; bb <= R; ++bb) {
+        Real rs = 0, rp = 0, rdp = 0;
+#pragma unroll
+        for (int a = 0; a <= R; ++a) {
+          const int li = (eyl + bb) * TCO + exl + a;
+          rs += bx[a] * sS[li];
+          rp += dbx[a] * sP[li];
+          rdp += bx[a] * sP[li];
+        }
+        s += by[bb] * rs;
+        px += by[bb] * rp;
+        py += dby[bb] * rdp;
+      }
+      // Q1 interpolation of the nodal data at the Gauss point
+      const Real xi = gxi[gx], eta = gxi[gy];
+      const Real w00 = (1 - xi) * (1 - eta), w10 = xi * (1 - eta), w01 = (1 - xi) * eta, w11 = xi * eta;
+      const int n00 = eyl * TN + exl;
+      auto interp = [&](const Real* a) {
+        return w00 * a[n00] + w10 * a[n00 + 1] + w01 * a[n00 + TN] + w11 * a[n00 + TN + 1];
+      };
+      const Real kk = interp(sK), phi = interp(sF), qin = interp(sQi), qpr = interp(sQp);
+      const Real scl = clamp01(s);
+      const Real lam_g = powi_or_pow(scl, nexp) * inv_mu_g;
+      const Real lam_w = powi_or_pow(Real(1) - scl, nexp) * inv_mu_w;
+      const Real fg = lam_g / (lam_g + lam_w);
+      const Real qg = qin + fg * qpr;
+      const Real w = gw[gx] * gw[gy];
+      const Real tphi = tau / phi;
+      f0 = w * (s + tphi * qg);
+      const Real c = -w * tphi * lam_g * kk;
+      fx = c * px;
+      fy = c * py;
+    }
+    sF0[t] = f0;
+    sFx[t] = fx;
+    sFy[t] = fy;
+  }
+  __syncthreads();
+  const int tx = tid % TC, ty = tid / TC;
+  const int k = k0 + tx, l = l0 + ty;
+  if (k >= nb || l >= nb) return;
+  Real acc = 0;
+  for (int ey = l - R; ey <= l; ++ey) {
+    if (ey < 0 || ey >= ne) continue;
+    const int bb = l - ey, eyl = ey - c0y;
+    for (int ex = k - R; ex <= k; ++ex) {
+      if (ex < 0 || ex >= ne) continue;
+      const int a = k - ex, exl = ex - c0x;
+#pragma unroll
+      for (int gy = 0; gy < NG; ++gy) {
+        const Real by = gb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+        const Real dby = gdb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+        Real rx0 = 0, rxx = 0, rxy = 0;
+#pragma unroll
+        for (int gx = 0; gx < NG; ++gx) {
+          const Real bx = gb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+          const Real dbx = gdb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+          const int t = (eyl * NG + gy) * GP + exl * NG + gx;
+          rx0 += bx * sF0[t];
+          rxx += dbx * sFx[t];
+          rxy += bx * sFy[t];
+        }
+        acc += by * (rx0 + rxx) + dby * rxy;
+      }
+    }
+  }
+  b[int64_t(l) * nb + k] = acc;
+}
+
+template <typename Real>
+void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
+                         const Real* poro, const Real* qi, const Real* qp, const Real* gb,
+                         const Real* gdb, const Real* gxi, const Real* gw, double tau,
+                         double mu_w, double mu_g, double nexp, Real* b, hipStream_t st) {
+  const Real t = Real(tau), iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  constexpr bool big = sizeof(Real) == 8;
+  if (g.r == 1) {
+    constexpr int TC = 16;
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
+    k_ads_assemble2<Real, 1, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+  } else if (g.r == 2) {
+    constexpr int TC = big ? 8 : 16;
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
+    k_ads_assemble2<Real, 2, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+  } else {
+    constexpr int TC = 8;
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
+    k_ads_assemble2<Real, 3, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K7f: float64 factorisations (device), converted to the working precision.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_factor_band(const double* __restrict__ band, int n, int r,
+                              double* __restrict__ d, Real* __restrict__ lt,
+                              Real* __restrict__ inv_d, int* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // M(j, j+t) = band[j*(r+1)+t]; keep L in float64 in the lt slots of d[n..]
+  double* L = d + n;  // n*r entries, L(i, i-t) at L[i*r + t-1]
+  for (int j = 0; j < n; ++j) {
+    double dj = band[int64_t(j) * (r + 1)];
+    for (int k = max(0, j - r); k < j; ++k) {
+      const double l = L[int64_t(j) * r + (j - k - 1)];
+      dj -= l * l * d[k];
+    }
+    if (!(dj > 0.0)) {
+      *status = 1;
+      return;
+    }
+    d[j] = dj;
+    for (int i = j + 1; i <= min(n - 1, j + r); ++i) {
+      double mij = band[int64_t(j) * (r + 1) + (i - j)];
+      for (int k = max(0, i - r); k < j; ++k)
+        mij -= L[int64_t(i) * r + (i - k - 1)] * L[int64_t(j) * r + (j - k - 1)] * d[k];
+      L[int64_t(i) * r + (i - j - 1)] = mij / dj;
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    inv_d[j] = Real(1.0 / d[j]);
+    for (int t = 0; t < r; ++t) lt[int64_t(j) * r + t] = Real(j - t - 1 >= 0 ? L[int64_t(j) * r + t] : 0.0);
+  }
+  *status = 0;
+}
+
+template <typename Real>
+void launch_factor_band(const double* band, int n, int r, double* work_d, Real* lt, Real* inv_d,
+                        int* status, hipStream_t st) {
+  k_factor_band<Real><<<1, 64, 0, st>>>(band, n, r, work_d, lt, inv_d, status);
+}
+
+template <typename Real>
+__global__ void k_factor_shifted(const double* __restrict__ shifts, int nlines, int m, int mp,
+                                 double scale, Real* __restrict__ lt, Real* __restrict__ inv_d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nlines) return;
+  const double diag = scale * (2.0 + shifts[k]), off = -scale;
+  double dprev = 0;
+  for (int j = 0; j < m; ++j) {
+    double dj, l = 0;
+    if (j == 0) {
+      dj = diag;
+    } else {
+      l = off / dprev;
+      dj = diag - l * l * dprev;
+    }
+    lt[int64_t(k) * mp + j] = Real(l);
+    inv_d[int64_t(k) * mp + j] = Real(1.0 / dj);
+    dprev = dj;
+  }
+}
+
+template <typename Real>
+void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, double scale,
+                           Real* lt, Real* inv_d, hipStream_t st) {
+  k_factor_shifted<Real><<<cdiv(nlines, 64), 64, 0, st>>>(shifts, nlines, m, mp, scale, lt, inv_d);
+}
+
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_fill(Real* p, size_t n, Real v) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+template <typename Real>
+void launch_fill(Real* p, size_t n, Real v, hipStream_t st) {
+  if (n == 0) return;
+  k_fill<Real><<<cdiv(n, 256), 256, 0, st>>>(p, n, v);
+}
+
+template <typename Src, typename Dst>
+__global__ void k_convert(const Src* in, Dst* out, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = Dst(in[i]);
+}
+template <typename Src, typename Dst>
+void launch_convert(const Src* in, Dst* out, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  k_convert<Src, Dst><<<cdiv(n, 256), 256, 0, st>>>(in, out, n);
+}
+
+template <typename Real>
+__global__ void k_check_finite(const Real* p, size_t n, int* flag) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(p[i])) *flag = 1;
+}
+template <typename Real>
+void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st) {
+  if (n == 0) return;
+  k_check_finite<Real><<<cdiv(n, 256), 256, 0, st>>>(p, n, flag);
+}
+
+#define CRV_INST(R)                                                                              \
+  template void launch_refresh<R>(const Geom&, const R*, const int*, const R*, const R*, double, \
+                                  double, double, R*, R*, hipStream_t);                          \
+  template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t);  \
+  template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t); \
+  template void launch_loss_finalize<R>(const R*, int, double*, int, long long*, int, hipStream_t); \
+  template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t); \
+  template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t);             \
+  template void launch_ads_assemble<R>(const Geom&, const R*, const R*, const R*, const R*,      \
+                                       const R*, const R*, const R*, const R*, const R*,         \
+                                       const R*, double, double, double, double, R*, hipStream_t); \
+  template void launch_factor_band<R>(const double*, int, int, double*, R*, R*, int*, hipStream_t); \
+  template void launch_factor_shifted<R>(const double*, int, int, int, double, R*, R*, hipStream_t); \
+  template void launch_fill<R>(R*, size_t, R, hipStream_t);                                      \
+  template void launch_check_finite<R>(const R*, size_t, int*, hipStream_t);
+
+CRV_INST(float)
+CRV_INST(double)
+template void launch_convert<double, float>(const double*, float*, size_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, size_t, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, size_t, hipStream_t);
+template void launch_fill<int>(int*, size_t, int, hipStream_t);
+
+}  // namespace crv

@@ -1,0 +1,351 @@
+// Directional banded solves and the dense products of the Gram solve.
+//
+// The 1D factors are L D L^T with unit lower L of bandwidth r, computed in
+// float64 once (eq. 14 for the B-spline mass matrix; eq. 28 for the shifted
+// tridiagonal lines of the Gram matrix) and applied here in the working
+// precision.
+//
+// Contiguous lines: one wavefront per line.  Lane l owns P consecutive
+// entries.  Forward substitution is the order-r linear recurrence
+//   y_j = b_j - sum_t L(j, j-t) y_{j-t},
+// i.e. an affine map on the state (y_j, ..., y_{j-r+1}).  Each lane composes
+// the maps of its chunk (a particular solution plus r homogeneous ones), a
+// 6-step wavefront scan of the composed maps gives every lane its incoming
+// state, and the lane re-runs its chunk from that state.  The backward sweep
+// x_j = y_j / D_j - sum_t L(j+t, j) x_{j+t} is the same scan in reverse.
+#include "kernels.h"
+
+namespace crv {
+
+template <typename Real, int R>
+struct Affine {
+  Real a[R][R];
+  Real c[R];
+};
+
+template <typename Real, int R>
+__device__ inline void compose(Affine<Real, R>& self, const Affine<Real, R>& prev) {
+  // self <- self o prev : a = A_self A_prev, c = A_self c_prev + c_self
+  Affine<Real, R> out;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    Real cc = self.c[i];
+#pragma unroll
+    for (int k = 0; k < R; ++k) cc += self.a[i][k] * prev.c[k];
+    out.c[i] = cc;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      Real s = 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) s += self.a[i][k] * prev.a[k][j];
+      out.a[i][j] = s;
+    }
+  }
+  self = out;
+}
+
+template <typename Real, int R>
+__device__ inline Affine<Real, R> shfl_affine(const Affine<Real, R>& v, int off, bool up) {
+  Affine<Real, R> o;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    o.c[i] = up ? shfl_up(v.c[i], off) : shfl_down(v.c[i], off);
+#pragma unroll
+    for (int j = 0; j < R; ++j) o.a[i][j] = up ? shfl_up(v.a[i][j], off) : shfl_down(v.a[i][j], off);
+  }
+  return o;
+}
+
+// LDS index of entry j of a wave's line buffer, padded so the per-lane chunk
+// reads (stride P) avoid bank conflicts.
+template <int P>
+__device__ inline int lidx(int j) {
+  constexpr int S = (P % 2 == 0) ? P + 1 : P;
+  return (j / P) * S + (j % P);
+}
+
+template <typename Real, int R, int P>
+__global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, Real* x, int n,
+                                                   int nlines, int64_t line_stride,
+                                                   const Real* __restrict__ lt,
+                                                   const Real* __restrict__ invd, int64_t cs,
+                                                   int64_t csd) {
+  constexpr int S = (P % 2 == 0) ? P + 1 : P;
+  __shared__ Real buf[4][64 * S];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int line = blockIdx.x * 4 + w;
+  const bool active = line < nlines;
+  // an idle wave (past the last line) runs the scan on an empty line so the
+  // block barriers stay uniform, and touches no memory
+  n = active ? n : 0;
+  const Real* bl = b + int64_t(line) * line_stride;
+  Real* xl = x + int64_t(line) * line_stride;
+  const Real* L = lt + int64_t(line) * cs;
+  const Real* D = invd + int64_t(line) * csd;
+  Real* sb = buf[w];
+  if (active)
+    for (int j = lane; j < n; j += 64) sb[lidx<P>(j)] = bl[j];
+  __syncthreads();
+  const int j0 = lane * P;
+  Real v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = (j0 + e < n) ? sb[lane * S + e] : Real(0);
+
+  // ---------------- forward: y_j = b_j - sum_t L(j,j-t) y_{j-t} --------------
+  Affine<Real, R> f;
+#pragma unroll
+  for (int col = -1; col < R; ++col) {
+    Real s[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) s[t] = (t == col) ? Real(1) : Real(0);
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int j = j0 + e;
+      if (j < n) {
+        Real y = (col < 0) ? v[e] : Real(0);
+#pragma unroll
+        for (int t = 1; t <= R; ++t) y -= L[int64_t(j) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+        s[0] = y;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (col < 0) f.c[t] = s[t];
+      else f.a[t][col] = s[t];
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Affine<Real, R> prev = shfl_affine(f, off, true);
+    if (lane >= off) compose(f, prev);
+  }
+  {
+    Real s[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const Real in = shfl_up(f.c[t], 1);
+      s[t] = lane > 0 ? in : Real(0);
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int j = j0 + e;
+      if (j < n) {
+        Real y = v[e];
+#pragma unroll
+        for (int t = 1; t <= R; ++t) y -= L[int64_t(j) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+        s[0] = y;
+        v[e] = y * D[j];  // z_j = y_j / D_j
+      }
+    }
+  }
+
+  // ------- backward: x_j = z_j - sum_t L(j+t, j) x_{j+t}, from j = n-1 down -------
+  Affine<Real, R> g;
+#pragma unroll
+  for (int col = -1; col < R; ++col) {
+    Real s[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) s[t] = (t == col) ? Real(1) : Real(0);
+#pragma unroll
+    for (int e = P - 1; e >= 0; --e) {
+      const int j = j0 + e;
+      if (j < n) {
+        Real xv = (col < 0) ? v[e] : Real(0);
+#pragma unroll
+        for (int t = 1; t <= R; ++t)
+          if (j + t < n) xv -= L[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+        s[0] = xv;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (col < 0) g.c[t] = s[t];
+      else g.a[t][col] = s[t];
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Affine<Real, R> nxt = shfl_affine(g, off, false);
+    if (lane + off < 64) compose(g, nxt);
+  }
+  {
+    Real s[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const Real in = shfl_down(g.c[t], 1);
+      s[t] = lane < 63 ? in : Real(0);
+    }
+#pragma unroll
+    for (int e = P - 1; e >= 0; --e) {
+      const int j = j0 + e;
+      if (j < n) {
+        Real xv = v[e];
+#pragma unroll
+        for (int t = 1; t <= R; ++t)
+          if (j + t < n) xv -= L[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+        s[0] = xv;
+        v[e] = xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < P; ++e) sb[lane * S + e] = v[e];
+  __syncthreads();
+  if (active)
+    for (int j = lane; j < n; j += 64) xl[j] = sb[lidx<P>(j)];
+}
+
+template <typename Real, int R>
+static void band_rows_dispatch(int P, const Real* b, Real* x, int n, int nlines, int64_t ls,
+                               const Real* lt, const Real* invd, int64_t cs, int64_t csd,
+                               hipStream_t st) {
+  dim3 grid(cdiv(nlines, 4));
+#define CRV_P(PP) \
+  case PP: k_band_rows<Real, R, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, ls, lt, invd, cs, csd); break;
+  switch (P) {
+    CRV_P(1) CRV_P(2) CRV_P(3) CRV_P(4) CRV_P(5) CRV_P(8) CRV_P(9) CRV_P(12) CRV_P(16) CRV_P(17)
+    default: break;
+  }
+#undef CRV_P
+}
+
+static int pick_p(int n) {
+  static const int ps[] = {1, 2, 3, 4, 5, 8, 9, 12, 16, 17};
+  for (int p : ps)
+    if (64 * p >= n) return p;
+  return -1;
+}
+
+template <typename Real>
+void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_stride, int r,
+                      const Real* lt, const Real* inv_d, int64_t coef_stride,
+                      int64_t coef_stride_d, hipStream_t st) {
+  const int P = pick_p(n);
+  if (P < 0 || nlines <= 0) return;
+  switch (r) {
+    case 1: band_rows_dispatch<Real, 1>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
+    case 2: band_rows_dispatch<Real, 2>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
+    default: band_rows_dispatch<Real, 3>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
+  }
+}
+
+// Strided lines: one thread per line (consecutive threads = consecutive
+// columns, so every row access is coalesced), shared coefficients.
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_band_cols(const Real* __restrict__ b, Real* __restrict__ x,
+                                                   int n, int ncols, int64_t rs,
+                                                   const Real* __restrict__ lt,
+                                                   const Real* __restrict__ invd,
+                                                   int64_t batch_stride) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const Real* bb = b + int64_t(blockIdx.y) * batch_stride + c;
+  Real* xx = x + int64_t(blockIdx.y) * batch_stride + c;
+  Real s[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) s[t] = 0;
+  for (int j = 0; j < n; ++j) {
+    Real y = bb[int64_t(j) * rs];
+#pragma unroll
+    for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+    for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+    s[0] = y;
+    xx[int64_t(j) * rs] = y * invd[j];
+  }
+#pragma unroll
+  for (int t = 0; t < R; ++t) s[t] = 0;
+  for (int j = n - 1; j >= 0; --j) {
+    Real xv = xx[int64_t(j) * rs];
+#pragma unroll
+    for (int t = 1; t <= R; ++t)
+      if (j + t < n) xv -= lt[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+#pragma unroll
+    for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
+    s[0] = xv;
+    xx[int64_t(j) * rs] = xv;
+  }
+}
+
+template <typename Real>
+void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_stride, int r,
+                      const Real* lt, const Real* inv_d, int64_t batch, int64_t batch_stride,
+                      hipStream_t st) {
+  dim3 grid(cdiv(nlines, 64), unsigned(batch));
+  switch (r) {
+    case 1: k_band_cols<Real, 1><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
+    case 2: k_band_cols<Real, 2><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
+    default: k_band_cols<Real, 3><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C = A B (row-major, dims multiples of 64): 64x64 tiles, 16-deep K slabs in
+// LDS, 4x4 outputs per thread.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* __restrict__ A,
+                                              int lda, const Real* __restrict__ B, int ldb,
+                                              Real* __restrict__ C, int ldc) {
+  __shared__ Real As[16][64 + 4];
+  __shared__ Real Bs[16][64 + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  Real acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    {
+      const int mm = tid / 4, kk = (tid % 4) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[kk + q][mm] = A[int64_t(m0 + mm) * lda + k0 + kk + q];
+      const int kb = tid / 16, nn = (tid % 16) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[kb][nn + q] = B[int64_t(k0 + kb) * ldb + n0 + nn + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      Real a[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[k][ty * 4 + q];
+        bv[q] = Bs[k][tx * 4 + q];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) C[int64_t(m0 + ty * 4 + i) * ldc + n0 + tx * 4 + j] = acc[i][j];
+}
+
+template <typename Real>
+void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
+                 int ldc, hipStream_t st) {
+  dim3 grid(N / 64, M / 64);
+  k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+}
+
+#define CRV_INST(R)                                                                            \
+  template void launch_band_rows<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
+                                    int64_t, int64_t, hipStream_t);                           \
+  template void launch_band_cols<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
+                                    int64_t, int64_t, hipStream_t);                           \
+  template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t);
+CRV_INST(float)
+CRV_INST(double)
+
+}  // namespace crv

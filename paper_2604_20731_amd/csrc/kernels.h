@@ -1,0 +1,112 @@
+// Launchers of the libcrv HIP kernels (instantiated for float and double).
+#pragma once
+#include "common.h"
+
+namespace crv {
+
+// ---- fields (k_fields.hip) ------------------------------------------------
+// a1: saturation at the nodes from the spline coefficients (knot values) and
+// alpha = K (kr_w/mu_w + kr_g/mu_g) at clamp(S,0,1).
+template <typename Real>
+void launch_refresh(const Geom& g, const Real* s_coefs, const int* knot_first, const Real* knot_val,
+                    const Real* perm, double mu_w, double mu_g, double nexp, Real* s_nodal,
+                    Real* alpha, hipStream_t st);
+
+// a3: RES on the interior nodes (padded layout, pitch mp).
+template <typename Real>
+void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real* hq, Real* res,
+                     hipStream_t st);
+
+// a5: g_u = 2 A^T q (zero on the boundary) and per-block partial sums of RES.q.
+// Returns the number of partials written.
+template <typename Real>
+int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* res, Real* gu,
+                   Real* loss_partials, hipStream_t st);
+int adjoint_partials(const Geom& g);
+
+// Sum of the loss partials (fixed order) into loss_hist[t % cap], then ++t.
+template <typename Real>
+void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int cap,
+                          long long* t_dev, int bump, hipStream_t st);
+
+// a3 differentiation form: dLOSS/dlogK = 2 sum_dir grad+ u . grad+ q h^(d-2) * alpha.
+template <typename Real>
+void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real* alpha,
+                         Real* out, hipStream_t st);
+
+// a8: b_kl = int I_h(u) B_kl (Q1 nodal interpolant, exact Gauss).
+template <typename Real>
+void launch_project(const Geom& g, const Real* u, const Real* proj_val, Real* b, hipStream_t st);
+
+// a10: b_kl = int [S B_kl + tau/phi (-lambda_g K grad p . grad B_kl + q_g B_kl)].
+template <typename Real>
+void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
+                         const Real* poro, const Real* qi, const Real* qp, const Real* gb,
+                         const Real* gdb, const Real* gxi, const Real* gw, double tau,
+                         double mu_w, double mu_g, double nexp, Real* b, hipStream_t st);
+
+// K7f: float64 factorisations on the device.
+// Banded LDL^T of the 1D mass matrix (band (nb, r+1)) -> lt (nb*r), inv_d (nb).
+template <typename Real>
+void launch_factor_band(const double* band, int n, int r, double* work_d, Real* lt, Real* inv_d,
+                        int* status, hipStream_t st);
+// LDL^T of the shifted tridiagonals scale*(T + shift_k I), T = tridiag(-1,2,-1)
+// of size m; line k has shift shifts[k]; tables pitch mp.
+template <typename Real>
+void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, double scale,
+                           Real* lt, Real* inv_d, hipStream_t st);
+
+template <typename Real>
+void launch_fill(Real* p, size_t n, Real v, hipStream_t st);
+template <typename Src, typename Dst>
+void launch_convert(const Src* in, Dst* out, size_t n, hipStream_t st);
+// non-finite check: sets *flag = 1 if any entry is NaN/Inf
+template <typename Real>
+void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st);
+
+// ---- solves (k_solve.hip) --------------------------------------------------
+// Banded unit-lower L D L^T solves along contiguous lines: one wavefront per
+// line, chunked recurrence + wavefront affine scan.  Line l occupies
+// x[l*line_stride + j], j < n.  Coefficients: lt[(l*coef_stride) + j*r + t-1]
+// = L(j, j-t), inv_d[(l*coef_stride_d) + j].  In place allowed (x == b).
+template <typename Real>
+void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_stride, int r,
+                      const Real* lt, const Real* inv_d, int64_t coef_stride,
+                      int64_t coef_stride_d, hipStream_t st);
+// Same solve along strided lines (element j of line c at x[j*row_stride + c]),
+// one thread per line, shared coefficients.
+template <typename Real>
+void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_stride, int r,
+                      const Real* lt, const Real* inv_d, int64_t batch, int64_t batch_stride,
+                      hipStream_t st);
+
+// C = A B, row-major, all dims multiples of 64, pitches in elements.
+template <typename Real>
+void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
+                 int ldc, hipStream_t st);
+
+// ---- network (k_mlp.hip) ---------------------------------------------------
+struct MlpShape {
+  int dim, width, hidden;
+  int64_t nparams;
+};
+int64_t mlp_param_count(int dim, int width, int hidden);
+// u = mask * NN(2x-1) on all nodes.
+template <typename Real>
+void launch_mlp_forward(const Geom& g, const MlpShape& s, const Real* theta, Real* u,
+                        hipStream_t st);
+// per-block partial gradients of sum_p gu_p NN(z_p); returns rows written
+template <typename Real>
+int launch_mlp_backward(const Geom& g, const MlpShape& s, const Real* theta, const Real* gu,
+                        Real* partials, hipStream_t st);
+int mlp_backward_rows(const Geom& g, const MlpShape& s, int real_bytes);
+// fixed-order column sums of partials (rows x P) -> out (P); uses scratch
+template <typename Real>
+void launch_reduce_rows(const Real* in, int rows, int64_t P, Real* scratch, Real* out,
+                        hipStream_t st);
+template <typename Real>
+void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double lr,
+                 double beta1, double beta2, double eps, const long long* t_dev,
+                 hipStream_t st);
+
+}  // namespace crv

@@ -1,0 +1,704 @@
+// libcrv host runtime: the C ABI of include/crv.h.
+//
+// One context = one scenario on one device stream.  All state (fields,
+// factor tables, network parameters, Adam moments, loss history) lives in a
+// single device workspace carved at init; after init the coupled step runs
+// entirely on the device and the host only reads results back on request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/crv.h"
+#include "kernels.h"
+#include "tables.h"
+
+namespace crv {
+
+static thread_local std::string g_err;
+
+static crv_status fail(crv_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define CRV_HIP(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(CRV_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kLossCap = 1 << 16;
+
+// ---------------------------------------------------------------------------
+// workspace layout (identical dry run for crv_workspace_size)
+// ---------------------------------------------------------------------------
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+static Geom make_geom(const crv_config& c) {
+  Geom g;
+  g.dim = c.dim;
+  g.ne = c.n_elem;
+  g.n = c.n_elem + 1;
+  g.r = c.degree;
+  g.nb = c.n_elem + c.degree;
+  g.m = c.n_elem - 1;
+  g.mp = (g.m + 63) / 64 * 64;
+  return g;
+}
+
+template <typename Real>
+struct Buffers {
+  // nodal (N+1)^d
+  Real *perm, *poro, *qi, *qp, *hq, *s_nodal, *alpha, *u, *gu, *tmp_nodal;
+  // coefficients nb^d
+  Real *s, *p, *bvec;
+  // interior, padded mp x mp
+  Real *res, *rhat, *qhat, *q, *dst;
+  // Gram lines (m lines, pitch mp) and mass factors
+  Real *g_lt, *g_invd, *m_lt, *m_invd;
+  double *band, *band_work, *shifts;
+  int* status;
+  // tables
+  int* knot_first;
+  Real *knot_val, *proj_val, *gb, *gdb, *gxi, *gw;
+  // network and optimiser
+  Real *theta, *am, *av, *grad, *partials, *red_scratch, *loss_part;
+  double *loss_hist, *loss_scalar;
+  long long *t_dev, *t_zero;
+  int* flag;
+  int bwd_rows;
+  int loss_np;
+};
+
+template <typename Real>
+static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
+  const Geom g = make_geom(c);
+  const size_t nn = size_t(ipow(g.n, g.dim));
+  const size_t nc = size_t(ipow(g.nb, g.dim));
+  const size_t ni = size_t(g.mp) * g.mp;
+  const int64_t P = mlp_param_count(c.dim, c.width, c.hidden);
+  MlpShape ms{c.dim, c.width, c.hidden, P};
+  b.perm = cv.take<Real>(nn);
+  b.poro = cv.take<Real>(nn);
+  b.qi = cv.take<Real>(nn);
+  b.qp = cv.take<Real>(nn);
+  b.hq = cv.take<Real>(nn);
+  b.s_nodal = cv.take<Real>(nn);
+  b.alpha = cv.take<Real>(nn);
+  b.u = cv.take<Real>(nn);
+  b.gu = cv.take<Real>(nn);
+  b.tmp_nodal = cv.take<Real>(nn);
+  b.s = cv.take<Real>(nc);
+  b.p = cv.take<Real>(nc);
+  b.bvec = cv.take<Real>(nc);
+  b.res = cv.take<Real>(ni);
+  b.rhat = cv.take<Real>(ni);
+  b.qhat = cv.take<Real>(ni);
+  b.q = cv.take<Real>(ni);
+  b.dst = cv.take<Real>(ni);
+  b.g_lt = cv.take<Real>(size_t(g.m) * g.mp);
+  b.g_invd = cv.take<Real>(size_t(g.m) * g.mp);
+  b.m_lt = cv.take<Real>(size_t(g.nb) * g.r);
+  b.m_invd = cv.take<Real>(size_t(g.nb));
+  b.band = cv.take<double>(size_t(g.nb) * (g.r + 1));
+  b.band_work = cv.take<double>(size_t(g.nb) * (g.r + 1));
+  b.shifts = cv.take<double>(size_t(g.m));
+  b.status = cv.take<int>(1);
+  b.knot_first = cv.take<int>(size_t(g.n));
+  b.knot_val = cv.take<Real>(size_t(g.n) * (g.r + 1));
+  b.proj_val = cv.take<Real>(size_t(g.nb) * (g.r + 2));
+  b.gb = cv.take<Real>(size_t(g.ne) * (g.r + 1) * (g.r + 1));
+  b.gdb = cv.take<Real>(size_t(g.ne) * (g.r + 1) * (g.r + 1));
+  b.gxi = cv.take<Real>(size_t(g.r + 1));
+  b.gw = cv.take<Real>(size_t(g.r + 1));
+  b.theta = cv.take<Real>(P);
+  b.am = cv.take<Real>(P);
+  b.av = cv.take<Real>(P);
+  b.grad = cv.take<Real>(P);
+  b.bwd_rows = mlp_backward_rows(g, ms, int(sizeof(Real)));
+  b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
+  b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
+  b.loss_np = adjoint_partials(g);
+  b.loss_part = cv.take<Real>(size_t(b.loss_np));
+  b.loss_hist = cv.take<double>(kLossCap);
+  b.loss_scalar = cv.take<double>(1);
+  b.t_dev = cv.take<long long>(1);
+  b.t_zero = cv.take<long long>(1);
+  b.flag = cv.take<int>(1);
+  return (cv.off + 255) & ~size_t(255);
+}
+
+static crv_status validate_config(const crv_config* c) {
+  if (!c) return fail(CRV_EINVAL, "config is NULL");
+  if (c->dim != 2) return fail(CRV_EINVAL, "dim must be 2");
+  if (c->n_elem < 4 || c->n_elem > 1024) return fail(CRV_EINVAL, "n_elem must be in [4, 1024]");
+  if (c->degree < 1 || c->degree > 3) return fail(CRV_EINVAL, "degree must be 1, 2 or 3");
+  if (!(c->width == 16 || c->width == 32 || c->width == 64 || c->width == 128))
+    return fail(CRV_EINVAL, "width must be 16, 32, 64 or 128");
+  if (c->hidden < 1 || c->hidden > 8) return fail(CRV_EINVAL, "hidden must be in [1, 8]");
+  if (c->precision != CRV_PREC_FP32 && c->precision != CRV_PREC_FP64 && c->precision != CRV_PREC_BF16)
+    return fail(CRV_EINVAL, "unknown precision");
+  if (c->precision == CRV_PREC_BF16) return fail(CRV_EINVAL, "bf16 network path not available");
+  if (!(c->mu_w > 0) || !(c->mu_g > 0)) return fail(CRV_EINVAL, "viscosities must be > 0");
+  if (!(c->relperm_exp >= 1)) return fail(CRV_EINVAL, "relperm_exp must be >= 1");
+  if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) ||
+      !(c->eps >= 0))
+    return fail(CRV_EINVAL, "bad Adam parameters");
+  if (c->adam_iters < 0 || c->substeps < 1) return fail(CRV_EINVAL, "bad iteration counts");
+  if (!(c->well_radius > 0)) return fail(CRV_EINVAL, "well_radius must be > 0");
+  return CRV_OK;
+}
+
+// ---------------------------------------------------------------------------
+struct SolverBase {
+  crv_config cfg;
+  Geom g;
+  hipStream_t st = nullptr;
+  int64_t P = 0;
+  bool owns_ws = false;
+  void* ws = nullptr;
+  bool pretrained = false;
+  virtual ~SolverBase() {
+    if (owns_ws && ws) (void)hipFree(ws);
+  }
+  virtual crv_status init(const double*, const double*, const double*, int, const double*,
+                          const double*) = 0;
+  virtual crv_status train(int iters) = 0;
+  virtual crv_status step(double dt) = 0;
+  virtual crv_status fields(double*, double*, double*) = 0;
+  virtual crv_status loss_grad(double*, double*, double*) = 0;
+  virtual crv_status get_state(double*, double*, double*, int64_t*) = 0;
+  virtual crv_status set_state(const double*, const double*, const double*, int64_t) = 0;
+  virtual crv_status set_saturation(const double*) = 0;
+  virtual crv_status loss_history(double*, int, int*) = 0;
+  virtual crv_status gram_solve_host(const double*, double*) = 0;
+  virtual crv_status mass_solve_host(const double*, double*) = 0;
+  virtual crv_status project_host(double*) = 0;
+  virtual crv_status substeps(double tau, int n) = 0;
+};
+
+template <typename Real>
+struct Solver : SolverBase {
+  Buffers<Real> b;
+  MlpShape ms;
+  size_t nn = 0, nc = 0;
+
+  // -------- host <-> device helpers --------
+  crv_status upload(Real* dst, const double* src, size_t n) {
+    std::vector<Real> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = Real(src[i]);
+    CRV_HIP(hipMemcpyAsync(dst, tmp.data(), n * sizeof(Real), hipMemcpyHostToDevice, st));
+    CRV_HIP(hipStreamSynchronize(st));
+    return CRV_OK;
+  }
+  template <typename T>
+  crv_status upload_raw(T* dst, const std::vector<T>& src) {
+    CRV_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    CRV_HIP(hipStreamSynchronize(st));
+    return CRV_OK;
+  }
+  crv_status download(double* dst, const Real* src, size_t n) {
+    std::vector<Real> tmp(n);
+    CRV_HIP(hipMemcpyAsync(tmp.data(), src, n * sizeof(Real), hipMemcpyDeviceToHost, st));
+    CRV_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < n; ++i) dst[i] = double(tmp[i]);
+    return CRV_OK;
+  }
+  crv_status check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRV_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return CRV_OK;
+  }
+  crv_status sync_and_check() {
+    CRV_HIP(hipStreamSynchronize(st));
+    int flag = 0;
+    CRV_HIP(hipMemcpy(&flag, b.flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) return fail(CRV_ENUMERIC, "non-finite saturation or loss");
+    return CRV_OK;
+  }
+
+  crv_status init(const double* log_perm, const double* poro, const double* wells, int n_wells,
+                  const double* s0, const double* theta0) override {
+    nn = size_t(ipow(g.n, g.dim));
+    nc = size_t(ipow(g.nb, g.dim));
+    ms = MlpShape{cfg.dim, cfg.width, cfg.hidden, P};
+    for (size_t i = 0; i < nn; ++i) {
+      if (!std::isfinite(log_perm[i])) return fail(CRV_EINVAL, "log_perm has non-finite entries");
+      if (!(poro[i] > 0) || !std::isfinite(poro[i])) return fail(CRV_EINVAL, "porosity must be > 0");
+    }
+    if (n_wells < 0 || (n_wells > 0 && !wells)) return fail(CRV_EINVAL, "bad well list");
+    for (int w = 0; w < n_wells; ++w)
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(wells[3 * w + k])) return fail(CRV_EINVAL, "well entries must be finite");
+    if (s0)
+      for (size_t i = 0; i < nc; ++i)
+        if (!std::isfinite(s0[i])) return fail(CRV_EINVAL, "s0 has non-finite entries");
+    for (int64_t i = 0; i < P; ++i)
+      if (!std::isfinite(theta0[i])) return fail(CRV_EINVAL, "theta0 has non-finite entries");
+
+    // zero the whole workspace (padding of interior arrays must stay finite)
+    {
+      Carve dry(nullptr);
+      Buffers<Real> tmpb;
+      const size_t bytes = carve<Real>(dry, cfg, tmpb);
+      CRV_HIP(hipMemsetAsync(ws, 0, bytes, st));
+    }
+    std::string err;
+    std::vector<double> qi, qp;
+    if (!well_sources(wells, n_wells, g.ne, g.dim, cfg.well_radius, qi, qp, err))
+      return fail(CRV_EINVAL, err);
+    const double h = 1.0 / g.ne;
+    const double hd = std::pow(h, g.dim);
+    std::vector<double> perm(nn), hq(nn);
+    for (size_t i = 0; i < nn; ++i) {
+      perm[i] = std::exp(log_perm[i]);
+      hq[i] = hd * (qi[i] + qp[i]);
+    }
+    crv_status s;
+    if ((s = upload(b.perm, perm.data(), nn))) return s;
+    if ((s = upload(b.poro, poro, nn))) return s;
+    if ((s = upload(b.qi, qi.data(), nn))) return s;
+    if ((s = upload(b.qp, qp.data(), nn))) return s;
+    if ((s = upload(b.hq, hq.data(), nn))) return s;
+    if (s0 && (s = upload(b.s, s0, nc))) return s;
+    if ((s = upload(b.theta, theta0, size_t(P)))) return s;
+
+    // discretisation tables (float64 on the host)
+    std::vector<int> kf, pf;
+    std::vector<double> kv, pv, gbv, gdbv, gxi, gw;
+    knot_table(g.ne, g.r, kf, kv);
+    projection_table(g.ne, g.r, pf, pv);
+    gauss_tables(g.ne, g.r, gbv, gdbv, gxi, gw);
+    if ((s = upload_raw(b.knot_first, kf))) return s;
+    if ((s = upload(b.knot_val, kv.data(), kv.size()))) return s;
+    if ((s = upload(b.proj_val, pv.data(), pv.size()))) return s;
+    if ((s = upload(b.gb, gbv.data(), gbv.size()))) return s;
+    if ((s = upload(b.gdb, gdbv.data(), gdbv.size()))) return s;
+    if ((s = upload(b.gxi, gxi.data(), gxi.size()))) return s;
+    if ((s = upload(b.gw, gw.data(), gw.size()))) return s;
+    std::vector<double> dst, lam;
+    dst_table(g.m, g.mp, dst, lam);
+    if ((s = upload(b.dst, dst.data(), dst.size()))) return s;
+    lam.resize(g.m);
+    if ((s = upload_raw(b.shifts, lam))) return s;
+    std::vector<double> band = mass_band(g.ne, g.r);
+    if ((s = upload_raw(b.band, band))) return s;
+
+    // float64 factorisations on the device (eq. 14 mass band, eq. 28 Gram lines)
+    launch_factor_band<Real>(b.band, g.nb, g.r, b.band_work, b.m_lt, b.m_invd, b.status, st);
+    launch_factor_shifted<Real>(b.shifts, g.m, g.m, g.mp, 1.0, b.g_lt, b.g_invd, st);
+    if ((s = check_launch())) return s;
+    refresh();
+    if ((s = check_launch())) return s;
+    CRV_HIP(hipStreamSynchronize(st));
+    int status = 0;
+    CRV_HIP(hipMemcpy(&status, b.status, sizeof(int), hipMemcpyDeviceToHost));
+    if (status) return fail(CRV_ENUMERIC, "mass matrix factorisation failed");
+    return CRV_OK;
+  }
+
+  void refresh() {
+    launch_refresh<Real>(g, b.s, b.knot_first, b.knot_val, b.perm, cfg.mu_w, cfg.mu_g,
+                         cfg.relperm_exp, b.s_nodal, b.alpha, st);
+  }
+
+  // q = G^-1 res: DST-I along y (product with the orthonormal sine basis),
+  // shifted tridiagonal solves along x, inverse DST-I along y (eq. 26-28).
+  void gram_solve() {
+    launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.res, g.mp, b.rhat, g.mp, st);
+    launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, g.mp, 1, b.g_lt, b.g_invd, g.mp, g.mp, st);
+    launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.qhat, g.mp, b.q, g.mp, st);
+  }
+
+  // x = (M^x (x) M^y)^-1 x in place (eq. 14): x-lines then y-lines.
+  void mass_solve(Real* x) {
+    launch_band_rows<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 0, 0, st);
+    launch_band_cols<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 1, 0, st);
+  }
+
+  // robust loss, g_u and the loss value (slot given by hist/t)
+  void loss_pass(double* hist, int cap, long long* t, int bump) {
+    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st);
+    gram_solve();
+    const int np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
+    launch_loss_finalize<Real>(b.loss_part, np, hist, cap, t, bump, st);
+  }
+
+  void grad_pass() {
+    const int rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);
+    launch_reduce_rows<Real>(b.partials, rows, P, b.red_scratch, b.grad, st);
+  }
+
+  void iteration() {
+    loss_pass(b.loss_hist, kLossCap, b.t_dev, 1);
+    grad_pass();
+    launch_adam<Real>(P, b.theta, b.am, b.av, b.grad, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps,
+                      b.t_dev, st);
+  }
+
+  crv_status train(int iters) override {
+    for (int i = 0; i < iters; ++i) iteration();
+    crv_status s = check_launch();
+    if (s) return s;
+    pretrained = true;
+    return CRV_OK;
+  }
+
+  void project_into_p() {
+    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    launch_project<Real>(g, b.u, b.proj_val, b.bvec, st);
+    mass_solve(b.bvec);
+    hipMemcpyAsync(b.p, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
+  }
+
+  void substep(double tau) {
+    launch_ads_assemble<Real>(g, b.s, b.p, b.perm, b.poro, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
+                              tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, b.bvec, st);
+    mass_solve(b.bvec);
+    hipMemcpyAsync(b.s, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
+  }
+
+  crv_status step(double dt) override {
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CRV_EINVAL, "dt must be > 0");
+    project_into_p();
+    const double tau = dt / cfg.substeps;
+    for (int k = 0; k < cfg.substeps; ++k) substep(tau);
+    launch_check_finite<Real>(b.s, nc, b.flag, st);
+    refresh();
+    for (int i = 0; i < cfg.adam_iters; ++i) iteration();
+    return check_launch();
+  }
+
+  crv_status substeps(double tau, int n) override {
+    if (!(tau > 0) || !std::isfinite(tau) || n < 0) return fail(CRV_EINVAL, "bad tau or count");
+    project_into_p();
+    for (int k = 0; k < n; ++k) substep(tau);
+    launch_check_finite<Real>(b.s, nc, b.flag, st);
+    refresh();
+    crv_status s = check_launch();
+    if (s) return s;
+    return sync_and_check();
+  }
+
+  crv_status fields(double* p_nodal, double* s_coefs, double* s_nodal) override {
+    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    crv_status s = check_launch();
+    if (s) return s;
+    if ((s = sync_and_check())) return s;
+    if (p_nodal && (s = download(p_nodal, b.u, nn))) return s;
+    if (s_coefs && (s = download(s_coefs, b.s, nc))) return s;
+    if (s_nodal && (s = download(s_nodal, b.s_nodal, nn))) return s;
+    return CRV_OK;
+  }
+
+  crv_status loss_grad(double* loss, double* dtheta, double* dlogperm) override {
+    loss_pass(b.loss_scalar, 1, b.t_zero, 0);
+    grad_pass();
+    if (dlogperm) launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, b.tmp_nodal, st);
+    crv_status s = check_launch();
+    if (s) return s;
+    CRV_HIP(hipStreamSynchronize(st));
+    if (loss) CRV_HIP(hipMemcpy(loss, b.loss_scalar, sizeof(double), hipMemcpyDeviceToHost));
+    if (dtheta && (s = download(dtheta, b.grad, size_t(P)))) return s;
+    if (dlogperm && (s = download(dlogperm, b.tmp_nodal, nn))) return s;
+    return CRV_OK;
+  }
+
+  crv_status get_state(double* th, double* m, double* v, int64_t* t) override {
+    crv_status s;
+    CRV_HIP(hipStreamSynchronize(st));
+    if (th && (s = download(th, b.theta, size_t(P)))) return s;
+    if (m && (s = download(m, b.am, size_t(P)))) return s;
+    if (v && (s = download(v, b.av, size_t(P)))) return s;
+    if (t) {
+      long long tt = 0;
+      CRV_HIP(hipMemcpy(&tt, b.t_dev, sizeof(tt), hipMemcpyDeviceToHost));
+      *t = tt;
+    }
+    return CRV_OK;
+  }
+
+  crv_status set_state(const double* th, const double* m, const double* v, int64_t t) override {
+    if (t < 0) return fail(CRV_EINVAL, "t must be >= 0");
+    crv_status s;
+    CRV_HIP(hipStreamSynchronize(st));
+    if (th && (s = upload(b.theta, th, size_t(P)))) return s;
+    if (m && (s = upload(b.am, m, size_t(P)))) return s;
+    if (v && (s = upload(b.av, v, size_t(P)))) return s;
+    long long tt = t;
+    CRV_HIP(hipMemcpy(b.t_dev, &tt, sizeof(tt), hipMemcpyHostToDevice));
+    pretrained = true;
+    return CRV_OK;
+  }
+
+  crv_status set_saturation(const double* sc) override {
+    for (size_t i = 0; i < nc; ++i)
+      if (!std::isfinite(sc[i])) return fail(CRV_EINVAL, "saturation has non-finite entries");
+    crv_status s = upload(b.s, sc, nc);
+    if (s) return s;
+    refresh();
+    return check_launch();
+  }
+
+  crv_status loss_history(double* out, int cap, int* n) override {
+    CRV_HIP(hipStreamSynchronize(st));
+    long long t = 0;
+    CRV_HIP(hipMemcpy(&t, b.t_dev, sizeof(t), hipMemcpyDeviceToHost));
+    std::vector<double> h(kLossCap);
+    CRV_HIP(hipMemcpy(h.data(), b.loss_hist, kLossCap * sizeof(double), hipMemcpyDeviceToHost));
+    long long avail = std::min<long long>(t, kLossCap);
+    long long cnt = std::min<long long>(avail, cap);
+    for (long long i = 0; i < cnt; ++i) out[i] = h[(t - cnt + i) % kLossCap];
+    *n = int(cnt);
+    return CRV_OK;
+  }
+
+  crv_status gram_solve_host(const double* res, double* q) override {
+    std::vector<double> pad(size_t(g.mp) * g.mp, 0.0);
+    for (int j = 0; j < g.m; ++j)
+      for (int i = 0; i < g.m; ++i) pad[size_t(j) * g.mp + i] = res[size_t(j) * g.m + i];
+    crv_status s = upload(b.res, pad.data(), pad.size());
+    if (s) return s;
+    gram_solve();
+    if ((s = check_launch())) return s;
+    if ((s = download(pad.data(), b.q, pad.size()))) return s;
+    for (int j = 0; j < g.m; ++j)
+      for (int i = 0; i < g.m; ++i) q[size_t(j) * g.m + i] = pad[size_t(j) * g.mp + i];
+    return CRV_OK;
+  }
+
+  crv_status mass_solve_host(const double* bin, double* x) override {
+    crv_status s = upload(b.bvec, bin, nc);
+    if (s) return s;
+    mass_solve(b.bvec);
+    if ((s = check_launch())) return s;
+    return download(x, b.bvec, nc);
+  }
+
+  crv_status project_host(double* p) override {
+    project_into_p();
+    crv_status s = check_launch();
+    if (s) return s;
+    return download(p, b.p, nc);
+  }
+};
+
+}  // namespace crv
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct crv_ctx {
+  std::unique_ptr<crv::SolverBase> impl;
+};
+
+using namespace crv;
+
+template <typename Real>
+static crv_status make_solver(const crv_config* c, void* ws, std::unique_ptr<SolverBase>& out) {
+  auto sv = std::make_unique<Solver<Real>>();
+  Carve cv(ws);
+  carve<Real>(cv, *c, sv->b);
+  out = std::move(sv);
+  return CRV_OK;
+}
+
+
+extern "C" {
+
+const char* crv_last_error(void) { return g_err.c_str(); }
+
+crv_status crv_config_default(crv_config* c) {
+  if (!c) return fail(CRV_EINVAL, "config is NULL");
+  std::memset(c, 0, sizeof(*c));
+  c->dim = 2;
+  c->n_elem = 32;
+  c->degree = 2;
+  c->width = 32;
+  c->hidden = 3;
+  c->precision = CRV_PREC_FP32;
+  c->mu_w = 1.0;
+  c->mu_g = 0.1;
+  c->relperm_exp = 2.0;
+  c->lr = 1e-4;
+  c->beta1 = 0.9;
+  c->beta2 = 0.999;
+  c->eps = 1e-8;
+  c->adam_iters = 100;
+  c->substeps = 10;
+  c->well_radius = 0.06;
+  return CRV_OK;
+}
+
+crv_status crv_param_count(const crv_config* c, int64_t* n) {
+  crv_status s = validate_config(c);
+  if (s) return s;
+  if (!n) return fail(CRV_EINVAL, "output is NULL");
+  *n = mlp_param_count(c->dim, c->width, c->hidden);
+  return CRV_OK;
+}
+
+crv_status crv_workspace_size(const crv_config* c, size_t* bytes) {
+  crv_status s = validate_config(c);
+  if (s) return s;
+  if (!bytes) return fail(CRV_EINVAL, "output is NULL");
+  Carve dry(nullptr);
+  if (c->precision == CRV_PREC_FP64) {
+    Buffers<double> b;
+    *bytes = carve<double>(dry, *c, b);
+  } else {
+    Buffers<float> b;
+    *bytes = carve<float>(dry, *c, b);
+  }
+  return CRV_OK;
+}
+
+crv_status crv_init(const crv_config* c, const double* log_perm, const double* porosity,
+                    const double* wells, int n_wells, const double* s0_coefs,
+                    const double* theta0, void* d_workspace, size_t ws_bytes, void* stream,
+                    crv_ctx** out) {
+  crv_status s = validate_config(c);
+  if (s) return s;
+  if (!out || !log_perm || !porosity || !theta0)
+    return fail(CRV_EINVAL, "log_perm, porosity, theta0 and out are required");
+  *out = nullptr;
+  size_t need = 0;
+  crv_workspace_size(c, &need);
+  bool owns = false;
+  if (d_workspace) {
+    if (ws_bytes < need)
+      return fail(CRV_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+      return fail(CRV_EINVAL, "workspace must be 256-byte aligned");
+  } else {
+    hipError_t e = hipMalloc(&d_workspace, need);
+    if (e != hipSuccess) return fail(CRV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    owns = true;
+  }
+  auto ctx = std::make_unique<crv_ctx>();
+  if (c->precision == CRV_PREC_FP64)
+    make_solver<double>(c, d_workspace, ctx->impl);
+  else
+    make_solver<float>(c, d_workspace, ctx->impl);
+  SolverBase& sv = *ctx->impl;
+  sv.cfg = *c;
+  sv.g = make_geom(*c);
+  sv.st = static_cast<hipStream_t>(stream);
+  sv.P = mlp_param_count(c->dim, c->width, c->hidden);
+  sv.ws = d_workspace;
+  sv.owns_ws = owns;
+  s = sv.init(log_perm, porosity, wells, n_wells, s0_coefs, theta0);
+  if (s) return s;
+  *out = ctx.release();
+  return CRV_OK;
+}
+
+#define CRV_CTX(c)                                          \
+  if (!(c) || !(c)->impl) return fail(CRV_EINVAL, "context is NULL"); \
+  SolverBase& sv = *(c)->impl;
+
+crv_status crv_pretrain_pressure(crv_ctx* c, int iters, double* final_loss) {
+  CRV_CTX(c);
+  if (iters < 0) return fail(CRV_EINVAL, "iters must be >= 0");
+  crv_status s = sv.train(iters);
+  if (s) return s;
+  if (final_loss) {
+    int n = 0;
+    s = sv.loss_history(final_loss, 1, &n);
+    if (s) return s;
+    if (n == 0) *final_loss = NAN;
+    if (n > 0 && !std::isfinite(*final_loss)) return fail(CRV_ENUMERIC, "non-finite loss");
+  } else {
+    hipError_t e = hipStreamSynchronize(sv.st);
+    if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
+  }
+  return CRV_OK;
+}
+
+crv_status crv_step(crv_ctx* c, double dt) {
+  CRV_CTX(c);
+  if (!sv.pretrained) return fail(CRV_ESTATE, "crv_step before crv_pretrain_pressure");
+  return sv.step(dt);
+}
+
+crv_status crv_get_fields(crv_ctx* c, double* p_nodal, double* s_coefs, double* s_nodal) {
+  CRV_CTX(c);
+  return sv.fields(p_nodal, s_coefs, s_nodal);
+}
+
+crv_status crv_loss_grad(crv_ctx* c, double* loss, double* dtheta, double* dlogperm) {
+  CRV_CTX(c);
+  return sv.loss_grad(loss, dtheta, dlogperm);
+}
+
+crv_status crv_get_state(crv_ctx* c, double* theta, double* m, double* v, int64_t* t) {
+  CRV_CTX(c);
+  return sv.get_state(theta, m, v, t);
+}
+
+crv_status crv_set_state(crv_ctx* c, const double* theta, const double* m, const double* v,
+                         int64_t t) {
+  CRV_CTX(c);
+  return sv.set_state(theta, m, v, t);
+}
+
+crv_status crv_set_saturation(crv_ctx* c, const double* s_coefs) {
+  CRV_CTX(c);
+  if (!s_coefs) return fail(CRV_EINVAL, "s_coefs is NULL");
+  return sv.set_saturation(s_coefs);
+}
+
+crv_status crv_loss_history(crv_ctx* c, double* out, int cap, int* n) {
+  CRV_CTX(c);
+  if (!out || !n || cap < 0) return fail(CRV_EINVAL, "bad output buffer");
+  return sv.loss_history(out, cap, n);
+}
+
+crv_status crv_gram_solve(crv_ctx* c, const double* res, double* q) {
+  CRV_CTX(c);
+  if (!res || !q) return fail(CRV_EINVAL, "NULL array");
+  return sv.gram_solve_host(res, q);
+}
+
+crv_status crv_mass_solve(crv_ctx* c, const double* b, double* x) {
+  CRV_CTX(c);
+  if (!b || !x) return fail(CRV_EINVAL, "NULL array");
+  return sv.mass_solve_host(b, x);
+}
+
+crv_status crv_project_pressure(crv_ctx* c, double* p) {
+  CRV_CTX(c);
+  if (!p) return fail(CRV_EINVAL, "NULL array");
+  return sv.project_host(p);
+}
+
+crv_status crv_saturation_substeps(crv_ctx* c, double tau, int n) {
+  CRV_CTX(c);
+  return sv.substeps(tau, n);
+}
+
+crv_status crv_destroy(crv_ctx* c) {
+  if (!c) return CRV_OK;
+  if (c->impl) (void)hipStreamSynchronize(c->impl->st);
+  delete c;
+  return CRV_OK;
+}
+
+}  // extern "C"

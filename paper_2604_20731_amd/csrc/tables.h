@@ -1,0 +1,51 @@
+// Host-side float64 tables of the discretisation (basis values, quadrature,
+// 1D mass bands, projection weights, DST-I basis, well sources).  Built once
+// per context at init; the device receives them converted to the working
+// precision.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace crv {
+
+// (r+1)-point Gauss-Legendre rule on [0,1]: points and weights.
+void gauss_rule01(int npts, std::vector<double>& x, std::vector<double>& w);
+
+// Values (and first derivatives) of the r+1 B-splines that are nonzero on the
+// knot span containing x (open uniform knots, Ne elements, degree r).
+// first = global index of the first of them.
+void local_basis(int ne, int r, double x, double* val, double* der, int* first);
+
+// Banded 1D mass matrix: band[i*(r+1) + t] = int B_i B_{i+t}, t = 0..r.
+std::vector<double> mass_band(int ne, int r);
+
+// Banded LDL^T of the symmetric band matrix (bandwidth r): L entries
+// lt[j*r + t-1] = L(j, j-t) (t = 1..r), inv_d[j] = 1/D(j).
+bool ldlt_band(const std::vector<double>& band, int n, int r,
+               std::vector<double>& lt, std::vector<double>& inv_d);
+
+// Projection weights Q(k, i) = int B_k(x) hat_i(x) dx; the nonzeros of row k
+// are nodes first(k) .. first(k)+r+1, stored qv[k*(r+2) + t].
+void projection_table(int ne, int r, std::vector<int>& first, std::vector<double>& qv);
+
+// Knot values: at node x_i = i/Ne, B-spline values of indices
+// first(i)..first(i)+r, stored kv[i*(r+1) + t].
+void knot_table(int ne, int r, std::vector<int>& first, std::vector<double>& kv);
+
+// Per element e and Gauss point g (r+1 per element): values and derivatives
+// of the r+1 local basis functions (global indices e..e+r), and the local
+// coordinate xi in [0,1] of every Gauss point and its weight (times h_e).
+void gauss_tables(int ne, int r, std::vector<double>& gb, std::vector<double>& gdb,
+                  std::vector<double>& xi, std::vector<double>& w);
+
+// Orthonormal DST-I basis of size m, padded to mp x mp with zeros:
+// S(k, j) = sqrt(2/(m+1)) sin((k+1)(j+1) pi/(m+1)); lam[k] = 4 sin^2((k+1) pi/(2(m+1))).
+void dst_table(int m, int mp, std::vector<double>& s, std::vector<double>& lam);
+
+// Well sources on the nodal grid (injectors and producers separate).
+// Returns false with a message if a well covers no node or a boundary node.
+bool well_sources(const double* wells, int n_wells, int ne, int dim, double radius,
+                  std::vector<double>& q_inj, std::vector<double>& q_prod, std::string& err);
+
+}  // namespace crv

@@ -154,10 +154,10 @@ def make_problem(name: str, seed: int = 0, **over) -> Problem:
           layered log-permeability, 5 balanced wells, 20 steps.
     c5    3D, 128 quadratic elements, 129^3 nodes, 3->4x128->1, BF16 MLP,
           GRF l=0.1, two vertical injectors, 10 steps.
-    tiny  2D, 8 quadratic elements, 2->2x8->1 (unit tests).
+    tiny  2D, 8 quadratic elements, 2->2x16->1 (unit tests).
     """
     presets = {
-        "tiny": dict(dim=2, n_elem=8, degree=2, width=8, hidden=2, ell=0.2, wells="pair",
+        "tiny": dict(dim=2, n_elem=8, degree=2, width=16, hidden=2, ell=0.2, wells="pair",
                      pretrain_iters=20, steps=2, precision="fp64"),
         "c1": dict(dim=2, n_elem=32, degree=2, width=32, hidden=3, ell=0.1, wells="pair",
                    pretrain_iters=2000, steps=10, precision="fp64"),

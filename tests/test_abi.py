@@ -1,0 +1,58 @@
+"""Host-side checks of the C ABI (no device work): the library loads, exports
+every function include/crv.h declares, validates configurations and sizes its
+workspace consistently."""
+import os
+import re
+
+import pytest
+
+from paper_2604_20731_amd import crv, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "crv.h")).read()
+    return sorted(set(re.findall(r"\b(crv_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert "crv_init" in names and "crv_step" in names
+    for n in names:
+        assert hasattr(crv.LIB, n), n
+    assert sorted(crv.EXPORTED) == names
+
+
+@pytest.mark.parametrize("dim,width,hidden", [(2, 32, 3), (2, 64, 4), (2, 128, 4), (3, 128, 4)])
+def test_param_count_matches_layout(dim, width, hidden):
+    if dim == 3:
+        pytest.skip("3D path not built")
+    cfg = crv.config(dim=dim, width=width, hidden=hidden)
+    assert crv.param_count(cfg) == inputs.n_params(dim, width, hidden)
+    assert crv.param_count(cfg) == inputs.theta_xavier(dim, width, hidden, 0).size
+
+
+def test_config_validation_errors():
+    bad = [dict(dim=4), dict(n_elem=2), dict(degree=5), dict(width=48), dict(hidden=0),
+           dict(mu_g=0.0), dict(lr=-1.0), dict(well_radius=0.0), dict(substeps=0),
+           dict(precision=7)]
+    for kw in bad:
+        cfg = crv.config(**kw)
+        with pytest.raises(crv.CrvError) as ei:
+            crv.workspace_size(cfg)
+        assert ei.value.status == crv.CRV_EINVAL, kw
+
+
+def test_workspace_grows_with_grid_and_precision():
+    a = crv.workspace_size(crv.config(n_elem=64, width=64, hidden=4))
+    b = crv.workspace_size(crv.config(n_elem=128, width=64, hidden=4))
+    c = crv.workspace_size(crv.config(n_elem=128, width=64, hidden=4, precision="fp64"))
+    assert 0 < a < b < c
+    assert a % 256 == 0
+
+
+def test_defaults():
+    cfg = crv.config()
+    assert cfg.lr == 1e-4 and cfg.adam_iters == 100 and cfg.substeps == 10
+    assert cfg.mu_w == 1.0 and cfg.mu_g == 0.1 and cfg.relperm_exp == 2.0
