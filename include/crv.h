@@ -158,6 +158,31 @@ crv_status crv_mass_solve(crv_ctx* ctx, const double* b, double* x);
 crv_status crv_project_pressure(crv_ctx* ctx, double* p_coefs);
 crv_status crv_saturation_substeps(crv_ctx* ctx, double tau, int n);
 
+/* Kernel timing with HIP events on the context's stream (bench and
+ * profiling).  While enabled, every launch of the kernels below is bracketed
+ * by an event pair; crv_profile_read synchronises and returns, for one
+ * kernel id, the summed duration in milliseconds and the number of launches
+ * since the last crv_profile_enable(ctx, 1). */
+typedef enum {
+  CRV_K_MLP_FWD = 0,   /* network forward (u at the nodes) */
+  CRV_K_MLP_BWD,       /* network backward (recompute + backprop + partials) */
+  CRV_K_RESIDUAL,      /* collocation residual */
+  CRV_K_GRAM_DST,      /* DST-I products of the Gram solve (2 per solve) */
+  CRV_K_GRAM_LINES,    /* shifted tridiagonal line solves */
+  CRV_K_ADJOINT,       /* adjoint stencil + loss partials */
+  CRV_K_LOSS,          /* loss reduction */
+  CRV_K_GRAD_REDUCE,   /* gradient partial reduction passes */
+  CRV_K_ADAM,          /* fused Adam */
+  CRV_K_REFRESH,       /* alpha refresh */
+  CRV_K_PROJECT,       /* pressure projection assembly */
+  CRV_K_ADS_ASSEMBLE,  /* saturation right-hand side */
+  CRV_K_MASS_ROWS,     /* mass solve, contiguous direction */
+  CRV_K_MASS_COLS,     /* mass solve, strided direction */
+  CRV_K_COUNT
+} crv_kernel;
+crv_status crv_profile_enable(crv_ctx* ctx, int enable);
+crv_status crv_profile_read(crv_ctx* ctx, int kernel, double* total_ms, int64_t* count);
+
 crv_status crv_destroy(crv_ctx* ctx);
 const char* crv_last_error(void);
 

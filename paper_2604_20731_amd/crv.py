@@ -26,8 +26,12 @@ EXPORTED = [
     "crv_pretrain_pressure", "crv_step", "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_loss_history",
     "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
-    "crv_saturation_substeps", "crv_destroy", "crv_last_error",
+    "crv_saturation_substeps", "crv_profile_enable", "crv_profile_read", "crv_destroy",
+    "crv_last_error",
 ]
+
+KERNELS = ["mlp_fwd", "mlp_bwd", "residual", "gram_dst", "gram_lines", "adjoint", "loss",
+           "grad_reduce", "adam", "refresh", "project", "ads_assemble", "mass_rows", "mass_cols"]
 
 
 class CrvConfig(C.Structure):
@@ -75,6 +79,8 @@ def _load() -> C.CDLL:
         "crv_mass_solve": [vp, dp, dp],
         "crv_project_pressure": [vp, dp],
         "crv_saturation_substeps": [vp, C.c_double, C.c_int],
+        "crv_profile_enable": [vp, C.c_int],
+        "crv_profile_read": [vp, C.c_int, dp, C.POINTER(C.c_int64)],
         "crv_destroy": [vp],
         "crv_last_error": [],
     }
@@ -235,6 +241,18 @@ class Scenario:
 
     def saturation_substeps(self, tau: float, n: int):
         _check(LIB.crv_saturation_substeps(self.ctx, float(tau), int(n)))
+
+    def profile_enable(self, on: bool = True):
+        _check(LIB.crv_profile_enable(self.ctx, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last profile_enable."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n = C.c_double(), C.c_int64()
+            _check(LIB.crv_profile_read(self.ctx, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
 
 def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:

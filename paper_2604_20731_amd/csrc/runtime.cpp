@@ -174,7 +174,44 @@ struct SolverBase {
   bool owns_ws = false;
   void* ws = nullptr;
   bool pretrained = false;
+
+  // ---- event timing of kernel launches ----
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  int open_k = -1;
+  hipEvent_t open_ev = nullptr;
+  hipEvent_t next_event() {
+    if (pool_used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[pool_used++];
+  }
+  void tb(int k) {
+    if (!prof) return;
+    open_k = k;
+    open_ev = next_event();
+    if (open_ev) hipEventRecord(open_ev, st);
+  }
+  void te() {
+    if (!prof || open_k < 0) return;
+    hipEvent_t e = next_event();
+    if (e && open_ev) {
+      hipEventRecord(e, st);
+      marks.push_back({open_k, {open_ev, e}});
+    }
+    open_k = -1;
+  }
+  void profile_reset() {
+    marks.clear();
+    pool_used = 0;
+  }
+
   virtual ~SolverBase() {
+    for (auto e : pool) (void)hipEventDestroy(e);
     if (owns_ws && ws) (void)hipFree(ws);
   }
   virtual crv_status init(const double*, const double*, const double*, int, const double*,
@@ -314,43 +351,73 @@ struct Solver : SolverBase {
   }
 
   void refresh() {
+    tb(CRV_K_REFRESH);
     launch_refresh<Real>(g, b.s, b.knot_first, b.knot_val, b.perm, cfg.mu_w, cfg.mu_g,
                          cfg.relperm_exp, b.s_nodal, b.alpha, st);
+    te();
   }
 
   // q = G^-1 res: DST-I along y (product with the orthonormal sine basis),
   // shifted tridiagonal solves along x, inverse DST-I along y (eq. 26-28).
   void gram_solve() {
+    tb(CRV_K_GRAM_DST);
     launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.res, g.mp, b.rhat, g.mp, st);
+    te();
+    tb(CRV_K_GRAM_LINES);
     launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, g.mp, 1, b.g_lt, b.g_invd, g.mp, g.mp, st);
+    te();
+    tb(CRV_K_GRAM_DST);
     launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.qhat, g.mp, b.q, g.mp, st);
+    te();
   }
 
   // x = (M^x (x) M^y)^-1 x in place (eq. 14): x-lines then y-lines.
   void mass_solve(Real* x) {
+    tb(CRV_K_MASS_ROWS);
     launch_band_rows<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 0, 0, st);
+    te();
+    tb(CRV_K_MASS_COLS);
     launch_band_cols<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 1, 0, st);
+    te();
   }
 
   // robust loss, g_u and the loss value (slot given by hist/t)
-  void loss_pass(double* hist, int cap, long long* t, int bump) {
+  void forward() {
+    tb(CRV_K_MLP_FWD);
     launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    te();
+  }
+
+  void loss_pass(double* hist, int cap, long long* t, int bump) {
+    forward();
+    tb(CRV_K_RESIDUAL);
     launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st);
+    te();
     gram_solve();
+    tb(CRV_K_ADJOINT);
     const int np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
+    te();
+    tb(CRV_K_LOSS);
     launch_loss_finalize<Real>(b.loss_part, np, hist, cap, t, bump, st);
+    te();
   }
 
   void grad_pass() {
+    tb(CRV_K_MLP_BWD);
     const int rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);
+    te();
+    tb(CRV_K_GRAD_REDUCE);
     launch_reduce_rows<Real>(b.partials, rows, P, b.red_scratch, b.grad, st);
+    te();
   }
 
   void iteration() {
     loss_pass(b.loss_hist, kLossCap, b.t_dev, 1);
     grad_pass();
+    tb(CRV_K_ADAM);
     launch_adam<Real>(P, b.theta, b.am, b.av, b.grad, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps,
                       b.t_dev, st);
+    te();
   }
 
   crv_status train(int iters) override {
@@ -362,15 +429,19 @@ struct Solver : SolverBase {
   }
 
   void project_into_p() {
-    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    forward();
+    tb(CRV_K_PROJECT);
     launch_project<Real>(g, b.u, b.proj_val, b.bvec, st);
+    te();
     mass_solve(b.bvec);
     hipMemcpyAsync(b.p, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
   }
 
   void substep(double tau) {
+    tb(CRV_K_ADS_ASSEMBLE);
     launch_ads_assemble<Real>(g, b.s, b.p, b.perm, b.poro, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
                               tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, b.bvec, st);
+    te();
     mass_solve(b.bvec);
     hipMemcpyAsync(b.s, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
   }
@@ -692,6 +763,36 @@ crv_status crv_project_pressure(crv_ctx* c, double* p) {
 crv_status crv_saturation_substeps(crv_ctx* c, double tau, int n) {
   CRV_CTX(c);
   return sv.substeps(tau, n);
+}
+
+crv_status crv_profile_enable(crv_ctx* c, int enable) {
+  CRV_CTX(c);
+  hipError_t e = hipStreamSynchronize(sv.st);
+  if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
+  sv.profile_reset();
+  sv.prof = enable != 0;
+  return CRV_OK;
+}
+
+crv_status crv_profile_read(crv_ctx* c, int kernel, double* total_ms, int64_t* count) {
+  CRV_CTX(c);
+  if (kernel < 0 || kernel >= CRV_K_COUNT || !total_ms || !count)
+    return fail(CRV_EINVAL, "bad kernel id or output");
+  hipError_t e = hipStreamSynchronize(sv.st);
+  if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
+  double tot = 0;
+  int64_t n = 0;
+  for (auto& m : sv.marks) {
+    if (m.first != kernel) continue;
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, m.second.first, m.second.second);
+    if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *count = n;
+  return CRV_OK;
 }
 
 crv_status crv_destroy(crv_ctx* c) {
