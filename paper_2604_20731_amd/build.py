@@ -26,6 +26,7 @@ SOURCES = [
     "k_fields.hip",
     "k_solve.hip",
     "k_mlp.hip",
+    "k_mlp_mfma.hip",
 ]
 
 ARCH = os.environ.get("CRV_OFFLOAD_ARCH", "gfx950")

@@ -109,4 +109,17 @@ void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double
                  double beta1, double beta2, double eps, const long long* t_dev,
                  hipStream_t st);
 
+// ---- network on matrix cores (k_mlp_mfma.hip), float32 parameters ----------
+bool mlp_mfma_supported(int dim, int width, int hidden, bool bf16);
+int64_t mlp_fragment_elems(int width, int hidden);
+// rearrange theta into the MFMA operand fragments (bf16 or float32)
+void launch_pack_fragments(const float* theta, int dim, int width, int hidden, bool bf16,
+                           void* frag, hipStream_t st);
+void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, bool bf16, const float* theta,
+                             const void* frag, float* u, hipStream_t st);
+int mlp_bwd_mfma_blocks(const Geom& g, bool bf16, int cu_count);
+void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, bool bf16, int64_t P,
+                              const float* theta, const void* frag, const float* gu,
+                              float* partials, int blocks, hipStream_t st);
+
 }  // namespace crv

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/crv.h"
@@ -82,9 +83,17 @@ struct Buffers {
   double *loss_hist, *loss_scalar;
   long long *t_dev, *t_zero;
   int* flag;
+  void* frag;      // MFMA weight fragments (bf16 or float32)
   int bwd_rows;
   int loss_np;
 };
+
+constexpr int kMaxBwdBlocks = 256;  // persistent backward blocks (one per CU on MI355X)
+
+static bool uses_mfma(const crv_config& c) {
+  return c.precision != CRV_PREC_FP64 &&
+         mlp_mfma_supported(c.dim, c.width, c.hidden, c.precision == CRV_PREC_BF16);
+}
 
 template <typename Real>
 static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
@@ -131,7 +140,10 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.am = cv.take<Real>(P);
   b.av = cv.take<Real>(P);
   b.grad = cv.take<Real>(P);
-  b.bwd_rows = mlp_backward_rows(g, ms, int(sizeof(Real)));
+  b.frag = cv.take<float>(size_t(std::max<int64_t>(1, mlp_fragment_elems(c.width, c.hidden))));
+  b.bwd_rows = uses_mfma(c) ? std::min(kMaxBwdBlocks, mlp_bwd_mfma_blocks(g, c.precision == CRV_PREC_BF16,
+                                                                          kMaxBwdBlocks))
+                            : mlp_backward_rows(g, ms, int(sizeof(Real)));
   b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
   b.loss_np = adjoint_partials(g);
@@ -154,7 +166,8 @@ static crv_status validate_config(const crv_config* c) {
   if (c->hidden < 1 || c->hidden > 8) return fail(CRV_EINVAL, "hidden must be in [1, 8]");
   if (c->precision != CRV_PREC_FP32 && c->precision != CRV_PREC_FP64 && c->precision != CRV_PREC_BF16)
     return fail(CRV_EINVAL, "unknown precision");
-  if (c->precision == CRV_PREC_BF16) return fail(CRV_EINVAL, "bf16 network path not available");
+  if (c->precision == CRV_PREC_BF16 && !mlp_mfma_supported(c->dim, c->width, c->hidden, true))
+    return fail(CRV_EINVAL, "bf16 network path needs width 32 or 64 and 3 or 4 hidden layers");
   if (!(c->mu_w > 0) || !(c->mu_g > 0)) return fail(CRV_EINVAL, "viscosities must be > 0");
   if (!(c->relperm_exp >= 1)) return fail(CRV_EINVAL, "relperm_exp must be >= 1");
   if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) ||
@@ -235,6 +248,8 @@ struct Solver : SolverBase {
   Buffers<Real> b;
   MlpShape ms;
   size_t nn = 0, nc = 0;
+  bool mfma = false, bf16 = false;
+  int bwd_blocks = 0;
 
   // -------- host <-> device helpers --------
   crv_status upload(Real* dst, const double* src, size_t n) {
@@ -275,6 +290,14 @@ struct Solver : SolverBase {
     nn = size_t(ipow(g.n, g.dim));
     nc = size_t(ipow(g.nb, g.dim));
     ms = MlpShape{cfg.dim, cfg.width, cfg.hidden, P};
+    mfma = uses_mfma(cfg);
+    bf16 = cfg.precision == CRV_PREC_BF16;
+    if (mfma) {
+      int dev = 0, cus = kMaxBwdBlocks;
+      CRV_HIP(hipGetDevice(&dev));
+      CRV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      bwd_blocks = std::min(b.bwd_rows, mlp_bwd_mfma_blocks(g, bf16, std::min(cus, kMaxBwdBlocks)));
+    }
     for (size_t i = 0; i < nn; ++i) {
       if (!std::isfinite(log_perm[i])) return fail(CRV_EINVAL, "log_perm has non-finite entries");
       if (!(poro[i] > 0) || !std::isfinite(poro[i])) return fail(CRV_EINVAL, "porosity must be > 0");
@@ -342,6 +365,7 @@ struct Solver : SolverBase {
     launch_factor_shifted<Real>(b.shifts, g.m, g.m, g.mp, 1.0, b.g_lt, b.g_invd, st);
     if ((s = check_launch())) return s;
     refresh();
+    pack();
     if ((s = check_launch())) return s;
     CRV_HIP(hipStreamSynchronize(st));
     int status = 0;
@@ -382,8 +406,22 @@ struct Solver : SolverBase {
   }
 
   // robust loss, g_u and the loss value (slot given by hist/t)
+  // weight fragments of the matrix-core kernels follow every change of theta
+  void pack() {
+    if constexpr (std::is_same<Real, float>::value) {
+      if (mfma) launch_pack_fragments(b.theta, cfg.dim, cfg.width, cfg.hidden, bf16, b.frag, st);
+    }
+  }
+
   void forward() {
     tb(CRV_K_MLP_FWD);
+    if constexpr (std::is_same<Real, float>::value) {
+      if (mfma) {
+        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, bf16, b.theta, b.frag, b.u, st);
+        te();
+        return;
+      }
+    }
     launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
     te();
   }
@@ -404,7 +442,15 @@ struct Solver : SolverBase {
 
   void grad_pass() {
     tb(CRV_K_MLP_BWD);
-    const int rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);
+    int rows = 0;
+    if constexpr (std::is_same<Real, float>::value) {
+      if (mfma) {
+        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, bf16, P, b.theta, b.frag, b.gu,
+                                 b.partials, bwd_blocks, st);
+        rows = bwd_blocks;
+      }
+    }
+    if (!rows) rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);
     te();
     tb(CRV_K_GRAD_REDUCE);
     launch_reduce_rows<Real>(b.partials, rows, P, b.red_scratch, b.grad, st);
@@ -417,6 +463,7 @@ struct Solver : SolverBase {
     tb(CRV_K_ADAM);
     launch_adam<Real>(P, b.theta, b.am, b.av, b.grad, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps,
                       b.t_dev, st);
+    pack();
     te();
   }
 
@@ -513,6 +560,8 @@ struct Solver : SolverBase {
     if (th && (s = upload(b.theta, th, size_t(P)))) return s;
     if (m && (s = upload(b.am, m, size_t(P)))) return s;
     if (v && (s = upload(b.av, v, size_t(P)))) return s;
+    pack();
+    if ((s = check_launch())) return s;
     long long tt = t;
     CRV_HIP(hipMemcpy(b.t_dev, &tt, sizeof(tt), hipMemcpyHostToDevice));
     pretrained = true;

@@ -37,21 +37,30 @@ def test_gram_solve(prec, ne):
     assert rel(q, pressure.gram_solve(res)) < TOL[prec] * (10 if ne >= 256 else 1)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name,over", [("tiny", {}), ("c1", {}), ("c1", dict(n_elem=40, width=64, hidden=4)),
-                                       ("c1", dict(degree=3, width=16, hidden=2))])
+GRAD_CASES = [("tiny", {}), ("c1", {}), ("c1", dict(n_elem=40, width=64, hidden=4)),
+              ("c1", dict(degree=3, width=16, hidden=2)), ("c1", dict(n_elem=256, width=64, hidden=4)),
+              ("c1", dict(n_elem=100, width=32, hidden=4))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("name,over", GRAD_CASES)
 def test_loss_and_gradients(prec, name, over):
+    """Robust loss, dLOSS/dtheta and dLOSS/dlogK of the same parameters.
+    Widths 32/64 with 3-4 hidden layers run on the matrix cores in fp32/bf16
+    (257^2 and 101^2 nodes leave a partial last 32-node tile)."""
     say("loss_grad", prec, name, over)
     prob = problem(name, **over)
+    if prec == "bf16" and not (prob.width in (32, 64) and prob.hidden in (3, 4)):
+        pytest.skip("bf16 network path covers widths 32/64 with 3-4 hidden layers")
     sc = scenario_for(prob, prec)
     orc = oracle_for(prob)
     loss, g, gl = sc.loss_grad(with_logperm=True)
     lref, gref = orc.loss_and_grad()
     glref = orc.loss_grad_logperm()
-    tol = 1e-10 if prec == "fp64" else 1e-4
-    assert abs(loss - lref) <= tol * abs(lref)
-    assert rel(g, gref) < tol
-    assert rel(gl, glref) < tol
+    el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
+    say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
+    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1}[prec]
+    assert el <= tol and eg < tol and egl < tol
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -96,7 +105,7 @@ def test_saturation_substeps(prec, nsub, ne, r, wells):
     assert rel(s_gpu - s0, orc.s - s0) < (1e-10 if prec == "fp64" else 1e-3)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16", 5e-2)])
 def test_coupled_trajectory_c1(prec, tol):
     """C1 geometry: pretraining then coupled steps, fields after every step."""
     say("coupled c1", prec)
@@ -113,8 +122,9 @@ def test_coupled_trajectory_c1(prec, tol):
         orc.step(dt)
         p, s, sn = sc.fields()
         pr, sr, snr = orc.fields()
-        say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}")
+        say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
         assert rel(p, pr) < tol and rel(s, sr) < tol and rel(sn, snr) < tol
     hist = sc.loss_history()
     assert len(hist) == n_pre + n_steps * 100
+    say(f"  loss history {rel(hist, np.array(orc.loss_history)):.3e}")
     assert rel(hist, np.array(orc.loss_history)) < tol
