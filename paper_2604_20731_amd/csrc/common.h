@@ -26,10 +26,12 @@ __host__ __device__ inline int64_t ipow(int64_t b, int e) {
   return r;
 }
 
-// tanh from its definition 1 - 2/(exp(2x)+1); exp overflow gives +1, underflow -1.
+// tanh from its definition 1 - 2/(exp(2x)+1), on the hardware base-2
+// exponential and reciprocal (each about 1 ulp): exp(2x) = 2^(x * 2/ln 2).
+// Overflow of the exponential gives +1, underflow -1.
 __device__ inline float tanh_fast(float x) {
-  const float e = __expf(2.0f * x);
-  return 1.0f - 2.0f / (e + 1.0f);
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+  return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 __device__ inline double tanh_fast(double x) { return tanh(x); }
 

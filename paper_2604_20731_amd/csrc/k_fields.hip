@@ -128,22 +128,19 @@ int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* 
 template <typename Real>
 __global__ __launch_bounds__(256) void k_loss_finalize(const Real* __restrict__ part, int np,
                                                        double* __restrict__ hist, int cap,
-                                                       long long* __restrict__ t_dev, int bump) {
+                                                       const long long* __restrict__ t_dev,
+                                                       int slot_offset) {
   __shared__ double sbuf[256];
   double v = 0;
   for (int k = threadIdx.x; k < np; k += 256) v += double(part[k]);
   const double tot = block_sum(v, sbuf);
-  if (threadIdx.x == 0) {
-    const long long t = *t_dev;
-    hist[t % cap] = tot;
-    if (bump) *t_dev = t + 1;
-  }
+  if (threadIdx.x == 0) hist[(*t_dev + slot_offset) % cap] = tot;
 }
 
 template <typename Real>
 void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int cap,
-                          long long* t_dev, int bump, hipStream_t st) {
-  k_loss_finalize<Real><<<1, 256, 0, st>>>(partials, np, loss_hist, cap, t_dev, bump);
+                          const long long* t_dev, int slot_offset, hipStream_t st) {
+  k_loss_finalize<Real><<<1, 256, 0, st>>>(partials, np, loss_hist, cap, t_dev, slot_offset);
 }
 
 // dLOSS/dalpha_p = 2 sum_dir (u_{p+e}-u_p)(q_{p+e}-q_p) (2D, q zero-extended);
@@ -423,6 +420,11 @@ void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, doub
 }
 
 // ---------------------------------------------------------------------------
+__global__ void k_bump(long long* t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t = *t + 1;
+}
+void launch_bump(long long* t, hipStream_t st) { k_bump<<<1, 64, 0, st>>>(t); }
+
 template <typename Real>
 __global__ void k_fill(Real* p, size_t n, Real v) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -461,7 +463,8 @@ void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st) {
                                   double, double, R*, R*, hipStream_t);                          \
   template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t);  \
   template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t); \
-  template void launch_loss_finalize<R>(const R*, int, double*, int, long long*, int, hipStream_t); \
+  template void launch_loss_finalize<R>(const R*, int, double*, int, const long long*, int,      \
+                                        hipStream_t);                                            \
   template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t); \
   template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t);             \
   template void launch_ads_assemble<R>(const Geom&, const R*, const R*, const R*, const R*,      \

@@ -37,9 +37,10 @@ __device__ inline void node_input(const Geom& g, int64_t p, Real* z, bool* inter
 // exact i/N as the oracle computes it (double division, then scaling)
 template <typename Real, int W, int DIM>
 __global__ __launch_bounds__(256) void k_mlp_fwd(Geom g, int hidden, const Real* __restrict__ th,
-                                                 Real* __restrict__ u) {
+                                                 Real* __restrict__ u, long long* t_bump) {
   const int64_t total = ipow(g.n, DIM);
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t_bump && p == 0) *t_bump = *t_bump + 1;  // first kernel of an Adam iteration
   if (p >= total) return;
   Real z[DIM];
   bool interior;
@@ -216,11 +217,11 @@ int mlp_backward_rows(const Geom& g, const MlpShape& s, int real_bytes) {
 
 template <typename Real>
 void launch_mlp_forward(const Geom& g, const MlpShape& s, const Real* theta, Real* u,
-                        hipStream_t st) {
+                        long long* t_bump, hipStream_t st) {
   const int64_t total = ipow(g.n, s.dim);
   dim3 grid(cdiv(total, 256));
 #define CRV_F(WW, DD) \
-  if (s.width == WW && s.dim == DD) { k_mlp_fwd<Real, WW, DD><<<grid, 256, 0, st>>>(g, s.hidden, theta, u); return; }
+  if (s.width == WW && s.dim == DD) { k_mlp_fwd<Real, WW, DD><<<grid, 256, 0, st>>>(g, s.hidden, theta, u, t_bump); return; }
   CRV_F(16, 2) CRV_F(32, 2) CRV_F(64, 2) CRV_F(128, 2)
   CRV_F(16, 3) CRV_F(32, 3) CRV_F(64, 3) CRV_F(128, 3)
 #undef CRV_F
@@ -301,7 +302,8 @@ void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double
 }
 
 #define CRV_INST(R)                                                                            \
-  template void launch_mlp_forward<R>(const Geom&, const MlpShape&, const R*, R*, hipStream_t); \
+  template void launch_mlp_forward<R>(const Geom&, const MlpShape&, const R*, R*, long long*,    \
+                                      hipStream_t);                                            \
   template int launch_mlp_backward<R>(const Geom&, const MlpShape&, const R*, const R*, R*,    \
                                       hipStream_t);                                            \
   template void launch_reduce_rows<R>(const R*, int, int64_t, R*, R*, hipStream_t);            \

@@ -202,9 +202,10 @@ __device__ inline void forward_tile(const float* sp,
 template <int W, int L, bool BF16, int DIM>
 __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __restrict__ th,
                                                       const typename MM<BF16>::elem* __restrict__ frag,
-                                                      float* __restrict__ u) {
+                                                      float* __restrict__ u, long long* t_bump) {
   constexpr int NR = W / 2;
   using SM = Small<W, L, DIM>;
+  if (t_bump && blockIdx.x == 0 && threadIdx.x == 0) *t_bump = *t_bump + 1;  // new Adam iteration
   __shared__ float sp[SM::SIZE];
   SM::stage(th, sp, threadIdx.x, blockDim.x);
   __syncthreads();
@@ -442,6 +443,108 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
 }
 
 // ---------------------------------------------------------------------------
+// Fused gradient reduction + Adam + fragment update.  Block = 4 waves over
+// 64 parameters (one per lane); wave w sums partial rows w, w+4, ... and the
+// four wave sums are added in a fixed order.  The updated weight of a
+// hidden-to-hidden layer is written straight into its two fragment slots
+// (the inverse of the k_pack_fragments map).
+// ---------------------------------------------------------------------------
+// flat accumulator register t and lane group g holding feature f (cfeat inverse)
+__device__ inline void cfeat_inv(int f, int* t, int* g) {
+  *g = (f >> 2) & 1;
+  *t = 16 * (f >> 5) + 4 * ((f & 31) >> 3) + (f & 3);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_reduce_adam_pack(
+    const float* __restrict__ part, int rows, int64_t P, float* __restrict__ th,
+    float* __restrict__ m, float* __restrict__ v, double lr, double b1, double b2, double eps,
+    const long long* __restrict__ t_dev, int dim, int W, int hidden,
+    typename MM<BF16>::elem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
+    double* __restrict__ hist, int cap) {
+  using T = MM<BF16>;
+  __shared__ float red[4][64];
+  if (blockIdx.x == gridDim.x - 1) {
+    // the extra block: loss of this iteration (fixed-order sum of the partials)
+    __shared__ double lb[256];
+    double v = 0;
+    for (int k = threadIdx.x; k < loss_np; k += 256) v += double(loss_part[k]);
+    const double tot = block_sum(v, lb);
+    if (threadIdx.x == 0) hist[(*t_dev - 1) % cap] = tot;
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
+  float s = 0.f;
+  if (p < P) {
+    int r = w;
+    for (; r + 12 < rows; r += 16) {
+      const float a0 = part[int64_t(r) * P + p], a1 = part[int64_t(r + 4) * P + p];
+      const float a2 = part[int64_t(r + 8) * P + p], a3 = part[int64_t(r + 12) * P + p];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; r < rows; r += 4) s += part[int64_t(r) * P + p];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || p >= P) return;
+  const float gg = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const double t = double(*t_dev);
+  const float c1 = float(1.0 - pow(b1, t)), c2 = float(1.0 - pow(b2, t));
+  const float mm = float(b1) * m[p] + float(1.0 - b1) * gg;
+  const float vv = float(b2) * v[p] + float(1.0 - b2) * gg * gg;
+  m[p] = mm;
+  v[p] = vv;
+  const float nw = th[p] - float(lr) * (mm / c1) / (sqrtf(vv / c2) + float(eps));
+  th[p] = nw;
+  if (frag == nullptr) return;
+  // hidden-to-hidden weight? layer l = 2..hidden occupies [off_l, off_l + W*W)
+  const int64_t base = int64_t(W) * dim + W;
+  if (p < base) return;
+  const int64_t rel = p - base, per = int64_t(W) * W + W;
+  const int hl = int(rel / per);
+  const int64_t within = rel % per;
+  if (hl >= hidden - 1 || within >= int64_t(W) * W) return;
+  const int o = int(within / W), i = int(within % W);
+  const int nks = W / T::KS, nmb = W / 32;
+  const typename MM<BF16>::elem e = typename MM<BF16>::elem(nw);
+  int tt, g;
+  // forward fragment: row o, contraction feature i
+  cfeat_inv(i, &tt, &g);
+  {
+    const int ks = tt / T::S, vv2 = tt % T::S, mb = o >> 5, lanei = (o & 31) + 32 * g;
+    frag[((((int64_t(hl) * 2 + 0) * nmb + mb) * nks + ks) * 64 + lanei) * T::S + vv2] = e;
+  }
+  // backward (transposed) fragment: row i, contraction feature o
+  cfeat_inv(o, &tt, &g);
+  {
+    const int ks = tt / T::S, vv2 = tt % T::S, mb = i >> 5, lanei = (i & 31) + 32 * g;
+    frag[((((int64_t(hl) * 2 + 1) * nmb + mb) * nks + ks) * 64 + lanei) * T::S + vv2] = e;
+  }
+}
+
+void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
+                             float* v, double lr, double b1, double b2, double eps,
+                             const long long* t_dev, int dim, int width, int hidden, bool bf16,
+                             void* frag, const float* loss_part, int loss_np, double* loss_hist,
+                             int cap, hipStream_t st) {
+  const int blocks = cdiv(P, 64) + 1;
+  if (bf16)
+    k_reduce_adam_pack<true><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps,
+                                                     t_dev, dim, width, hidden,
+                                                     static_cast<__bf16*>(frag), loss_part, loss_np,
+                                                     loss_hist, cap);
+  else
+    k_reduce_adam_pack<false><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps,
+                                                      t_dev, dim, width, hidden,
+                                                      static_cast<float*>(frag), loss_part, loss_np,
+                                                      loss_hist, cap);
+}
+
+// ---------------------------------------------------------------------------
 bool mlp_mfma_supported(int dim, int width, int hidden, bool bf16) {
   if (dim != 2) return false;
   if (!(hidden == 3 || hidden == 4)) return false;
@@ -464,17 +567,18 @@ void launch_pack_fragments(const float* theta, int dim, int width, int hidden, b
 }
 
 template <int W, int L, bool BF16>
-static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, hipStream_t st) {
+static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, long long* tb,
+                     hipStream_t st) {
   const int64_t total = ipow(g.n, 2);
   const int64_t tiles = (total + 31) / 32;
   k_mlp_fwd_mfma<W, L, BF16, 2><<<cdiv(tiles, 4), 256, 0, st>>>(
-      g, th, static_cast<const typename MM<BF16>::elem*>(frag), u);
+      g, th, static_cast<const typename MM<BF16>::elem*>(frag), u, tb);
 }
 
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, bool bf16, const float* theta,
-                             const void* frag, float* u, hipStream_t st) {
+                             const void* frag, float* u, long long* t_bump, hipStream_t st) {
 #define CRV_FW(WW, LL, BB) \
-  if (width == WW && hidden == LL && bf16 == BB) return fwd_inst<WW, LL, BB>(g, theta, frag, u, st);
+  if (width == WW && hidden == LL && bf16 == BB) return fwd_inst<WW, LL, BB>(g, theta, frag, u, t_bump, st);
   CRV_FW(32, 3, true) CRV_FW(64, 3, true)
   CRV_FW(32, 4, true) CRV_FW(64, 4, true)
   CRV_FW(32, 3, false) CRV_FW(64, 3, false) CRV_FW(32, 4, false) CRV_FW(64, 4, false)

@@ -237,53 +237,148 @@ void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_st
   }
 }
 
-// Strided lines: one thread per line (consecutive threads = consecutive
-// columns, so every row access is coalesced), shared coefficients.
+// Strided lines (element j of line c at x[j*row_stride + c]), shared
+// coefficients.  A block owns 64 consecutive lines (one per lane, so every
+// row access is coalesced) and splits their length into NWV chunks, one per
+// wavefront.  Each wave composes the affine maps of its chunk (particular
+// solution + r homogeneous ones), wave 0 scans the NWV chunk maps through LDS
+// in order, and every wave re-runs its chunk from its incoming state; the
+// backward sweep repeats this from the far end.
 template <typename Real, int R>
-__global__ __launch_bounds__(256) void k_band_cols(const Real* __restrict__ b, Real* __restrict__ x,
-                                                   int n, int ncols, int64_t rs,
-                                                   const Real* __restrict__ lt,
-                                                   const Real* __restrict__ invd,
-                                                   int64_t batch_stride) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  const Real* bb = b + int64_t(blockIdx.y) * batch_stride + c;
-  Real* xx = x + int64_t(blockIdx.y) * batch_stride + c;
-  Real s[R];
+__global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict__ b, Real* x, int n,
+                                                         int ncols, int64_t rs,
+                                                         const Real* __restrict__ lt,
+                                                         const Real* __restrict__ invd,
+                                                         int64_t batch_stride) {
+  constexpr int NWV = 16;
+  constexpr int NM = R * R + R;  // one affine map
+  __shared__ Real maps[NWV][NM][64];
+  __shared__ Real instate[NWV][R][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const bool colok = c < ncols;
+  const int ch = (n + NWV - 1) / NWV;        // rows per chunk
+  const int j0 = w * ch, j1 = min(n, j0 + ch);
+  const Real* bb = b + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
+  Real* xx = x + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
+
+  // compose the chunk's affine map of the forward (dir 0) or backward (dir 1)
+  // recurrence; src is b (forward) or the scaled forward result (backward)
+  auto chunk_map = [&](int dir, const Real* src) {
+    Real a[R][R], cc[R];
 #pragma unroll
-  for (int t = 0; t < R; ++t) s[t] = 0;
-  for (int j = 0; j < n; ++j) {
-    Real y = bb[int64_t(j) * rs];
+    for (int col = -1; col < R; ++col) {
+      Real st[R];
 #pragma unroll
-    for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * s[t - 1];
+      for (int t = 0; t < R; ++t) st[t] = (t == col) ? Real(1) : Real(0);
+      for (int e = 0; e < j1 - j0; ++e) {
+        const int j = dir == 0 ? j0 + e : j1 - 1 - e;
+        Real y = (col < 0) ? src[int64_t(j) * rs] : Real(0);
+        if (dir == 0) {
 #pragma unroll
-    for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
-    s[0] = y;
-    xx[int64_t(j) * rs] = y * invd[j];
+          for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * st[t - 1];
+        } else {
+#pragma unroll
+          for (int t = 1; t <= R; ++t)
+            if (j + t < n) y -= lt[int64_t(j + t) * R + (t - 1)] * st[t - 1];
+        }
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+        st[0] = y;
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        if (col < 0) cc[t] = st[t];
+        else a[t][col] = st[t];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      maps[w][R * R + i][lane] = cc[i];
+#pragma unroll
+      for (int k = 0; k < R; ++k) maps[w][i * R + k][lane] = a[i][k];
+    }
+  };
+  // wave 0 chains the chunk maps in order (dir 0: first to last chunk)
+  auto scan = [&](int dir) {
+    if (w != 0) return;
+    Real st[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) st[t] = 0;
+    for (int k = 0; k < NWV; ++k) {
+      const int q = dir == 0 ? k : NWV - 1 - k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) instate[q][t][lane] = st[t];
+      Real nx[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        Real acc = maps[q][R * R + i][lane];
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) acc += maps[q][i * R + k2][lane] * st[k2];
+        nx[i] = acc;
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) st[t] = nx[t];
+    }
+  };
+
+  if (colok) chunk_map(0, bb);
+  __syncthreads();
+  scan(0);
+  __syncthreads();
+  if (colok) {
+    Real st[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) st[t] = instate[w][t][lane];
+    for (int j = j0; j < j1; ++j) {
+      Real y = bb[int64_t(j) * rs];
+#pragma unroll
+      for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * st[t - 1];
+#pragma unroll
+      for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = y;
+      xx[int64_t(j) * rs] = y * invd[j];  // z_j = y_j / D_j (b is not read again)
+    }
   }
+  __syncthreads();  // every chunk of z is written before the backward maps read it
+  if (colok) chunk_map(1, xx);
+  __syncthreads();
+  scan(1);
+  __syncthreads();
+  if (colok) {
+    Real st[R];
 #pragma unroll
-  for (int t = 0; t < R; ++t) s[t] = 0;
-  for (int j = n - 1; j >= 0; --j) {
-    Real xv = xx[int64_t(j) * rs];
+    for (int t = 0; t < R; ++t) st[t] = instate[w][t][lane];
+    for (int j = j1 - 1; j >= j0; --j) {
+      Real xv = xx[int64_t(j) * rs];
 #pragma unroll
-    for (int t = 1; t <= R; ++t)
-      if (j + t < n) xv -= lt[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+      for (int t = 1; t <= R; ++t)
+        if (j + t < n) xv -= lt[int64_t(j + t) * R + (t - 1)] * st[t - 1];
 #pragma unroll
-    for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
-    s[0] = xv;
-    xx[int64_t(j) * rs] = xv;
+      for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = xv;
+      xx[int64_t(j) * rs] = xv;
+    }
   }
+}
+
+template <typename Real, int R>
+static void band_cols_dispatch(const Real* b, Real* x, int n, int nlines, int64_t rs,
+                               const Real* lt, const Real* inv_d, int64_t batch,
+                               int64_t batch_stride, hipStream_t st) {
+  dim3 grid(cdiv(nlines, 64), unsigned(batch));
+  k_band_cols_scan<Real, R><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
 }
 
 template <typename Real>
 void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t batch, int64_t batch_stride,
                       hipStream_t st) {
-  dim3 grid(cdiv(nlines, 64), unsigned(batch));
+  if (nlines <= 0) return;
   switch (r) {
-    case 1: k_band_cols<Real, 1><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
-    case 2: k_band_cols<Real, 2><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
-    default: k_band_cols<Real, 3><<<grid, 64, 0, st>>>(b, x, n, nlines, row_stride, lt, inv_d, batch_stride); break;
+    case 1: band_cols_dispatch<Real, 1>(b, x, n, nlines, row_stride, lt, inv_d, batch, batch_stride, st); break;
+    case 2: band_cols_dispatch<Real, 2>(b, x, n, nlines, row_stride, lt, inv_d, batch, batch_stride, st); break;
+    default: band_cols_dispatch<Real, 3>(b, x, n, nlines, row_stride, lt, inv_d, batch, batch_stride, st); break;
   }
 }
 
@@ -332,11 +427,57 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* _
     for (int j = 0; j < 4; ++j) C[int64_t(m0 + ty * 4 + i) * ldc + n0 + tx * 4 + j] = acc[i][j];
 }
 
+// float32 C = A B on the matrix cores (v_mfma_f32_32x32x2f32): one 32x32
+// output tile per block; the 4 waves split K in four contiguous ranges and
+// their partial tiles are summed in a fixed order through LDS.  Lane
+// (r = lane%32, g = lane/32) feeds A[m0+r][k+g] and B[k+g][n0+r] per step.
+typedef float gemm_f32x16_t __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
+                                                       const float* __restrict__ A, int lda,
+                                                       const float* __restrict__ B, int ldb,
+                                                       float* __restrict__ C, int ldc) {
+  __shared__ float part[4][32 * 33];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, g = lane >> 5;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int kq = K / 4, kb = w * kq;
+  const float* a = A + int64_t(m0 + r) * lda + kb + g;
+  const float* b = B + int64_t(kb + g) * ldb + n0 + r;
+  gemm_f32x16_t acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k = 0; k < kq; k += 16) {
+    float av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = a[k + 2 * u];
+      bv[u] = b[int64_t(k + 2 * u) * ldb];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) part[w][(8 * (i >> 2) + 4 * g + (i & 3)) * 33 + r] = acc[i];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int row = e >> 5, col = e & 31;
+    const float v = ((part[0][row * 33 + col] + part[1][row * 33 + col]) + part[2][row * 33 + col]) +
+                    part[3][row * 33 + col];
+    C[int64_t(m0 + row) * ldc + n0 + col] = v;
+  }
+}
+
 template <typename Real>
 void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
                  int ldc, hipStream_t st) {
-  dim3 grid(N / 64, M / 64);
-  k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+  if constexpr (sizeof(Real) == 4) {
+    // dims are multiples of 64, so K/4 is a multiple of 16
+    dim3 grid(N / 32, M / 32);
+    k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+  } else {
+    dim3 grid(N / 64, M / 64);
+    k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+  }
 }
 
 #define CRV_INST(R)                                                                            \

@@ -24,10 +24,12 @@ int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* 
                    Real* loss_partials, hipStream_t st);
 int adjoint_partials(const Geom& g);
 
-// Sum of the loss partials (fixed order) into loss_hist[t % cap], then ++t.
+// Sum of the loss partials (fixed order) into loss_hist[(t + slot_offset) % cap].
 template <typename Real>
 void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int cap,
-                          long long* t_dev, int bump, hipStream_t st);
+                          const long long* t_dev, int slot_offset, hipStream_t st);
+// ++*t (one thread)
+void launch_bump(long long* t, hipStream_t st);
 
 // a3 differentiation form: dLOSS/dlogK = 2 sum_dir grad+ u . grad+ q h^(d-2) * alpha.
 template <typename Real>
@@ -91,10 +93,10 @@ struct MlpShape {
   int64_t nparams;
 };
 int64_t mlp_param_count(int dim, int width, int hidden);
-// u = mask * NN(2x-1) on all nodes.
+// u = mask * NN(2x-1) on all nodes; t_bump (nullable) is incremented once.
 template <typename Real>
 void launch_mlp_forward(const Geom& g, const MlpShape& s, const Real* theta, Real* u,
-                        hipStream_t st);
+                        long long* t_bump, hipStream_t st);
 // per-block partial gradients of sum_p gu_p NN(z_p); returns rows written
 template <typename Real>
 int launch_mlp_backward(const Geom& g, const MlpShape& s, const Real* theta, const Real* gu,
@@ -116,8 +118,15 @@ int64_t mlp_fragment_elems(int width, int hidden);
 void launch_pack_fragments(const float* theta, int dim, int width, int hidden, bool bf16,
                            void* frag, hipStream_t st);
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, bool bf16, const float* theta,
-                             const void* frag, float* u, hipStream_t st);
+                             const void* frag, float* u, long long* t_bump, hipStream_t st);
 int mlp_bwd_mfma_blocks(const Geom& g, bool bf16, int cu_count);
+// fixed-order sum of the partial rows + Adam + fragment update (frag may be
+// null); one extra block sums the loss partials into loss_hist[(t-1) % cap]
+void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
+                             float* v, double lr, double b1, double b2, double eps,
+                             const long long* t_dev, int dim, int width, int hidden, bool bf16,
+                             void* frag, const float* loss_part, int loss_np, double* loss_hist,
+                             int cap, hipStream_t st);
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, bool bf16, int64_t P,
                               const float* theta, const void* frag, const float* gu,
                               float* partials, int blocks, hipStream_t st);

@@ -413,34 +413,35 @@ struct Solver : SolverBase {
     }
   }
 
-  void forward() {
+  // network forward into b.u; t_bump (nullable) marks the start of an Adam iteration
+  void forward(long long* t_bump = nullptr) {
     tb(CRV_K_MLP_FWD);
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, bf16, b.theta, b.frag, b.u, st);
+        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, bf16, b.theta, b.frag, b.u, t_bump, st);
         te();
         return;
       }
     }
-    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    launch_mlp_forward<Real>(g, ms, b.theta, b.u, t_bump, st);
     te();
   }
 
-  void loss_pass(double* hist, int cap, long long* t, int bump) {
-    forward();
+  // forward, residual, Gram solve and adjoint: b.u, b.res, b.q, b.gu and the
+  // per-block loss partials
+  void loss_pass(long long* t_bump) {
+    forward(t_bump);
     tb(CRV_K_RESIDUAL);
     launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st);
     te();
     gram_solve();
     tb(CRV_K_ADJOINT);
-    const int np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
-    te();
-    tb(CRV_K_LOSS);
-    launch_loss_finalize<Real>(b.loss_part, np, hist, cap, t, bump, st);
+    launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
     te();
   }
 
-  void grad_pass() {
+  // partial gradient rows of the network backward; returns the row count
+  int backward() {
     tb(CRV_K_MLP_BWD);
     int rows = 0;
     if constexpr (std::is_same<Real, float>::value) {
@@ -452,13 +453,34 @@ struct Solver : SolverBase {
     }
     if (!rows) rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);
     te();
+    return rows;
+  }
+
+  void grad_pass() {
+    const int rows = backward();
     tb(CRV_K_GRAD_REDUCE);
     launch_reduce_rows<Real>(b.partials, rows, P, b.red_scratch, b.grad, st);
     te();
   }
 
+  // one Adam iteration: the forward advances the step counter t, the loss
+  // of the iteration lands in loss_hist[(t-1) % cap]
   void iteration() {
-    loss_pass(b.loss_hist, kLossCap, b.t_dev, 1);
+    loss_pass(b.t_dev);
+    if constexpr (std::is_same<Real, float>::value) {
+      if (mfma) {
+        const int rows = backward();
+        tb(CRV_K_ADAM);
+        launch_reduce_adam_pack(b.partials, rows, P, b.theta, b.am, b.av, cfg.lr, cfg.beta1,
+                                cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, bf16,
+                                b.frag, b.loss_part, b.loss_np, b.loss_hist, kLossCap, st);
+        te();
+        return;
+      }
+    }
+    tb(CRV_K_LOSS);
+    launch_loss_finalize<Real>(b.loss_part, b.loss_np, b.loss_hist, kLossCap, b.t_dev, -1, st);
+    te();
     grad_pass();
     tb(CRV_K_ADAM);
     launch_adam<Real>(P, b.theta, b.am, b.av, b.grad, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps,
@@ -516,7 +538,7 @@ struct Solver : SolverBase {
   }
 
   crv_status fields(double* p_nodal, double* s_coefs, double* s_nodal) override {
-    launch_mlp_forward<Real>(g, ms, b.theta, b.u, st);
+    forward();
     crv_status s = check_launch();
     if (s) return s;
     if ((s = sync_and_check())) return s;
@@ -527,7 +549,8 @@ struct Solver : SolverBase {
   }
 
   crv_status loss_grad(double* loss, double* dtheta, double* dlogperm) override {
-    loss_pass(b.loss_scalar, 1, b.t_zero, 0);
+    loss_pass(nullptr);
+    launch_loss_finalize<Real>(b.loss_part, b.loss_np, b.loss_scalar, 1, b.t_zero, 0, st);
     grad_pass();
     if (dlogperm) launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, b.tmp_nodal, st);
     crv_status s = check_launch();
