@@ -218,8 +218,9 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
     Geom g, const Real* __restrict__ sc, const Real* __restrict__ pc,
     const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
     const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
-    const Real* __restrict__ gxi, const Real* __restrict__ gw, Real tau, Real inv_mu_w,
-    Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+    const Real* __restrict__ gxi, const Real* __restrict__ gw, const double* __restrict__ tau_dev,
+    Real inv_mu_w, Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+  const Real tau = Real(*tau_dev);
   constexpr int NG = R + 1;          // Gauss points per element and axis
   constexpr int TE = TC + R;         // elements per tile and axis
   constexpr int TCO = TC + 2 * R;    // coefficients touched per axis
@@ -332,9 +333,10 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
 template <typename Real>
 void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
-                         const Real* gdb, const Real* gxi, const Real* gw, double tau,
+                         const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
                          double mu_w, double mu_g, double nexp, Real* b, hipStream_t st) {
-  const Real t = Real(tau), iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  const double* t = tau;
+  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
   constexpr bool big = sizeof(Real) == 8;
   if (g.r == 1) {
     constexpr int TC = 16;
@@ -469,7 +471,8 @@ void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st) {
   template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t);             \
   template void launch_ads_assemble<R>(const Geom&, const R*, const R*, const R*, const R*,      \
                                        const R*, const R*, const R*, const R*, const R*,         \
-                                       const R*, double, double, double, double, R*, hipStream_t); \
+                                       const R*, const double*, double, double, double, R*,      \
+                                       hipStream_t);                                             \
   template void launch_factor_band<R>(const double*, int, int, double*, R*, R*, int*, hipStream_t); \
   template void launch_factor_shifted<R>(const double*, int, int, int, double, R*, R*, hipStream_t); \
   template void launch_fill<R>(R*, size_t, R, hipStream_t);                                      \

@@ -40,11 +40,12 @@ void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real
 template <typename Real>
 void launch_project(const Geom& g, const Real* u, const Real* proj_val, Real* b, hipStream_t st);
 
-// a10: b_kl = int [S B_kl + tau/phi (-lambda_g K grad p . grad B_kl + q_g B_kl)].
+// a10: b_kl = int [S B_kl + tau/phi (-lambda_g K grad p . grad B_kl + q_g B_kl)];
+// tau is read from device memory so a captured step serves any step length.
 template <typename Real>
 void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
-                         const Real* gdb, const Real* gxi, const Real* gw, double tau,
+                         const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
                          double mu_w, double mu_g, double nexp, Real* b, hipStream_t st);
 
 // K7f: float64 factorisations on the device.

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -82,6 +83,7 @@ struct Buffers {
   Real *theta, *am, *av, *grad, *partials, *red_scratch, *loss_part;
   double *loss_hist, *loss_scalar;
   long long *t_dev, *t_zero;
+  double* tau;     // substep length of the current step (device, read by the assembly)
   int* flag;
   void* frag;      // MFMA weight fragments (bf16 or float32)
   int bwd_rows;
@@ -152,6 +154,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.loss_scalar = cv.take<double>(1);
   b.t_dev = cv.take<long long>(1);
   b.t_zero = cv.take<long long>(1);
+  b.tau = cv.take<double>(1);
   b.flag = cv.take<int>(1);
   return (cv.off + 255) & ~size_t(255);
 }
@@ -395,13 +398,13 @@ struct Solver : SolverBase {
     te();
   }
 
-  // x = (M^x (x) M^y)^-1 x in place (eq. 14): x-lines then y-lines.
-  void mass_solve(Real* x) {
+  // dst = (M^x (x) M^y)^-1 src (eq. 14): x-lines src -> dst, then y-lines in place.
+  void mass_solve(const Real* src, Real* dst) {
     tb(CRV_K_MASS_ROWS);
-    launch_band_rows<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 0, 0, st);
+    launch_band_rows<Real>(src, dst, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 0, 0, st);
     te();
     tb(CRV_K_MASS_COLS);
-    launch_band_cols<Real>(x, x, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 1, 0, st);
+    launch_band_cols<Real>(dst, dst, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 1, 0, st);
     te();
   }
 
@@ -489,50 +492,116 @@ struct Solver : SolverBase {
     te();
   }
 
+  // ---- captured work: one hipGraph per sequence, replayed on the caller's stream ----
+  hipStream_t cap = nullptr;
+  hipGraphExec_t g_train = nullptr, g_step = nullptr;
+  bool graphs_off = std::getenv("CRV_NO_GRAPH") != nullptr;
+
+  ~Solver() override {
+    if (g_train) (void)hipGraphExecDestroy(g_train);
+    if (g_step) (void)hipGraphExecDestroy(g_step);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+
+  template <typename F>
+  crv_status capture(hipGraphExec_t* out, F&& body) {
+    if (!cap) CRV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t user = st;
+    st = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) body();
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    st = user;
+    if (e != hipSuccess) return fail(CRV_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(CRV_EHIP, std::string("end capture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(CRV_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+    return CRV_OK;
+  }
+
+  bool use_graphs() const { return !prof && !graphs_off; }
+
   crv_status train(int iters) override {
-    for (int i = 0; i < iters; ++i) iteration();
+    const int chunk = std::max(1, cfg.adam_iters);
+    int done = 0;
+    if (use_graphs() && iters >= chunk) {
+      if (!g_train) {
+        crv_status s = capture(&g_train, [&] {
+          for (int i = 0; i < chunk; ++i) iteration();
+        });
+        if (s) return s;
+      }
+      for (; done + chunk <= iters; done += chunk) CRV_HIP(hipGraphLaunch(g_train, st));
+    }
+    for (; done < iters; ++done) iteration();
     crv_status s = check_launch();
     if (s) return s;
     pretrained = true;
     return CRV_OK;
   }
 
+  // algorithm step 4: p = M^-1 int I_h(u) B
   void project_into_p() {
     forward();
     tb(CRV_K_PROJECT);
     launch_project<Real>(g, b.u, b.proj_val, b.bvec, st);
     te();
-    mass_solve(b.bvec);
-    hipMemcpyAsync(b.p, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
+    mass_solve(b.bvec, b.p);
   }
 
-  void substep(double tau) {
+  // algorithm step 5 (tau from b.tau): S <- M^-1 b(S, p)
+  void substep() {
     tb(CRV_K_ADS_ASSEMBLE);
     launch_ads_assemble<Real>(g, b.s, b.p, b.perm, b.poro, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
-                              tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, b.bvec, st);
+                              b.tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, b.bvec, st);
     te();
-    mass_solve(b.bvec);
-    hipMemcpyAsync(b.s, b.bvec, nc * sizeof(Real), hipMemcpyDeviceToDevice, st);
+    mass_solve(b.bvec, b.s);
+  }
+
+  void step_body() {
+    project_into_p();
+    for (int k = 0; k < cfg.substeps; ++k) substep();
+    launch_check_finite<Real>(b.s, nc, b.flag, st);
+    refresh();
+    for (int i = 0; i < cfg.adam_iters; ++i) iteration();
+  }
+
+  crv_status set_tau(double tau) {
+    // the host value lives until the copy is done: stream-ordered, then synchronised
+    static thread_local double host_tau;
+    host_tau = tau;
+    CRV_HIP(hipMemcpyAsync(b.tau, &host_tau, sizeof(double), hipMemcpyHostToDevice, st));
+    CRV_HIP(hipStreamSynchronize(st));
+    return CRV_OK;
   }
 
   crv_status step(double dt) override {
     if (!(dt > 0) || !std::isfinite(dt)) return fail(CRV_EINVAL, "dt must be > 0");
-    project_into_p();
-    const double tau = dt / cfg.substeps;
-    for (int k = 0; k < cfg.substeps; ++k) substep(tau);
-    launch_check_finite<Real>(b.s, nc, b.flag, st);
-    refresh();
-    for (int i = 0; i < cfg.adam_iters; ++i) iteration();
+    crv_status s = set_tau(dt / cfg.substeps);
+    if (s) return s;
+    if (use_graphs()) {
+      if (!g_step) {
+        s = capture(&g_step, [&] { step_body(); });
+        if (s) return s;
+      }
+      CRV_HIP(hipGraphLaunch(g_step, st));
+    } else {
+      step_body();
+    }
     return check_launch();
   }
 
   crv_status substeps(double tau, int n) override {
     if (!(tau > 0) || !std::isfinite(tau) || n < 0) return fail(CRV_EINVAL, "bad tau or count");
+    crv_status s = set_tau(tau);
+    if (s) return s;
     project_into_p();
-    for (int k = 0; k < n; ++k) substep(tau);
+    for (int k = 0; k < n; ++k) substep();
     launch_check_finite<Real>(b.s, nc, b.flag, st);
     refresh();
-    crv_status s = check_launch();
+    s = check_launch();
     if (s) return s;
     return sync_and_check();
   }
@@ -630,7 +699,7 @@ struct Solver : SolverBase {
   crv_status mass_solve_host(const double* bin, double* x) override {
     crv_status s = upload(b.bvec, bin, nc);
     if (s) return s;
-    mass_solve(b.bvec);
+    mass_solve(b.bvec, b.bvec);
     if ((s = check_launch())) return s;
     return download(x, b.bvec, nc);
   }
