@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3", "fp64"])
     ap.add_argument("--workload", default="b512")
     ap.add_argument("--pretrain", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -164,9 +164,9 @@ def main():
             amount, unit = work
             if unit == "flop":
                 peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"],
-                        "fp64": PEAK["fp64_tflops"]}[args.precision]
+                        "bf16x3": PEAK["bf16_tflops"], "fp64": PEAK["fp64_tflops"]}[args.precision]
                 achieved = amount / (us * 1e-6) / 1e12
-                bound = "mfma" if args.precision == "bf16" else "alu"
+                bound = "alu" if args.precision == "fp64" else "mfma"
                 roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                             "work_per_launch": amount, "us_per_launch": us}
@@ -191,7 +191,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16 (network) / f32", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16 (network) / f32", "bf16x3": "bf16x3 (network) / f32",
+                  "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: 2D {prob.n_elem}^2 quadratic elements, "
                                f"{prob.n_elem + 1}^2 nodes, MLP 2->{prob.hidden}x{prob.width}->1, "

@@ -65,17 +65,23 @@ typedef enum {
 } crv_status;
 
 typedef enum {
-  CRV_PREC_FP32 = 0, /* fields, solves and network in float32 */
-  CRV_PREC_BF16 = 1, /* network products in bf16 on MFMA, float32 accumulate;
-                        everything else float32 */
-  CRV_PREC_FP64 = 2  /* everything in float64 (verification mode) */
+  CRV_PREC_FP32 = 0,   /* fields, solves and network in float32 (network on
+                          fp32 MFMA where the shape allows) */
+  CRV_PREC_BF16 = 1,   /* hidden-layer products on bf16 MFMA, float32
+                          accumulate; everything else float32 */
+  CRV_PREC_FP64 = 2,   /* everything in float64 (verification mode) */
+  CRV_PREC_BF16X3 = 3  /* hidden-layer products as three bf16 MFMAs on
+                          hi/lo-split operands (about 2^-16 relative error),
+                          float32 accumulate; everything else float32 */
 } crv_precision;
 
 typedef struct {
   int dim;              /* 2 or 3 */
   int n_elem;           /* Ne per axis, 4 <= Ne <= 1024 (3D: <= 256) */
   int degree;           /* B-spline degree r: 1, 2 or 3 */
-  int width;            /* hidden width: 16, 32, 64 or 128 */
+  int width;            /* hidden width: 16, 32, 64 or 128 (bf16 / bf16x3
+                           network paths: 32 or 64, bf16 also 128; 3 or 4
+                           hidden layers) */
   int hidden;           /* number of tanh hidden layers, 1..8 */
   int precision;        /* crv_precision */
   double mu_w, mu_g;    /* brine and gas viscosities */

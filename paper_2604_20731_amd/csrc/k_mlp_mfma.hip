@@ -1,6 +1,14 @@
-// Matrix-core (MFMA) formulation of the pressure network u = m NN_theta(2x-1)
-// for float32 (v_mfma_f32_32x32x2f32) and bf16 (v_mfma_f32_32x32x16_bf16,
-// float32 accumulate).
+// Matrix-core (MFMA) formulation of the pressure network u = m NN_theta(2x-1).
+//
+// Three arithmetic modes for the hidden-to-hidden products (float32
+// accumulation in all of them):
+//   F32   v_mfma_f32_32x32x2f32 on float32 operands;
+//   BF16  v_mfma_f32_32x32x16_bf16 on bf16-rounded operands;
+//   X3    split bf16: every operand a = a_hi + a_lo with a_hi = bf16(a),
+//         a_lo = bf16(a - a_hi), and a.b ~ a_hi.b_hi + a_hi.b_lo + a_lo.b_hi
+//         (three bf16 MFMAs, about 2^-16 relative error per product).
+// The first layer (K = d) and the output (N = 1) run on the vector ALUs in
+// float32, as do tanh and its derivative.
 //
 // Layout.  Activations are kept transposed, features x nodes, in 32 x 32
 // accumulator tiles: a wavefront owns 32 nodes (one per lane column) and lane
@@ -10,19 +18,18 @@
 // next layer's product: K-step ks takes the lane's registers
 // ks*S .. ks*S+S-1 (S = 8 for bf16, 1 for fp32), so the contraction index
 // runs over features in a lane-dependent order.  That order is folded into
-// the packed weight fragments (k_pack_fragments), so no data moves between
-// layers.  Bias is added by initialising the accumulators with it; tanh is
-// applied in float32 on the vector ALUs.
+// the packed weight fragments, so no data moves between layers.  Bias is
+// added by initialising the accumulators with it.
 //
 // Backward.  delta_{l-1} = (W_l^T delta_l) (1 - h_{l-1}^2) uses the same
-// register chain with transposed fragments.  The weight gradient
-// dW_l = sum_nodes delta_l h_{l-1}^T contracts over nodes: the waves of a
-// block write delta_l and h_{l-1} of their tiles transposed into LDS, and each
-// wave accumulates its share of the dW_l output tiles with MFMAs over the
-// block's nodes.  Accumulators persist in registers across the block's
-// node tiles; each block writes one partial gradient row at the end, reduced
-// in a fixed order afterwards.  Small gradients (biases, first and last
-// layer) are summed per thread from LDS.
+// register chain with transposed fragments.  dW_l = sum_nodes delta_l
+// h_{l-1}^T contracts over nodes: the waves of a block write delta_l
+// transposed into LDS next to the recomputed activations (also transposed),
+// and each wave accumulates its share of the dW_l output tiles with MFMAs
+// over the block's nodes.  Biases, first-layer and output weights are summed
+// over nodes inside registers by butterfly reduce-scatters across the 32 node
+// lanes.  All accumulators persist across the block's node tiles; each block
+// writes one partial gradient row, reduced in a fixed order afterwards.
 #include <algorithm>
 
 #include "kernels.h"
@@ -31,44 +38,99 @@ namespace crv {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-template <bool BF16>
+template <int M>
 struct MM;
 
 template <>
-struct MM<true> {
-  static constexpr int S = 8;    // operand values per lane
-  static constexpr int KS = 16;  // contraction length per instruction
-  using elem = __bf16;
+struct MM<NET_F32> {
+  static constexpr int S = 1, KS = 2, NP = 1;  // values per lane, K per MFMA, fragment planes
+  using felem = float;                          // fragment storage
+  using lelem = float;                          // LDS storage of activations / deltas
+  static constexpr int PAD = 1;
+  using op = float;
+  __device__ static inline f32x16_t mma(op a, op b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline op frag(const felem* p) { return *p; }
+  __device__ static inline op lds(const lelem* p) { return *p; }
+  __device__ static inline op from(const float* v) { return v[0]; }
+  __device__ static inline void put(felem* p, float w) { p[0] = w; }
+};
+
+template <>
+struct MM<NET_BF16> {
+  static constexpr int S = 8, KS = 16, NP = 1;
+  using felem = __bf16;
+  using lelem = __bf16;
+  static constexpr int PAD = 8;
   using op = bf16x8_t;
   __device__ static inline f32x16_t mma(op a, op b, f32x16_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
-  __device__ static inline op load(const elem* p) { return *reinterpret_cast<const op*>(p); }
+  __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
+  __device__ static inline op lds(const lelem* p) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline op from(const float* v) {
     op o;
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[k] = (__bf16)v[k];
     return o;
   }
+  __device__ static inline void put(felem* p, float w) { p[0] = (__bf16)w; }
+};
+
+struct SplitOp {
+  bf16x8_t h, l;
 };
 
 template <>
-struct MM<false> {
-  static constexpr int S = 1;
-  static constexpr int KS = 2;
-  using elem = float;
-  using op = float;
-  __device__ static inline f32x16_t mma(op a, op b, f32x16_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+struct MM<NET_X3> {
+  static constexpr int S = 8, KS = 16, NP = 2;
+  using felem = __bf16;
+  using lelem = float;
+  static constexpr int PAD = 4;
+  using op = SplitOp;
+  __device__ static inline f32x16_t mma(const op& a, const op& b, f32x16_t c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h, b.l, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h, b.h, c, 0, 0, 0);
   }
-  __device__ static inline op load(const elem* p) { return *p; }
-  __device__ static inline op from(const float* v) { return v[0]; }
+  // fragments hold the hi plane, then (64*S further) the lo plane
+  __device__ static inline op frag(const felem* p) {
+    return op{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + 64 * S)};
+  }
+  __device__ static inline op from(const float* v) {
+    op o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const __bf16 h = (__bf16)v[k];
+      o.h[k] = h;
+      o.l[k] = (__bf16)(v[k] - float(h));
+    }
+    return o;
+  }
+  __device__ static inline op lds(const lelem* p) {
+    const f32x4_t a = *reinterpret_cast<const f32x4_t*>(p);
+    const f32x4_t b = *reinterpret_cast<const f32x4_t*>(p + 4);
+    const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    return from(v);
+  }
+  __device__ static inline void put(felem* p, float w) {
+    const __bf16 h = (__bf16)w;
+    p[0] = h;
+    p[64 * S] = (__bf16)(w - float(h));
+  }
 };
 
 // feature held by lane group g in its flat accumulator register t (t = 16 mb + i)
 __host__ __device__ inline int cfeat(int t, int g) {
   return 32 * (t >> 4) + 8 * ((t & 15) >> 2) + 4 * g + (t & 3);
+}
+// inverse: register t and lane group g holding feature f
+__host__ __device__ inline void cfeat_inv(int f, int* t, int* g) {
+  *g = (f >> 2) & 1;
+  *t = 16 * (f >> 5) + 4 * ((f & 31) >> 3) + (f & 3);
 }
 
 __host__ __device__ inline int64_t off_layer(int l, int dim, int W) {
@@ -76,19 +138,22 @@ __host__ __device__ inline int64_t off_layer(int l, int dim, int W) {
   return l == 1 ? 0 : int64_t(W) * dim + W + int64_t(l - 2) * (int64_t(W) * W + W);
 }
 
-// ---------------------------------------------------------------------------
 // Packed fragments: for hidden-to-hidden layer hl (layer l = hl + 2), block mb
-// and K-step ks, lane (r = lane%32, g = lane/32) holds S consecutive values:
+// and K-step ks, lane (r = lane%32, g = lane/32) holds S consecutive values
 //   forward  (dir 0): W_l[32 mb + r][cfeat(ks*S + v, g)]
 //   backward (dir 1): W_l[cfeat(ks*S + v, g)][32 mb + r]      (= W_l^T)
-// index (((hl*2 + dir) * (W/32) + mb) * (W/KS) + ks) * 64*S + lane*S + v.
-// ---------------------------------------------------------------------------
-template <bool BF16>
+// at (((hl*2 + dir) * (W/32) + mb) * (W/KS) + ks) * NP*64*S + plane*64*S + lane*S + v.
+template <int MODE>
+__host__ __device__ inline int64_t frag_index(int hl, int dir, int mb, int ks, int lane, int v, int W) {
+  using T = MM<MODE>;
+  return (((((int64_t(hl) * 2 + dir) * (W / 32) + mb) * (W / T::KS) + ks) * T::NP) * 64 + lane) * T::S + v;
+}
+
+template <int MODE>
 __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, int hidden,
-                                 typename MM<BF16>::elem* __restrict__ frag) {
-  using T = MM<BF16>;
-  const int64_t per_layer = 2 * int64_t(W) * W;
-  const int64_t total = per_layer * (hidden - 1);
+                                 typename MM<MODE>::felem* __restrict__ frag) {
+  using T = MM<MODE>;
+  const int64_t total = 2 * int64_t(W) * W * (hidden - 1);
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int v = int(idx % T::S);
@@ -106,7 +171,7 @@ __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, i
   const int k = cfeat(ks * T::S + v, g);     // contraction feature
   const float* Wl = th + off_layer(hl + 2, dim, W);
   const float w = dir == 0 ? Wl[int64_t(a) * W + k] : Wl[int64_t(k) * W + a];
-  frag[idx] = typename MM<BF16>::elem(w);
+  T::put(frag + frag_index<MODE>(hl, dir, mb, ks, lane, v, W), w);
 }
 
 template <int DIM>
@@ -143,25 +208,21 @@ struct Small {
   }
 };
 
-// Forward of one 32-node tile held by this wave.  Every hidden layer's
-// activations (accumulator layout, float32) are handed to sink(l, h) as soon
-// as they are computed; on return h holds the last hidden layer.
 struct NoSink {
   template <typename H>
   __device__ void operator()(int, const H&) const {}
 };
 
-template <int W, int L, bool BF16, int DIM, typename Sink>
-__device__ inline void forward_tile(const float* sp,
-                                    const typename MM<BF16>::elem* __restrict__ frag,
+// Forward of one 32-node tile held by this wave.  Hidden layer l's
+// activations (accumulator layout, float32) go to sink(l, h) as soon as they
+// are computed; on return h holds the last hidden layer.
+template <int W, int L, int MODE, int DIM, typename Sink>
+__device__ inline void forward_tile(const float* sp, const typename MM<MODE>::felem* __restrict__ frag,
                                     const float* z, int g, int lane, float (&h)[W / 2],
                                     const Sink& sink) {
-  using T = MM<BF16>;
+  using T = MM<MODE>;
   using SM = Small<W, L, DIM>;
-  constexpr int NR = W / 2;          // accumulator registers per lane
-  constexpr int NKS = W / T::KS;     // K-steps per layer
-  constexpr int NMB = W / 32;
-  // layer 1 on the vector ALUs (K = DIM)
+  constexpr int NR = W / 2, NKS = W / T::KS, NMB = W / 32;
   {
     const float* W1 = sp + SM::W1;
     const float* b1 = sp + SM::B1;
@@ -186,22 +247,20 @@ __device__ inline void forward_tile(const float* sp,
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[mb][i] = bl[cfeat(mb * 16 + i, g)];
-    const typename T::elem* fl = frag + int64_t((l - 1) * 2 + 0) * NMB * NKS * 64 * T::S;
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
-        acc[mb] = T::mma(T::load(fl + (int64_t(mb) * NKS + ks) * 64 * T::S + lane * T::S), bop[ks],
-                         acc[mb]);
+        acc[mb] = T::mma(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
 #pragma unroll
     for (int t = 0; t < NR; ++t) h[t] = tanh_fast(acc[t >> 4][t & 15]);
     sink(l, h);
   }
 }
 
-template <int W, int L, bool BF16, int DIM>
+template <int W, int L, int MODE, int DIM>
 __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __restrict__ th,
-                                                      const typename MM<BF16>::elem* __restrict__ frag,
+                                                      const typename MM<MODE>::felem* __restrict__ frag,
                                                       float* __restrict__ u, long long* t_bump) {
   constexpr int NR = W / 2;
   using SM = Small<W, L, DIM>;
@@ -220,7 +279,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
   else
     for (int c = 0; c < DIM; ++c) z[c] = 0.f;
   float h[NR];
-  forward_tile<W, L, BF16, DIM>(sp, frag, z, g, lane, h, NoSink());
+  forward_tile<W, L, MODE, DIM>(sp, frag, z, g, lane, h, NoSink());
   const float* wo = sp + SM::WO;
   float s = 0.f;
 #pragma unroll
@@ -230,43 +289,46 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// Backward.  Block = NW waves, a block step covers NB = 32*NW nodes.  The
-// recomputed activations of every hidden layer go to LDS transposed
-// (Hall[l][feature][node]); that copy is the B operand of the dW products
-// and the source of the tanh derivative, so only one layer is live in
-// registers at a time.
+// Backward.  Block = NW waves, a block step covers NB = 32*NW nodes.
+// Hall[l][feature][node] holds the recomputed activations of hidden layers
+// 1..L-1 (the B operands of dW_2..dW_L and the source of the derivative);
+// the last layer stays in registers and passes through Dt once for the
+// output-weight gradient.  Biases, first-layer and output weights are summed
+// over nodes per thread from LDS: thread t owns feature t/4 (+ multiples of
+// NTH/4) and a quarter of the block's nodes.
 // ---------------------------------------------------------------------------
-template <int W, int L, bool BF16, int DIM, int NW>
+template <int W, int L, int MODE, int DIM, int NW>
 __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
                                                           const float* __restrict__ th,
-                                                          const typename MM<BF16>::elem* __restrict__ frag,
+                                                          const typename MM<MODE>::felem* __restrict__ frag,
                                                           const float* __restrict__ gu,
                                                           float* __restrict__ partials) {
-  using T = MM<BF16>;
-  using E = typename T::elem;
+  using T = MM<MODE>;
+  using E = typename T::lelem;
+  using SM = Small<W, L, DIM>;
   constexpr int NR = W / 2, NKS = W / T::KS, NMB = W / 32;
   constexpr int NB = 32 * NW;                 // nodes per block step
-  constexpr int PAD = BF16 ? 8 : 1;
-  constexpr int LD = NB + PAD;                // row pitch of the transposed buffers
+  constexpr int LD = NB + T::PAD;             // row pitch of the transposed buffers
   constexpr int NOB = NMB * NMB;              // 32x32 output tiles of one dW_l
   constexpr int OWN = (NOB + NW - 1) / NW;    // tiles owned by each wave
   constexpr int NTH = 64 * NW;
-  constexpr int FPT = (W * 4 + NTH - 1) / NTH;  // features per thread (4 quarters per feature)
+  constexpr int FPT = (W * 4 + NTH - 1) / NTH;  // features per thread
   constexpr int QN = NB / 4;                  // nodes per quarter
-  __shared__ __attribute__((aligned(16))) E Hall[L * W * LD];
+  __shared__ __attribute__((aligned(16))) E Hall[(L - 1) * W * LD];
   __shared__ __attribute__((aligned(16))) E Dt[W * LD];
+  __shared__ float sp[SM::SIZE];
   __shared__ float Gs[NB];
   __shared__ float Zs[DIM][NB];
   __shared__ float Red[NTH];
-  using SM = Small<W, L, DIM>;
-  __shared__ float sp[SM::SIZE];
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 5, n = lane & 31;
   const int col = w * 32 + n;  // this lane's node column in the block step
+  const int q = tid & 3;
   SM::stage(th, sp, tid, NTH);
   __syncthreads();
   const int64_t total = ipow(geo.n, DIM);
   const int64_t nsteps = (total + NB - 1) / NB;
+  const float* wo = sp + SM::WO;
 
   f32x16_t acc[L - 1][OWN];
 #pragma unroll
@@ -275,7 +337,6 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     for (int o = 0; o < OWN; ++o)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][o][i] = 0.f;
-  // per-thread small gradients: feature fq = tid/4 + f*(NTH/4), node quarter tid%4
   float s_wout[FPT], s_b[L][FPT], s_w1[DIM][FPT], s_bout = 0.f;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -285,11 +346,10 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
 #pragma unroll
     for (int c = 0; c < DIM; ++c) s_w1[c][f] = 0.f;
   }
-  const int q = tid & 3;
-  const float* wo = sp + SM::WO;
   auto sink = [&](int l, const float(&hv)[NR]) {
+    if (l < L - 1)
 #pragma unroll
-    for (int t = 0; t < NR; ++t) Hall[(l * W + cfeat(t, g)) * LD + col] = E(hv[t]);
+      for (int t = 0; t < NR; ++t) Hall[(l * W + cfeat(t, g)) * LD + col] = E(hv[t]);
   };
 
   for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
@@ -301,23 +361,26 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     float d[NR];
-    forward_tile<W, L, BF16, DIM>(sp, frag, z, g, lane, d, sink);
+    forward_tile<W, L, MODE, DIM>(sp, frag, z, g, lane, d, sink);
     const float gv = valid ? gu[p] : 0.f;
     if (g == 0) {
       Gs[col] = gv;
 #pragma unroll
       for (int c = 0; c < DIM; ++c) Zs[c][col] = z[c];
     }
-    // delta of the last hidden layer: g w_out (1 - h_L^2), h_L still in d
+    // h_L through Dt for the output layer; then delta_L = g w_out (1 - h_L^2)
 #pragma unroll
-    for (int t = 0; t < NR; ++t) d[t] = gv * wo[cfeat(t, g)] * (1.f - d[t] * d[t]);
+    for (int t = 0; t < NR; ++t) {
+      const int f = cfeat(t, g);
+      Dt[f * LD + col] = E(d[t]);
+      d[t] = gv * wo[f] * (1.f - d[t] * d[t]);
+    }
     __syncthreads();
-    // output layer: dW_out[f] = sum_n g_n h_L[f][n], db_out = sum_n g_n
 #pragma unroll
     for (int f = 0; f < FPT; ++f) {
       const int fq = (tid >> 2) + f * (NTH / 4);
       if (fq < W) {
-        const E* hr = Hall + ((L - 1) * W + fq) * LD + q * QN;
+        const E* hr = Dt + fq * LD + q * QN;
         float s = 0.f;
         for (int k = 0; k < QN; ++k) s += float(hr[k]) * Gs[q * QN + k];
         s_wout[f] += s;
@@ -328,9 +391,9 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
       for (int k = 0; k < QN; ++k) s += Gs[tid * QN + k];
       s_bout += s;
     }
+    __syncthreads();
 #pragma unroll
     for (int l = L; l >= 1; --l) {
-      // delta_l transposed into LDS
 #pragma unroll
       for (int t = 0; t < NR; ++t) Dt[cfeat(t, g) * LD + col] = E(d[t]);
       __syncthreads();
@@ -345,11 +408,11 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
             const E* brow = Hall + ((l - 2) * W + ib * 32 + n) * LD + T::S * g;
 #pragma unroll
             for (int ks = 0; ks < NB / T::KS; ++ks)
-              acc[l - 2][o] = T::mma(T::load(arow + ks * T::KS), T::load(brow + ks * T::KS),
-                                     acc[l - 2][o]);
+              acc[l - 2][o] = T::mma(T::lds(arow + ks * T::KS), T::lds(brow + ks * T::KS), acc[l - 2][o]);
           }
         }
       }
+      // db_l[f] = sum_n delta_l[f][n]; layer 1 also dW_1[f][c] = sum_n delta_1[f][n] z_c[n]
 #pragma unroll
       for (int f = 0; f < FPT; ++f) {
         const int fq = (tid >> 2) + f * (NTH / 4);
@@ -377,7 +440,6 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
         typename T::op bop[NKS];
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&d[ks * T::S]);
-        const E* fl = frag + int64_t((l - 2) * 2 + 1) * NMB * NKS * 64 * T::S;
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
           f32x16_t c2;
@@ -385,7 +447,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
           for (int i = 0; i < 16; ++i) c2[i] = 0.f;
 #pragma unroll
           for (int ks = 0; ks < NKS; ++ks)
-            c2 = T::mma(T::load(fl + (int64_t(mb) * NKS + ks) * 64 * T::S + lane * T::S), bop[ks], c2);
+            c2 = T::mma(T::frag(frag + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const float hv = float(Hall[((l - 2) * W + cfeat(mb * 16 + i, g)) * LD + col]);
@@ -393,11 +455,11 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
           }
         }
       }
-      __syncthreads();
+      __syncthreads();  // Dt (and Hall in the next step) are rewritten
     }
   }
 
-  // ---- write this block's partial gradient row ----
+  // ---- this block's partial gradient row ----
   float* row = partials + int64_t(blockIdx.x) * P;
 #pragma unroll
   for (int l = 2; l <= L; ++l) {
@@ -410,17 +472,16 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int orow = ob * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-          const int icol = ib * 32 + n;
-          row[off + int64_t(orow) * W + icol] = acc[l - 2][o][i];
+          row[off + int64_t(orow) * W + ib * 32 + n] = acc[l - 2][o][i];
         }
       }
     }
   }
-  // small gradients: reduce the four quarters of each feature through LDS
+  // small gradients: add the four node quarters of each feature through LDS
   auto reduce4 = [&](float v, int64_t dst, bool ok) {
     Red[tid] = v;
     __syncthreads();
-    if (ok && q == 0) row[dst] = Red[tid] + Red[tid + 1] + Red[tid + 2] + Red[tid + 3];
+    if (ok && q == 0) row[dst] = ((Red[tid] + Red[tid + 1]) + Red[tid + 2]) + Red[tid + 3];
     __syncthreads();
   };
 #pragma unroll
@@ -436,40 +497,32 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
 #pragma unroll
     for (int c = 0; c < DIM; ++c) reduce4(s_w1[c][f], int64_t(fq) * DIM + c, ok);
   }
-  // threads 0..3 each summed one quarter of g: combine them for the output bias
-  Red[tid] = (tid < 4) ? s_bout : 0.f;
+  Red[tid] = (tid < 4) ? s_bout : 0.f;  // threads 0..3 summed one node quarter of g each
   __syncthreads();
-  if (tid == 0) row[off_layer(L + 1, DIM, W) + W] = Red[0] + Red[1] + Red[2] + Red[3];
+  if (tid == 0) row[off_layer(L + 1, DIM, W) + W] = ((Red[0] + Red[1]) + Red[2]) + Red[3];
 }
 
 // ---------------------------------------------------------------------------
 // Fused gradient reduction + Adam + fragment update.  Block = 4 waves over
 // 64 parameters (one per lane); wave w sums partial rows w, w+4, ... and the
 // four wave sums are added in a fixed order.  The updated weight of a
-// hidden-to-hidden layer is written straight into its two fragment slots
-// (the inverse of the k_pack_fragments map).
+// hidden-to-hidden layer is written straight into its two fragment slots.
+// One extra block sums the iteration's loss partials.
 // ---------------------------------------------------------------------------
-// flat accumulator register t and lane group g holding feature f (cfeat inverse)
-__device__ inline void cfeat_inv(int f, int* t, int* g) {
-  *g = (f >> 2) & 1;
-  *t = 16 * (f >> 5) + 4 * ((f & 31) >> 3) + (f & 3);
-}
-
-template <bool BF16>
+template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce_adam_pack(
     const float* __restrict__ part, int rows, int64_t P, float* __restrict__ th,
     float* __restrict__ m, float* __restrict__ v, double lr, double b1, double b2, double eps,
     const long long* __restrict__ t_dev, int dim, int W, int hidden,
-    typename MM<BF16>::elem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
+    typename MM<MODE>::felem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
     double* __restrict__ hist, int cap) {
-  using T = MM<BF16>;
+  using T = MM<MODE>;
   __shared__ float red[4][64];
   if (blockIdx.x == gridDim.x - 1) {
-    // the extra block: loss of this iteration (fixed-order sum of the partials)
     __shared__ double lb[256];
-    double v = 0;
-    for (int k = threadIdx.x; k < loss_np; k += 256) v += double(loss_part[k]);
-    const double tot = block_sum(v, lb);
+    double s = 0;
+    for (int k = threadIdx.x; k < loss_np; k += 256) s += double(loss_part[k]);
+    const double tot = block_sum(s, lb);
     if (threadIdx.x == 0) hist[(*t_dev - 1) % cap] = tot;
     return;
   }
@@ -500,7 +553,6 @@ __global__ __launch_bounds__(256) void k_reduce_adam_pack(
   v[p] = vv;
   const float nw = th[p] - float(lr) * (mm / c1) / (sqrtf(vv / c2) + float(eps));
   th[p] = nw;
-  if (frag == nullptr) return;
   // hidden-to-hidden weight? layer l = 2..hidden occupies [off_l, off_l + W*W)
   const int64_t base = int64_t(W) * dim + W;
   if (p < base) return;
@@ -509,109 +561,105 @@ __global__ __launch_bounds__(256) void k_reduce_adam_pack(
   const int64_t within = rel % per;
   if (hl >= hidden - 1 || within >= int64_t(W) * W) return;
   const int o = int(within / W), i = int(within % W);
-  const int nks = W / T::KS, nmb = W / 32;
-  const typename MM<BF16>::elem e = typename MM<BF16>::elem(nw);
   int tt, g;
-  // forward fragment: row o, contraction feature i
-  cfeat_inv(i, &tt, &g);
-  {
-    const int ks = tt / T::S, vv2 = tt % T::S, mb = o >> 5, lanei = (o & 31) + 32 * g;
-    frag[((((int64_t(hl) * 2 + 0) * nmb + mb) * nks + ks) * 64 + lanei) * T::S + vv2] = e;
-  }
-  // backward (transposed) fragment: row i, contraction feature o
-  cfeat_inv(o, &tt, &g);
-  {
-    const int ks = tt / T::S, vv2 = tt % T::S, mb = i >> 5, lanei = (i & 31) + 32 * g;
-    frag[((((int64_t(hl) * 2 + 1) * nmb + mb) * nks + ks) * 64 + lanei) * T::S + vv2] = e;
-  }
+  cfeat_inv(i, &tt, &g);  // forward fragment: row o, contraction feature i
+  T::put(frag + frag_index<MODE>(hl, 0, o >> 5, tt / T::S, (o & 31) + 32 * g, tt % T::S, W), nw);
+  cfeat_inv(o, &tt, &g);  // backward fragment: row i, contraction feature o
+  T::put(frag + frag_index<MODE>(hl, 1, i >> 5, tt / T::S, (i & 31) + 32 * g, tt % T::S, W), nw);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+bool mlp_mfma_supported(int dim, int width, int hidden, int mode) {
+  if (dim != 2) return false;
+  if (!(hidden == 3 || hidden == 4)) return false;
+  if (mode == NET_BF16) return width == 32 || width == 64 || width == 128;
+  return width == 32 || width == 64;
+}
+
+int64_t mlp_fragment_bytes(int width, int hidden) {
+  return 2 * int64_t(width) * width * (hidden - 1) * 4;  // float32, or a bf16 hi/lo pair
+}
+
+void launch_pack_fragments(const float* theta, int dim, int width, int hidden, int mode,
+                           void* frag, hipStream_t st) {
+  const int64_t total = 2 * int64_t(width) * width * (hidden - 1);
+  if (total <= 0) return;
+  const int blocks = cdiv(total, 256);
+  if (mode == NET_F32)
+    k_pack_fragments<NET_F32><<<blocks, 256, 0, st>>>(theta, dim, width, hidden, static_cast<float*>(frag));
+  else if (mode == NET_BF16)
+    k_pack_fragments<NET_BF16><<<blocks, 256, 0, st>>>(theta, dim, width, hidden, static_cast<__bf16*>(frag));
+  else
+    k_pack_fragments<NET_X3><<<blocks, 256, 0, st>>>(theta, dim, width, hidden, static_cast<__bf16*>(frag));
 }
 
 void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
                              float* v, double lr, double b1, double b2, double eps,
-                             const long long* t_dev, int dim, int width, int hidden, bool bf16,
+                             const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
                              int cap, hipStream_t st) {
   const int blocks = cdiv(P, 64) + 1;
-  if (bf16)
-    k_reduce_adam_pack<true><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps,
-                                                     t_dev, dim, width, hidden,
-                                                     static_cast<__bf16*>(frag), loss_part, loss_np,
-                                                     loss_hist, cap);
-  else
-    k_reduce_adam_pack<false><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps,
-                                                      t_dev, dim, width, hidden,
-                                                      static_cast<float*>(frag), loss_part, loss_np,
-                                                      loss_hist, cap);
+#define CRV_RA(MM_, TT)                                                                           \
+  k_reduce_adam_pack<MM_><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps, \
+                                                  t_dev, dim, width, hidden, static_cast<TT*>(frag), \
+                                                  loss_part, loss_np, loss_hist, cap)
+  if (mode == NET_F32) CRV_RA(NET_F32, float);
+  else if (mode == NET_BF16) CRV_RA(NET_BF16, __bf16);
+  else CRV_RA(NET_X3, __bf16);
+#undef CRV_RA
 }
 
-// ---------------------------------------------------------------------------
-bool mlp_mfma_supported(int dim, int width, int hidden, bool bf16) {
-  if (dim != 2) return false;
-  if (!(hidden == 3 || hidden == 4)) return false;
-  (void)bf16;
-  return width == 32 || width == 64;
-}
-
-int64_t mlp_fragment_elems(int width, int hidden) { return 2 * int64_t(width) * width * (hidden - 1); }
-
-void launch_pack_fragments(const float* theta, int dim, int width, int hidden, bool bf16,
-                           void* frag, hipStream_t st) {
-  const int64_t total = mlp_fragment_elems(width, hidden);
-  if (total <= 0) return;
-  if (bf16)
-    k_pack_fragments<true><<<cdiv(total, 256), 256, 0, st>>>(theta, dim, width, hidden,
-                                                             static_cast<__bf16*>(frag));
-  else
-    k_pack_fragments<false><<<cdiv(total, 256), 256, 0, st>>>(theta, dim, width, hidden,
-                                                              static_cast<float*>(frag));
-}
-
-template <int W, int L, bool BF16>
+template <int W, int L, int MODE>
 static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, long long* tb,
                      hipStream_t st) {
   const int64_t total = ipow(g.n, 2);
   const int64_t tiles = (total + 31) / 32;
-  k_mlp_fwd_mfma<W, L, BF16, 2><<<cdiv(tiles, 4), 256, 0, st>>>(
-      g, th, static_cast<const typename MM<BF16>::elem*>(frag), u, tb);
+  k_mlp_fwd_mfma<W, L, MODE, 2><<<cdiv(tiles, 4), 256, 0, st>>>(
+      g, th, static_cast<const typename MM<MODE>::felem*>(frag), u, tb);
 }
 
-void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, bool bf16, const float* theta,
+#define CRV_FOR_SHAPES(X)                                                                    \
+  X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
+  X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
+  X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
+  X(32, 3, NET_X3) X(64, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)
+
+void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
                              const void* frag, float* u, long long* t_bump, hipStream_t st) {
-#define CRV_FW(WW, LL, BB) \
-  if (width == WW && hidden == LL && bf16 == BB) return fwd_inst<WW, LL, BB>(g, theta, frag, u, t_bump, st);
-  CRV_FW(32, 3, true) CRV_FW(64, 3, true)
-  CRV_FW(32, 4, true) CRV_FW(64, 4, true)
-  CRV_FW(32, 3, false) CRV_FW(64, 3, false) CRV_FW(32, 4, false) CRV_FW(64, 4, false)
+#define CRV_FW(WW, LL, MM_) \
+  if (width == WW && hidden == LL && mode == MM_) return fwd_inst<WW, LL, MM_>(g, theta, frag, u, t_bump, st);
+  CRV_FOR_SHAPES(CRV_FW)
 #undef CRV_FW
 }
 
-// waves per backward block: bf16 activations fit 4 waves' worth of nodes in
-// LDS, float32 ones 2
-constexpr int bwd_nw(bool bf16) { return bf16 ? 4 : 2; }
+// waves per backward block: bf16 activations let 4 waves' worth of nodes fit
+// in LDS, float32-sized ones 2 (with two blocks per CU)
+constexpr int bwd_nw(int mode) { return 4; }
 
-int mlp_bwd_mfma_blocks(const Geom& g, bool bf16, int cu_count) {
+int mlp_bwd_mfma_blocks(const Geom& g, int mode, int cu_count) {
   const int64_t total = ipow(g.n, g.dim);
-  const int nb = 32 * bwd_nw(bf16);
+  const int nb = 32 * bwd_nw(mode);
+  const int per_cu = 1;
   const int64_t steps = (total + nb - 1) / nb;
-  return int(std::max<int64_t>(1, std::min<int64_t>(steps, cu_count)));
+  return int(std::max<int64_t>(1, std::min<int64_t>(steps, int64_t(cu_count) * per_cu)));
 }
 
-template <int W, int L, bool BF16>
+template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* gu,
                      float* partials, int blocks, hipStream_t st) {
-  constexpr int NW = bwd_nw(BF16);
-  k_mlp_bwd_mfma<W, L, BF16, 2, NW><<<blocks, 64 * NW, 0, st>>>(
-      g, P, th, static_cast<const typename MM<BF16>::elem*>(frag), gu, partials);
+  constexpr int NW = bwd_nw(MODE);
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(
+      g, P, th, static_cast<const typename MM<MODE>::felem*>(frag), gu, partials);
 }
 
-void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, bool bf16, int64_t P,
+void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
                               const float* theta, const void* frag, const float* gu,
                               float* partials, int blocks, hipStream_t st) {
-#define CRV_BW(WW, LL, BB) \
-  if (width == WW && hidden == LL && bf16 == BB) return bwd_inst<WW, LL, BB>(g, P, theta, frag, gu, partials, blocks, st);
-  CRV_BW(32, 3, true) CRV_BW(64, 3, true)
-  CRV_BW(32, 4, true) CRV_BW(64, 4, true)
-  CRV_BW(32, 3, false) CRV_BW(64, 3, false) CRV_BW(32, 4, false) CRV_BW(64, 4, false)
+#define CRV_BW(WW, LL, MM_) \
+  if (width == WW && hidden == LL && mode == MM_) return bwd_inst<WW, LL, MM_>(g, P, theta, frag, gu, partials, blocks, st);
+  CRV_FOR_SHAPES(CRV_BW)
 #undef CRV_BW
 }
 

@@ -113,23 +113,25 @@ void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double
                  hipStream_t st);
 
 // ---- network on matrix cores (k_mlp_mfma.hip), float32 parameters ----------
-bool mlp_mfma_supported(int dim, int width, int hidden, bool bf16);
-int64_t mlp_fragment_elems(int width, int hidden);
-// rearrange theta into the MFMA operand fragments (bf16 or float32)
-void launch_pack_fragments(const float* theta, int dim, int width, int hidden, bool bf16,
+// arithmetic of the hidden-to-hidden products
+enum NetMode : int { NET_F32 = 0, NET_BF16 = 1, NET_X3 = 2 };
+bool mlp_mfma_supported(int dim, int width, int hidden, int mode);
+int64_t mlp_fragment_bytes(int width, int hidden);
+// rearrange theta into the MFMA operand fragments of the mode
+void launch_pack_fragments(const float* theta, int dim, int width, int hidden, int mode,
                            void* frag, hipStream_t st);
-void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, bool bf16, const float* theta,
+void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
                              const void* frag, float* u, long long* t_bump, hipStream_t st);
-int mlp_bwd_mfma_blocks(const Geom& g, bool bf16, int cu_count);
-// fixed-order sum of the partial rows + Adam + fragment update (frag may be
-// null); one extra block sums the loss partials into loss_hist[(t-1) % cap]
-void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
-                             float* v, double lr, double b1, double b2, double eps,
-                             const long long* t_dev, int dim, int width, int hidden, bool bf16,
-                             void* frag, const float* loss_part, int loss_np, double* loss_hist,
-                             int cap, hipStream_t st);
-void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, bool bf16, int64_t P,
+int mlp_bwd_mfma_blocks(const Geom& g, int mode, int cu_count);
+void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
                               const float* theta, const void* frag, const float* gu,
                               float* partials, int blocks, hipStream_t st);
+// fixed-order sum of the partial rows + Adam + fragment update; one extra
+// block sums the loss partials into loss_hist[(t-1) % cap]
+void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
+                             float* v, double lr, double b1, double b2, double eps,
+                             const long long* t_dev, int dim, int width, int hidden, int mode,
+                             void* frag, const float* loss_part, int loss_np, double* loss_hist,
+                             int cap, hipStream_t st);
 
 }  // namespace crv

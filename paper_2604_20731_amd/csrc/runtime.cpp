@@ -90,11 +90,14 @@ struct Buffers {
   int loss_np;
 };
 
-constexpr int kMaxBwdBlocks = 256;  // persistent backward blocks (one per CU on MI355X)
+constexpr int kMaxCUs = 256;  // compute units sized for (MI355X); persistent grids use at most this
+
+static int net_mode(const crv_config& c) {
+  return c.precision == CRV_PREC_BF16 ? NET_BF16 : c.precision == CRV_PREC_BF16X3 ? NET_X3 : NET_F32;
+}
 
 static bool uses_mfma(const crv_config& c) {
-  return c.precision != CRV_PREC_FP64 &&
-         mlp_mfma_supported(c.dim, c.width, c.hidden, c.precision == CRV_PREC_BF16);
+  return c.precision != CRV_PREC_FP64 && mlp_mfma_supported(c.dim, c.width, c.hidden, net_mode(c));
 }
 
 template <typename Real>
@@ -142,9 +145,8 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.am = cv.take<Real>(P);
   b.av = cv.take<Real>(P);
   b.grad = cv.take<Real>(P);
-  b.frag = cv.take<float>(size_t(std::max<int64_t>(1, mlp_fragment_elems(c.width, c.hidden))));
-  b.bwd_rows = uses_mfma(c) ? std::min(kMaxBwdBlocks, mlp_bwd_mfma_blocks(g, c.precision == CRV_PREC_BF16,
-                                                                          kMaxBwdBlocks))
+  b.frag = cv.take<char>(size_t(std::max<int64_t>(4, mlp_fragment_bytes(c.width, c.hidden))));
+  b.bwd_rows = uses_mfma(c) ? mlp_bwd_mfma_blocks(g, net_mode(c), kMaxCUs)
                             : mlp_backward_rows(g, ms, int(sizeof(Real)));
   b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
@@ -167,10 +169,11 @@ static crv_status validate_config(const crv_config* c) {
   if (!(c->width == 16 || c->width == 32 || c->width == 64 || c->width == 128))
     return fail(CRV_EINVAL, "width must be 16, 32, 64 or 128");
   if (c->hidden < 1 || c->hidden > 8) return fail(CRV_EINVAL, "hidden must be in [1, 8]");
-  if (c->precision != CRV_PREC_FP32 && c->precision != CRV_PREC_FP64 && c->precision != CRV_PREC_BF16)
+  if (c->precision < CRV_PREC_FP32 || c->precision > CRV_PREC_BF16X3)
     return fail(CRV_EINVAL, "unknown precision");
-  if (c->precision == CRV_PREC_BF16 && !mlp_mfma_supported(c->dim, c->width, c->hidden, true))
-    return fail(CRV_EINVAL, "bf16 network path needs width 32 or 64 and 3 or 4 hidden layers");
+  if ((c->precision == CRV_PREC_BF16 || c->precision == CRV_PREC_BF16X3) &&
+      !mlp_mfma_supported(c->dim, c->width, c->hidden, net_mode(*c)))
+    return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 also 128) and 3 or 4 hidden layers");
   if (!(c->mu_w > 0) || !(c->mu_g > 0)) return fail(CRV_EINVAL, "viscosities must be > 0");
   if (!(c->relperm_exp >= 1)) return fail(CRV_EINVAL, "relperm_exp must be >= 1");
   if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) ||
@@ -251,7 +254,8 @@ struct Solver : SolverBase {
   Buffers<Real> b;
   MlpShape ms;
   size_t nn = 0, nc = 0;
-  bool mfma = false, bf16 = false;
+  bool mfma = false;
+  int mode = NET_F32;
   int bwd_blocks = 0;
 
   // -------- host <-> device helpers --------
@@ -294,12 +298,12 @@ struct Solver : SolverBase {
     nc = size_t(ipow(g.nb, g.dim));
     ms = MlpShape{cfg.dim, cfg.width, cfg.hidden, P};
     mfma = uses_mfma(cfg);
-    bf16 = cfg.precision == CRV_PREC_BF16;
+    mode = net_mode(cfg);
     if (mfma) {
-      int dev = 0, cus = kMaxBwdBlocks;
+      int dev = 0, cus = kMaxCUs;
       CRV_HIP(hipGetDevice(&dev));
       CRV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      bwd_blocks = std::min(b.bwd_rows, mlp_bwd_mfma_blocks(g, bf16, std::min(cus, kMaxBwdBlocks)));
+      bwd_blocks = std::min(b.bwd_rows, mlp_bwd_mfma_blocks(g, mode, std::min(cus, kMaxCUs)));
     }
     for (size_t i = 0; i < nn; ++i) {
       if (!std::isfinite(log_perm[i])) return fail(CRV_EINVAL, "log_perm has non-finite entries");
@@ -412,7 +416,7 @@ struct Solver : SolverBase {
   // weight fragments of the matrix-core kernels follow every change of theta
   void pack() {
     if constexpr (std::is_same<Real, float>::value) {
-      if (mfma) launch_pack_fragments(b.theta, cfg.dim, cfg.width, cfg.hidden, bf16, b.frag, st);
+      if (mfma) launch_pack_fragments(b.theta, cfg.dim, cfg.width, cfg.hidden, mode, b.frag, st);
     }
   }
 
@@ -421,7 +425,7 @@ struct Solver : SolverBase {
     tb(CRV_K_MLP_FWD);
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, bf16, b.theta, b.frag, b.u, t_bump, st);
+        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, mode, b.theta, b.frag, b.u, t_bump, st);
         te();
         return;
       }
@@ -449,7 +453,7 @@ struct Solver : SolverBase {
     int rows = 0;
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, bf16, P, b.theta, b.frag, b.gu,
+        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, P, b.theta, b.frag, b.gu,
                                  b.partials, bwd_blocks, st);
         rows = bwd_blocks;
       }
@@ -475,7 +479,7 @@ struct Solver : SolverBase {
         const int rows = backward();
         tb(CRV_K_ADAM);
         launch_reduce_adam_pack(b.partials, rows, P, b.theta, b.am, b.av, cfg.lr, cfg.beta1,
-                                cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, bf16,
+                                cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, mode,
                                 b.frag, b.loss_part, b.loss_np, b.loss_hist, kLossCap, st);
         te();
         return;

@@ -22,7 +22,7 @@ def _pair(prec, **over):
     return eager, graph
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp64"])
 def test_graph_replays_equal_eager(prec):
     say("graphs", prec)
     eager, graph = _pair(prec)
