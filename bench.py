@@ -98,14 +98,83 @@ def cpu_baseline(prob, seconds=20.0):
                       f"of the same workload, extrapolated to 100 iterations + 10 substeps"}
 
 
+def run_single(prob, precision, steps, warmup, pretrain, profile):
+    """Coupled steps/s of one scenario (captured steps replayed); optional
+    per-kernel breakdown from an eager, event-timed pass."""
+    import torch
+    from paper_2604_20731_amd import crv
+    sc = crv.scenario_from_problem(prob, precision)
+    sc.pretrain_pressure(pretrain)
+    p, _, _ = sc.fields()
+    dt = cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)
+    for _ in range(warmup):
+        sc.step(dt)
+    sc.fields()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sc.step(dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pf, scf, _ = sc.fields()  # raises on a non-finite saturation
+    assert np.all(np.isfinite(pf)) and np.all(np.isfinite(scf))
+    prof, nprof = {}, max(1, min(2, steps))
+    if profile:
+        sc.profile_enable(True)
+        for _ in range(nprof):
+            sc.step(dt)
+        prof = sc.profile_read()
+        sc.profile_enable(False)
+    sc.close()
+    kernels = {name: {"ms_per_step": ms / nprof, "launches_per_step": n / nprof,
+                      "us_per_launch": 1e3 * ms / n} for name, (ms, n) in prof.items() if n}
+    return {"value": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "dt": dt}, kernels
+
+
+def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
+    """Aggregate coupled steps/s of several 512^2 scenarios, each on its own
+    stream, their captured steps overlapping on the device."""
+    import torch
+    from paper_2604_20731_amd import crv, inputs
+    scs = []
+    for sd in seeds:
+        prob = inputs.make_problem("b512", seed=sd, n_elem=n_elem)
+        cfg = crv.config(dim=2, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
+                         hidden=prob.hidden, precision=precision)
+        st = torch.cuda.Stream()
+        sc = crv.Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0, stream=st)
+        sc.pretrain_pressure(pretrain)
+        p, _, _ = sc.fields()
+        scs.append((sc, cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)))
+    for _ in range(warmup):
+        for sc, dt in scs:
+            sc.step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sc, dt in scs:
+            sc.step(dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for sc, _ in scs:
+        pf, scf, _ = sc.fields()
+        assert np.all(np.isfinite(pf)) and np.all(np.isfinite(scf))
+        sc.close()
+    return {"value": len(seeds) * steps / elapsed, "scenarios": len(seeds),
+            "ms_per_round": 1e3 * elapsed / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3", "fp64"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3", "fp64"],
+                    help="network arithmetic of the headline (batched) run")
+    ap.add_argument("--batch", type=int, default=8, help="concurrent 512^2 scenarios")
     ap.add_argument("--workload", default="b512")
     ap.add_argument("--pretrain", type=int, default=100)
+    ap.add_argument("--serve", type=int, default=64, help="serving arrivals (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     args = ap.parse_args()
@@ -115,46 +184,26 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2604_20731_amd import crv, inputs
+    from paper_2604_20731_amd import inputs
 
     prob = inputs.make_problem(args.workload, seed=0)
-    sc = crv.scenario_from_problem(prob, args.precision)
-    print(f"[bench] {args.workload} {args.precision}: pretraining {args.pretrain} iterations",
-          file=sys.stderr, flush=True)
-    sc.pretrain_pressure(args.pretrain)
-    p, _, _ = sc.fields()
-    dt = cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)
-    for i in range(args.warmup):
-        sc.step(dt)
-    sc.fields()
-    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
-    # timed region: captured coupled steps replayed on the stream
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        sc.step(dt)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    pf, scf, _ = sc.fields()  # raises on a non-finite saturation
-    assert np.all(np.isfinite(pf)) and np.all(np.isfinite(scf))
-    # per-kernel durations: the same steps launched one kernel at a time with
-    # HIP events around every launch on the library's stream
-    prof = {}
-    nprof = max(1, min(2, args.steps))
-    if not args.no_profile:
-        sc.profile_enable(True)
-        for i in range(nprof):
-            sc.step(dt)
-        prof = sc.profile_read()
-        sc.profile_enable(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
-
-    kernels = {}
-    for name, (ms, n) in prof.items():
-        if n:
-            kernels[name] = {"ms_per_step": ms / nprof, "launches_per_step": n / nprof,
-                             "us_per_launch": 1e3 * ms / n}
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    log(f"plain fp32 single scenario, {args.steps} steps")
+    plain, kern_plain = run_single(prob, "fp32", args.steps, args.warmup, args.pretrain, False)
+    log(f"{args.precision} single scenario, {args.steps} steps (+ event-timed kernels)")
+    single, kernels = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain,
+                                 not args.no_profile)
+    log(f"{args.precision} batched: {args.batch} scenarios x {args.steps} steps")
+    batched = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
+                          args.pretrain)
+    serving = None
+    if args.serve > 0:
+        from paper_2604_20731_amd.serve import Server
+        log(f"serving: {args.serve} Poisson arrivals (mean 50 ms), 20 coupled steps each")
+        srv = Server(hbm_budget_bytes=16 << 30, max_active=16, precision=args.precision,
+                     pretrain_iters=200, steps=20)
+        out = srv.run(inputs.serving_mix(args.serve))
+        serving = {k: v for k, v in out.items() if k != "results"}
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
@@ -166,10 +215,10 @@ def main():
                 peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"],
                         "bf16x3": PEAK["bf16_tflops"], "fp64": PEAK["fp64_tflops"]}[args.precision]
                 achieved = amount / (us * 1e-6) / 1e12
-                bound = "alu" if args.precision == "fp64" else "mfma"
-                roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
-                            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                            "work_per_launch": amount, "us_per_launch": us}
+                roofline = {"kernel": dom, "bound": "alu" if args.precision == "fp64" else "mfma",
+                            "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                            "frac": achieved / peak, "traffic": None, "work_per_launch": amount,
+                            "us_per_launch": us}
             else:
                 achieved = amount / (us * 1e-6) / 1e9
                 roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved,
@@ -178,26 +227,32 @@ def main():
                             "work_per_launch": amount, "us_per_launch": us}
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle sample on the host", file=sys.stderr, flush=True)
+        log("timing the FP64 oracle sample on the host")
         cpu = cpu_baseline(prob)
     out = {
         "metric": "coupled time steps/s at 512^2",
-        "value": value,
+        "value": batched["value"],
         "unit": "coupled steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 / batched["value"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16 (network) / f32", "bf16x3": "bf16x3 (network) / f32",
                   "fp64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 2D {prob.n_elem}^2 quadratic elements, "
-                               f"{prob.n_elem + 1}^2 nodes, MLP 2->{prob.hidden}x{prob.width}->1, "
-                               "5 wells, 10 substeps + 100 Adam iterations per step",
-                   "precision": args.precision, "dt": dt},
+        "config": {"workload": f"{args.workload} x{args.batch}: {args.batch} concurrent scenarios, "
+                               f"2D {prob.n_elem}^2 quadratic elements, {prob.n_elem + 1}^2 nodes, "
+                               f"MLP 2->{prob.hidden}x{prob.width}->1, 5 wells, 10 substeps + 100 Adam "
+                               "iterations per coupled step",
+                   "precision": args.precision, "batch": args.batch, "dt": single["dt"]},
+        "plain_fp32_single": plain,
+        "single": single,
+        "batched": batched,
+        "vs_plain": batched["value"] / plain["value"],
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

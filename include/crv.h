@@ -123,6 +123,14 @@ crv_status crv_init(const crv_config* cfg, const double* log_perm, const double*
  * the last iteration (evaluated before its update).  Blocks until done. */
 crv_status crv_pretrain_pressure(crv_ctx* ctx, int iters, double* final_loss);
 
+/* Same iterations as crv_pretrain_pressure, enqueued on the context's stream
+ * without waiting (for schedulers overlapping several contexts). */
+crv_status crv_train_async(crv_ctx* ctx, int iters);
+
+/* Wait for all work enqueued on the context's stream; CRV_ENUMERIC if a
+ * non-finite saturation was flagged. */
+crv_status crv_sync(crv_ctx* ctx);
+
 /* Algorithm steps 4-7, one coupled step of length dt > 0: project the
  * network pressure, cfg.substeps substeps of tau = dt/substeps, refresh
  * alpha from the new saturation, cfg.adam_iters Adam iterations.

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
 
 EXPORTED = [
     "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
-    "crv_pretrain_pressure", "crv_step", "crv_get_fields", "crv_loss_grad",
+    "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_loss_history",
     "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
     "crv_saturation_substeps", "crv_profile_enable", "crv_profile_read", "crv_destroy",
@@ -69,6 +69,8 @@ def _load() -> C.CDLL:
         "crv_init": [cfgp, dp, dp, dp, C.c_int, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)],
         "crv_pretrain_pressure": [vp, C.c_int, dp],
         "crv_step": [vp, C.c_double],
+        "crv_train_async": [vp, C.c_int],
+        "crv_sync": [vp],
         "crv_get_fields": [vp, dp, dp, dp],
         "crv_loss_grad": [vp, dp, dp, dp],
         "crv_get_state": [vp, dp, dp, dp, C.POINTER(C.c_int64)],
@@ -171,6 +173,7 @@ class Scenario:
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             LIB.crv_destroy(self.ctx)
             self.ctx = None
+        self._ws = None  # the workspace may be reused once the context is gone
 
     def __del__(self):
         try:
@@ -186,6 +189,16 @@ class Scenario:
 
     def step(self, dt: float):
         _check(LIB.crv_step(self.ctx, float(dt)))
+
+    def train_async(self, iters: int):
+        _check(LIB.crv_train_async(self.ctx, int(iters)))
+
+    def sync(self):
+        _check(LIB.crv_sync(self.ctx))
+
+    @property
+    def stream(self):
+        return self._stream
 
     def fields(self):
         shp_n = (self.ne + 1,) * self.dim

@@ -247,6 +247,7 @@ struct SolverBase {
   virtual crv_status mass_solve_host(const double*, double*) = 0;
   virtual crv_status project_host(double*) = 0;
   virtual crv_status substeps(double tau, int n) = 0;
+  virtual crv_status sync() = 0;
 };
 
 template <typename Real>
@@ -284,6 +285,8 @@ struct Solver : SolverBase {
     if (e != hipSuccess) return fail(CRV_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return CRV_OK;
   }
+  crv_status sync() override { return sync_and_check(); }
+
   crv_status sync_and_check() {
     CRV_HIP(hipStreamSynchronize(st));
     int flag = 0;
@@ -846,6 +849,17 @@ crv_status crv_pretrain_pressure(crv_ctx* c, int iters, double* final_loss) {
     if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
   }
   return CRV_OK;
+}
+
+crv_status crv_train_async(crv_ctx* c, int iters) {
+  CRV_CTX(c);
+  if (iters < 0) return fail(CRV_EINVAL, "iters must be >= 0");
+  return sv.train(iters);
+}
+
+crv_status crv_sync(crv_ctx* c) {
+  CRV_CTX(c);
+  return sv.sync();
 }
 
 crv_status crv_step(crv_ctx* c, double dt) {
