@@ -38,13 +38,55 @@ __global__ __launch_bounds__(256) void k_refresh2(Geom g, const Real* __restrict
   alpha[p] = (krw * inv_mu_w + krg * inv_mu_g) * perm[p];
 }
 
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_refresh3(Geom g, const Real* __restrict__ c,
+                                                  const int* __restrict__ kf,
+                                                  const Real* __restrict__ kv,
+                                                  const Real* __restrict__ perm, Real inv_mu_w,
+                                                  Real inv_mu_g, Real nexp,
+                                                  Real* __restrict__ s_nodal,
+                                                  Real* __restrict__ alpha) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int n = g.n, nb = g.nb;
+  if (p >= int64_t(n) * n * n) return;
+  const int i = int(p % n), j = int((p / n) % n), k = int(p / (int64_t(n) * n));
+  const int fi = kf[i], fj = kf[j], fk = kf[k];
+  Real s = 0;
+#pragma unroll
+  for (int cc = 0; cc <= R; ++cc) {
+    Real plane = 0;
+#pragma unroll
+    for (int b = 0; b <= R; ++b) {
+      Real row = 0;
+#pragma unroll
+      for (int a = 0; a <= R; ++a)
+        row += kv[i * (R + 1) + a] * c[(int64_t(fk + cc) * nb + fj + b) * nb + fi + a];
+      plane += kv[j * (R + 1) + b] * row;
+    }
+    s += kv[k * (R + 1) + cc] * plane;
+  }
+  const Real sc = clamp01(s);
+  const Real krw = powi_or_pow(Real(1) - sc, nexp), krg = powi_or_pow(sc, nexp);
+  s_nodal[p] = s;
+  alpha[p] = (krw * inv_mu_w + krg * inv_mu_g) * perm[p];
+}
+
 template <typename Real>
 void launch_refresh(const Geom& g, const Real* s_coefs, const int* kf, const Real* kv,
                     const Real* perm, double mu_w, double mu_g, double nexp, Real* s_nodal,
                     Real* alpha, hipStream_t st) {
+  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  if (g.dim == 3) {
+    dim3 grid3(cdiv(ipow(g.n, 3), 256));
+    switch (g.r) {
+      case 1: k_refresh3<Real, 1><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+      case 2: k_refresh3<Real, 2><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+      default: k_refresh3<Real, 3><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+    }
+    return;
+  }
   const int64_t tot = int64_t(g.n) * g.n;
   dim3 grid(cdiv(tot, 256));
-  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
   switch (g.r) {
     case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
     case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
@@ -72,9 +114,34 @@ __global__ __launch_bounds__(256) void k_residual2(Geom g, const Real* __restric
   res[int64_t(jj) * g.mp + ii] = r;
 }
 
+// 3D: RES_p = h sum_dir [...] - h^3 q_p (the alpha terms carry h^(d-2));
+// interior arrays padded to mp in every direction
+template <typename Real>
+__global__ __launch_bounds__(256) void k_residual3(Geom g, const Real* __restrict__ u,
+                                                   const Real* __restrict__ alpha,
+                                                   const Real* __restrict__ hq, Real h,
+                                                   Real* __restrict__ res) {
+  const int ii = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int jj = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int kk = blockIdx.z;
+  if (ii >= g.m || jj >= g.m) return;
+  const int64_t n = g.n, n2 = n * n;
+  const int64_t p = (int64_t(kk + 1) * n + (jj + 1)) * n + (ii + 1);
+  const Real up = u[p], ap = alpha[p];
+  const Real sx = alpha[p - 1] * (up - u[p - 1]) - ap * (u[p + 1] - up);
+  const Real sy = alpha[p - n] * (up - u[p - n]) - ap * (u[p + n] - up);
+  const Real sz = alpha[p - n2] * (up - u[p - n2]) - ap * (u[p + n2] - up);
+  res[(int64_t(kk) * g.mp + jj) * g.mp + ii] = h * (sx + sy + sz) - hq[p];
+}
+
 template <typename Real>
 void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real* hq, Real* res,
                      hipStream_t st) {
+  if (g.dim == 3) {
+    dim3 grid3(cdiv(g.m, 64), cdiv(g.m, 4), g.m);
+    k_residual3<Real><<<grid3, 256, 0, st>>>(g, u, alpha, hq, Real(1.0 / g.ne), res);
+    return;
+  }
   dim3 grid(cdiv(g.m, 64), cdiv(g.m, 4));
   k_residual2<Real><<<grid, 256, 0, st>>>(g, u, alpha, hq, res);
 }
@@ -115,11 +182,54 @@ __global__ __launch_bounds__(256) void k_adjoint2(Geom g, const Real* __restrict
   if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
-int adjoint_partials(const Geom& g) { return cdiv(g.n, 64) * cdiv(g.n, 4); }
+template <typename Real>
+__device__ inline Real qext3(const Real* q, const Geom& g, int i, int j, int k) {
+  return (i >= 1 && i <= g.m && j >= 1 && j <= g.m && k >= 1 && k <= g.m)
+             ? q[(int64_t(k - 1) * g.mp + (j - 1)) * g.mp + (i - 1)]
+             : Real(0);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adjoint3(Geom g, const Real* __restrict__ q,
+                                                  const Real* __restrict__ alpha,
+                                                  const Real* __restrict__ res, Real h,
+                                                  Real* __restrict__ gu,
+                                                  Real* __restrict__ partials) {
+  __shared__ Real sbuf[256];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  const int64_t n = g.n, n2 = n * n;
+  Real lpart = 0;
+  if (i < n && j < n) {
+    const int64_t p = (int64_t(k) * n + j) * n + i;
+    Real out = 0;
+    if (i >= 1 && i <= g.m && j >= 1 && j <= g.m && k >= 1 && k <= g.m) {
+      const Real qp = qext3(q, g, i, j, k), ap = alpha[p];
+      const Real sx = alpha[p - 1] * (qp - qext3(q, g, i - 1, j, k)) - ap * (qext3(q, g, i + 1, j, k) - qp);
+      const Real sy = alpha[p - n] * (qp - qext3(q, g, i, j - 1, k)) - ap * (qext3(q, g, i, j + 1, k) - qp);
+      const Real sz = alpha[p - n2] * (qp - qext3(q, g, i, j, k - 1)) - ap * (qext3(q, g, i, j, k + 1) - qp);
+      out = Real(2) * h * (sx + sy + sz);
+      lpart = res[(int64_t(k - 1) * g.mp + (j - 1)) * g.mp + (i - 1)] * qp;
+    }
+    gu[p] = out;
+  }
+  const Real tot = block_sum(lpart, sbuf);
+  if (threadIdx.x == 0) partials[(int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+}
+
+int adjoint_partials(const Geom& g) {
+  return cdiv(g.n, 64) * cdiv(g.n, 4) * (g.dim == 3 ? g.n : 1);
+}
 
 template <typename Real>
 int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* res, Real* gu,
                    Real* partials, hipStream_t st) {
+  if (g.dim == 3) {
+    dim3 grid3(cdiv(g.n, 64), cdiv(g.n, 4), g.n);
+    k_adjoint3<Real><<<grid3, 256, 0, st>>>(g, q, alpha, res, Real(1.0 / g.ne), gu, partials);
+    return grid3.x * grid3.y * grid3.z;
+  }
   dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
   k_adjoint2<Real><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials);
   return grid.x * grid.y;
@@ -163,8 +273,32 @@ __global__ __launch_bounds__(256) void k_grad_logperm2(Geom g, const Real* __res
 }
 
 template <typename Real>
+__global__ __launch_bounds__(256) void k_grad_logperm3(Geom g, const Real* __restrict__ u,
+                                                       const Real* __restrict__ q,
+                                                       const Real* __restrict__ alpha, Real h,
+                                                       Real* __restrict__ out) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  const int64_t n = g.n, n2 = n * n;
+  if (i >= n || j >= n) return;
+  const int64_t p = (int64_t(k) * n + j) * n + i;
+  const Real qp = qext3(q, g, i, j, k);
+  Real s = 0;
+  if (i + 1 < n) s += (u[p + 1] - u[p]) * (qext3(q, g, i + 1, j, k) - qp);
+  if (j + 1 < n) s += (u[p + n] - u[p]) * (qext3(q, g, i, j + 1, k) - qp);
+  if (k + 1 < n) s += (u[p + n2] - u[p]) * (qext3(q, g, i, j, k + 1) - qp);
+  out[p] = Real(2) * h * s * alpha[p];
+}
+
+template <typename Real>
 void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real* alpha,
                          Real* out, hipStream_t st) {
+  if (g.dim == 3) {
+    dim3 grid3(cdiv(g.n, 64), cdiv(g.n, 4), g.n);
+    k_grad_logperm3<Real><<<grid3, 256, 0, st>>>(g, u, q, alpha, Real(1.0 / g.ne), out);
+    return;
+  }
   dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
   k_grad_logperm2<Real><<<grid, 256, 0, st>>>(g, u, q, alpha, out);
 }
@@ -197,8 +331,49 @@ __global__ __launch_bounds__(256) void k_project2(Geom g, const Real* __restrict
   b[idx] = acc;
 }
 
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_project3(Geom g, const Real* __restrict__ u,
+                                                  const Real* __restrict__ qv,
+                                                  Real* __restrict__ b) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int nb = g.nb, n = g.n;
+  if (idx >= int64_t(nb) * nb * nb) return;
+  const int a = int(idx % nb), bb = int((idx / nb) % nb), c = int(idx / (int64_t(nb) * nb));
+  Real acc = 0;
+#pragma unroll
+  for (int tc = 0; tc < R + 2; ++tc) {
+    const int k = c - R + tc;
+    if (k < 0 || k > g.ne) continue;
+    Real plane = 0;
+#pragma unroll
+    for (int tb = 0; tb < R + 2; ++tb) {
+      const int j = bb - R + tb;
+      if (j < 0 || j > g.ne) continue;
+      Real row = 0;
+#pragma unroll
+      for (int ta = 0; ta < R + 2; ++ta) {
+        const int i = a - R + ta;
+        if (i < 0 || i > g.ne) continue;
+        row += qv[a * (R + 2) + ta] * u[(int64_t(k) * n + j) * n + i];
+      }
+      plane += qv[bb * (R + 2) + tb] * row;
+    }
+    acc += qv[c * (R + 2) + tc] * plane;
+  }
+  b[idx] = acc;
+}
+
 template <typename Real>
 void launch_project(const Geom& g, const Real* u, const Real* qv, Real* b, hipStream_t st) {
+  if (g.dim == 3) {
+    dim3 grid3(cdiv(ipow(g.nb, 3), 256));
+    switch (g.r) {
+      case 1: k_project3<Real, 1><<<grid3, 256, 0, st>>>(g, u, qv, b); break;
+      case 2: k_project3<Real, 2><<<grid3, 256, 0, st>>>(g, u, qv, b); break;
+      default: k_project3<Real, 3><<<grid3, 256, 0, st>>>(g, u, qv, b); break;
+    }
+    return;
+  }
   dim3 grid(cdiv(int64_t(g.nb) * g.nb, 256));
   switch (g.r) {
     case 1: k_project2<Real, 1><<<grid, 256, 0, st>>>(g, u, qv, b); break;
@@ -330,6 +505,220 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
   b[int64_t(l) * nb + k] = acc;
 }
 
+// 3D form: a block owns TC x TC coefficients in (x, y) and ZC consecutive
+// coefficients in z, and streams through the element layers that touch them.
+// Per layer: integrand at the Gauss points of the (TC+R)^2 elements of the
+// layer (LDS), contraction with the x test functions, then with the y test
+// functions (sum factorisation), then each owning thread adds the z test
+// functions into R+1 rolling accumulators; coefficient c is complete once
+// layer c has been added.  Fixed order throughout, no atomics.
+template <typename Real, int R, int TC, int ZC>
+__global__ __launch_bounds__(256) void k_ads_assemble3(
+    Geom g, const Real* __restrict__ sc, const Real* __restrict__ pc,
+    const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
+    const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
+    const Real* __restrict__ gxi, const Real* __restrict__ gw, const double* __restrict__ tau_dev,
+    Real inv_mu_w, Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+  constexpr int NG = R + 1;
+  constexpr int TE = TC + R;
+  constexpr int TCO = TC + 2 * R;
+  constexpr int TN = TE + 1;
+  constexpr int GP = TE * NG;
+  constexpr int NT = 256;
+  static_assert(sizeof(Real) * (2 * TCO * TCO * (R + 1) + 8 * TN * TN + 4 * GP * GP * NG +
+                                3 * TC * GP * NG + 2 * TC * TC * NG) <= 65536,
+                "LDS of the 3D assembly tile");
+  __shared__ Real sS[(R + 1) * TCO * TCO], sP[(R + 1) * TCO * TCO];
+  __shared__ Real sK[2 * TN * TN], sF[2 * TN * TN], sQi[2 * TN * TN], sQp[2 * TN * TN];
+  __shared__ Real sF0[GP * GP * NG], sFx[GP * GP * NG], sFy[GP * GP * NG], sFz[GP * GP * NG];
+  __shared__ Real sG0[TC * GP * NG], sGy[TC * GP * NG], sGz[TC * GP * NG];
+  __shared__ Real sH0[TC * TC * NG], sHz[TC * TC * NG];
+  const Real tau = Real(*tau_dev);
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC, cz0 = blockIdx.z * ZC;
+  const int c0x = k0 - R, c0y = l0 - R;
+  const int nb = g.nb, ne = g.ne;
+  const int64_t n = g.n, nbb = int64_t(nb) * nb;
+  const int own_a = tid % TC, own_b = tid / TC;
+  const bool owner = tid < TC * TC;
+  const int kx = k0 + own_a, ly = l0 + own_b;
+  Real acc[R + 1];
+#pragma unroll
+  for (int j = 0; j <= R; ++j) acc[j] = 0;
+  const int ez_end = min(cz0 + ZC, nb);
+  for (int ez = cz0 - R; ez < ez_end; ++ez) {
+    if (ez >= 0 && ez < ne) {
+      // coefficient planes ez..ez+R and nodal planes ez, ez+1 of the tile
+      for (int t = tid; t < (R + 1) * TCO * TCO; t += NT) {
+        const int a = c0x + t % TCO, bb = c0y + (t / TCO) % TCO, cc = ez + t / (TCO * TCO);
+        const bool ok = a >= 0 && a < nb && bb >= 0 && bb < nb;
+        const int64_t q = int64_t(cc) * nbb + int64_t(bb) * nb + a;
+        sS[t] = ok ? sc[q] : Real(0);
+        sP[t] = ok ? pc[q] : Real(0);
+      }
+      for (int t = tid; t < 2 * TN * TN; t += NT) {
+        const int i = c0x + t % TN, j = c0y + (t / TN) % TN, k = ez + t / (TN * TN);
+        const bool ok = i >= 0 && i <= ne && j >= 0 && j <= ne;
+        const int64_t q = (int64_t(k) * n + j) * n + i;
+        sK[t] = ok ? perm[q] : Real(0);
+        sF[t] = ok ? poro[q] : Real(1);
+        sQi[t] = ok ? qi[q] : Real(0);
+        sQp[t] = ok ? qp[q] : Real(0);
+      }
+      __syncthreads();
+      // integrand at the Gauss points of the layer
+      for (int t = tid; t < GP * GP * NG; t += NT) {
+        const int gxl = t % GP, gyl = (t / GP) % GP, gz = t / (GP * GP);
+        const int exl = gxl / NG, gx = gxl % NG, eyl = gyl / NG, gy = gyl % NG;
+        const int ex = c0x + exl, ey = c0y + eyl;
+        Real f0 = 0, fx = 0, fy = 0, fz = 0;
+        if (ex >= 0 && ex < ne && ey >= 0 && ey < ne) {
+          const Real* bx = gb + (int64_t(ex) * NG + gx) * (R + 1);
+          const Real* dbx = gdb + (int64_t(ex) * NG + gx) * (R + 1);
+          const Real* by = gb + (int64_t(ey) * NG + gy) * (R + 1);
+          const Real* dby = gdb + (int64_t(ey) * NG + gy) * (R + 1);
+          const Real* bz = gb + (int64_t(ez) * NG + gz) * (R + 1);
+          const Real* dbz = gdb + (int64_t(ez) * NG + gz) * (R + 1);
+          Real s = 0, px = 0, py = 0, pz = 0;
+#pragma unroll
+          for (int cc = 0; cc <= R; ++cc) {
+            Real ps = 0, ppx = 0, ppy = 0, ppz = 0;
+#pragma unroll
+            for (int bb = 0; bb <= R; ++bb) {
+              Real rs = 0, rpx = 0, rp = 0;
+#pragma unroll
+              for (int a = 0; a <= R; ++a) {
+                const int li = (cc * TCO + eyl + bb) * TCO + exl + a;
+                rs += bx[a] * sS[li];
+                rpx += dbx[a] * sP[li];
+                rp += bx[a] * sP[li];
+              }
+              ps += by[bb] * rs;
+              ppx += by[bb] * rpx;
+              ppy += dby[bb] * rp;
+              ppz += by[bb] * rp;
+            }
+            s += bz[cc] * ps;
+            px += bz[cc] * ppx;
+            py += bz[cc] * ppy;
+            pz += dbz[cc] * ppz;
+          }
+          const Real xi = gxi[gx], eta = gxi[gy], zeta = gxi[gz];
+          const int n0 = eyl * TN + exl;
+          auto interp = [&](const Real* arr) {
+            const Real lo = (1 - eta) * ((1 - xi) * arr[n0] + xi * arr[n0 + 1]) +
+                            eta * ((1 - xi) * arr[n0 + TN] + xi * arr[n0 + TN + 1]);
+            const Real* a1 = arr + TN * TN;
+            const Real hi = (1 - eta) * ((1 - xi) * a1[n0] + xi * a1[n0 + 1]) +
+                            eta * ((1 - xi) * a1[n0 + TN] + xi * a1[n0 + TN + 1]);
+            return (1 - zeta) * lo + zeta * hi;
+          };
+          const Real kk = interp(sK), phi = interp(sF), qin = interp(sQi), qpr = interp(sQp);
+          const Real scl = clamp01(s);
+          const Real lam_g = powi_or_pow(scl, nexp) * inv_mu_g;
+          const Real lam_w = powi_or_pow(Real(1) - scl, nexp) * inv_mu_w;
+          const Real fg = lam_g / (lam_g + lam_w);
+          const Real qg = qin + fg * qpr;
+          const Real w = gw[gx] * gw[gy] * gw[gz];
+          const Real tphi = tau / phi;
+          f0 = w * (s + tphi * qg);
+          const Real c = -w * tphi * lam_g * kk;
+          fx = c * px;
+          fy = c * py;
+          fz = c * pz;
+        }
+        sF0[t] = f0;
+        sFx[t] = fx;
+        sFy[t] = fy;
+        sFz[t] = fz;
+      }
+      __syncthreads();
+      // x test functions: G[a][gyl][gz]
+      for (int t = tid; t < TC * GP * NG; t += NT) {
+        const int al = t % TC, gyl = (t / TC) % GP, gz = t / (TC * GP);
+        const int k = k0 + al;
+        Real r0 = 0, ry = 0, rz = 0;
+        if (k < nb) {
+          for (int ex = k - R; ex <= k; ++ex) {
+            if (ex < 0 || ex >= ne) continue;
+            const int a = k - ex, exl = ex - c0x;
+#pragma unroll
+            for (int gx = 0; gx < NG; ++gx) {
+              const Real bx = gb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+              const Real dbx = gdb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+              const int f = (gz * GP + gyl) * GP + exl * NG + gx;
+              r0 += bx * sF0[f] + dbx * sFx[f];
+              ry += bx * sFy[f];
+              rz += bx * sFz[f];
+            }
+          }
+        }
+        sG0[t] = r0;
+        sGy[t] = ry;
+        sGz[t] = rz;
+      }
+      __syncthreads();
+      // y test functions: H[a][b][gz]
+      for (int t = tid; t < TC * TC * NG; t += NT) {
+        const int al = t % TC, bl = (t / TC) % TC, gz = t / (TC * TC);
+        const int l = l0 + bl;
+        Real h0 = 0, hz = 0;
+        if (l < nb) {
+          for (int ey = l - R; ey <= l; ++ey) {
+            if (ey < 0 || ey >= ne) continue;
+            const int bb = l - ey, eyl = ey - c0y;
+#pragma unroll
+            for (int gy = 0; gy < NG; ++gy) {
+              const Real by = gb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+              const Real dby = gdb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+              const int f = (gz * GP + eyl * NG + gy) * TC + al;
+              h0 += by * sG0[f] + dby * sGy[f];
+              hz += by * sGz[f];
+            }
+          }
+        }
+        sH0[t] = h0;
+        sHz[t] = hz;
+      }
+      __syncthreads();
+      // z test functions into the rolling accumulators (c = ez + j)
+      if (owner) {
+#pragma unroll
+        for (int j = 0; j <= R; ++j) {
+          Real v = 0;
+#pragma unroll
+          for (int gz = 0; gz < NG; ++gz) {
+            const Real bz = gb[(int64_t(ez) * NG + gz) * (R + 1) + j];
+            const Real dbz = gdb[(int64_t(ez) * NG + gz) * (R + 1) + j];
+            const int f = (gz * TC + own_b) * TC + own_a;
+            v += bz * sH0[f] + dbz * sHz[f];
+          }
+          acc[j] += v;
+        }
+      }
+    }
+    // coefficient c = ez has all its layers once c >= cz0
+    if (owner && ez >= cz0 && kx < nb && ly < nb)
+      b[int64_t(ez) * nbb + int64_t(ly) * nb + kx] = acc[0];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = acc[j + 1];
+    acc[R] = 0;
+  }
+}
+
+template <typename Real, int R>
+void launch_ads3(const Geom& g, const Real* s, const Real* p, const Real* perm,
+                 const Real* poro, const Real* qi, const Real* qp, const Real* gb,
+                 const Real* gdb, const Real* gxi, const Real* gw, const double* tau, Real iw,
+                 Real ig, Real ne, Real* b, hipStream_t st) {
+  constexpr bool big = sizeof(Real) == 8;
+  constexpr int TC = big ? (R == 3 ? 2 : 4) : (R == 3 ? 4 : 8);
+  constexpr int ZC = 16;
+  dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC), cdiv(g.nb, ZC));
+  k_ads_assemble3<Real, R, TC, ZC><<<grid, 256, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb,
+                                                         gxi, gw, tau, iw, ig, ne, b);
+}
+
 template <typename Real>
 void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
@@ -337,6 +726,15 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
                          double mu_w, double mu_g, double nexp, Real* b, hipStream_t st) {
   const double* t = tau;
   const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  if (g.dim == 3) {
+    if (g.r == 1)
+      launch_ads3<Real, 1>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+    else if (g.r == 2)
+      launch_ads3<Real, 2>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+    else
+      launch_ads3<Real, 3>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+    return;
+  }
   constexpr bool big = sizeof(Real) == 8;
   if (g.r == 1) {
     constexpr int TC = 16;

@@ -572,8 +572,7 @@ __global__ __launch_bounds__(256) void k_reduce_adam_pack(
 // host launchers
 // ---------------------------------------------------------------------------
 bool mlp_mfma_supported(int dim, int width, int hidden, int mode) {
-  if (dim != 2) return false;
-  if (!(hidden == 3 || hidden == 4)) return false;
+  if (dim == 3 ? hidden != 4 : (dim != 2 || !(hidden == 3 || hidden == 4))) return false;
   if (mode == NET_BF16) return width == 32 || width == 64 || width == 128;
   return width == 32 || width == 64;
 }
@@ -614,10 +613,16 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* 
 template <int W, int L, int MODE>
 static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, long long* tb,
                      hipStream_t st) {
-  const int64_t total = ipow(g.n, 2);
+  const int64_t total = ipow(g.n, g.dim);
   const int64_t tiles = (total + 31) / 32;
-  k_mlp_fwd_mfma<W, L, MODE, 2><<<cdiv(tiles, 4), 256, 0, st>>>(
-      g, th, static_cast<const typename MM<MODE>::felem*>(frag), u, tb);
+  const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
+  if constexpr (L == 4) {
+    if (g.dim == 3) {
+      k_mlp_fwd_mfma<W, L, MODE, 3><<<cdiv(tiles, 4), 256, 0, st>>>(g, th, fr, u, tb);
+      return;
+    }
+  }
+  k_mlp_fwd_mfma<W, L, MODE, 2><<<cdiv(tiles, 4), 256, 0, st>>>(g, th, fr, u, tb);
 }
 
 #define CRV_FOR_SHAPES(X)                                                                    \
@@ -650,8 +655,14 @@ template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* gu,
                      float* partials, int blocks, hipStream_t st) {
   constexpr int NW = bwd_nw(MODE);
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(
-      g, P, th, static_cast<const typename MM<MODE>::felem*>(frag), gu, partials);
+  const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
+  if constexpr (L == 4) {
+    if (g.dim == 3) {
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, gu, partials);
+      return;
+    }
+  }
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, gu, partials);
 }
 
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,

@@ -384,12 +384,16 @@ void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_str
 
 // ---------------------------------------------------------------------------
 // C = A B (row-major, dims multiples of 64): 64x64 tiles, 16-deep K slabs in
-// LDS, 4x4 outputs per thread.
+// LDS, 4x4 outputs per thread.  blockIdx.z selects one product of a batch
+// that shares A (B and C advance by sb and sc).
 // ---------------------------------------------------------------------------
 template <typename Real>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* __restrict__ A,
                                               int lda, const Real* __restrict__ B, int ldb,
-                                              Real* __restrict__ C, int ldc) {
+                                              int64_t sb, Real* __restrict__ C, int ldc,
+                                              int64_t sc) {
+  B += int64_t(blockIdx.z) * sb;
+  C += int64_t(blockIdx.z) * sc;
   __shared__ Real As[16][64 + 4];
   __shared__ Real Bs[16][64 + 4];
   const int tid = threadIdx.x;
@@ -436,7 +440,10 @@ typedef float gemm_f32x16_t __attribute__((ext_vector_type(16)));
 __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
                                                        const float* __restrict__ A, int lda,
                                                        const float* __restrict__ B, int ldb,
-                                                       float* __restrict__ C, int ldc) {
+                                                       int64_t sb, float* __restrict__ C, int ldc,
+                                                       int64_t sc) {
+  B += int64_t(blockIdx.z) * sb;
+  C += int64_t(blockIdx.z) * sc;
   __shared__ float part[4][32 * 33];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, g = lane >> 5;
   const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
@@ -468,16 +475,23 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
 }
 
 template <typename Real>
-void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
-                 int ldc, hipStream_t st) {
+void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
+                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st) {
+  if (batch <= 0) return;
   if constexpr (sizeof(Real) == 4) {
     // dims are multiples of 64, so K/4 is a multiple of 16
-    dim3 grid(N / 32, M / 32);
-    k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    dim3 grid(N / 32, M / 32, batch);
+    k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
   } else {
-    dim3 grid(N / 64, M / 64);
-    k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    dim3 grid(N / 64, M / 64, batch);
+    k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
   }
+}
+
+template <typename Real>
+void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
+                 int ldc, hipStream_t st) {
+  launch_gemm_batched<Real>(M, N, K, A, lda, B, ldb, 0, C, ldc, 0, 1, st);
 }
 
 #define CRV_INST(R)                                                                            \
@@ -485,7 +499,9 @@ void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int
                                     int64_t, int64_t, hipStream_t);                           \
   template void launch_band_cols<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
                                     int64_t, int64_t, hipStream_t);                           \
-  template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t);
+  template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t); \
+  template void launch_gemm_batched<R>(int, int, int, const R*, int, const R*, int, int64_t, R*, \
+                                       int, int64_t, int, hipStream_t);
 CRV_INST(float)
 CRV_INST(double)
 

@@ -87,6 +87,10 @@ void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_str
 template <typename Real>
 void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
                  int ldc, hipStream_t st);
+// batch products sharing A: C_z = A B_z, B_z = B + z sb, C_z = C + z sc
+template <typename Real>
+void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
+                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st);
 
 // ---- network (k_mlp.hip) ---------------------------------------------------
 struct MlpShape {

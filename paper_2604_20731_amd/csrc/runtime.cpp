@@ -52,6 +52,10 @@ struct Carve {
   }
 };
 
+// Gram line solves: one tridiagonal line per interior (y[, z]) mode, padded
+// modes included in 3D so that the line index is the row index of the array
+static int64_t gram_lines(const Geom& g) { return g.dim == 3 ? int64_t(g.m) * g.mp : g.m; }
+
 static Geom make_geom(const crv_config& c) {
   Geom g;
   g.dim = c.dim;
@@ -70,9 +74,9 @@ struct Buffers {
   Real *perm, *poro, *qi, *qp, *hq, *s_nodal, *alpha, *u, *gu, *tmp_nodal;
   // coefficients nb^d
   Real *s, *p, *bvec;
-  // interior, padded mp x mp
+  // interior, padded to mp per axis
   Real *res, *rhat, *qhat, *q, *dst;
-  // Gram lines (m lines, pitch mp) and mass factors
+  // Gram lines (pitch mp) and mass factors
   Real *g_lt, *g_invd, *m_lt, *m_invd;
   double *band, *band_work, *shifts;
   int* status;
@@ -105,7 +109,8 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   const Geom g = make_geom(c);
   const size_t nn = size_t(ipow(g.n, g.dim));
   const size_t nc = size_t(ipow(g.nb, g.dim));
-  const size_t ni = size_t(g.mp) * g.mp;
+  const size_t ni = size_t(ipow(g.mp, g.dim));
+  const size_t nl = size_t(gram_lines(g));
   const int64_t P = mlp_param_count(c.dim, c.width, c.hidden);
   MlpShape ms{c.dim, c.width, c.hidden, P};
   b.perm = cv.take<Real>(nn);
@@ -125,14 +130,14 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.rhat = cv.take<Real>(ni);
   b.qhat = cv.take<Real>(ni);
   b.q = cv.take<Real>(ni);
-  b.dst = cv.take<Real>(ni);
-  b.g_lt = cv.take<Real>(size_t(g.m) * g.mp);
-  b.g_invd = cv.take<Real>(size_t(g.m) * g.mp);
+  b.dst = cv.take<Real>(size_t(g.mp) * g.mp);
+  b.g_lt = cv.take<Real>(nl * g.mp);
+  b.g_invd = cv.take<Real>(nl * g.mp);
   b.m_lt = cv.take<Real>(size_t(g.nb) * g.r);
   b.m_invd = cv.take<Real>(size_t(g.nb));
   b.band = cv.take<double>(size_t(g.nb) * (g.r + 1));
   b.band_work = cv.take<double>(size_t(g.nb) * (g.r + 1));
-  b.shifts = cv.take<double>(size_t(g.m));
+  b.shifts = cv.take<double>(nl);
   b.status = cv.take<int>(1);
   b.knot_first = cv.take<int>(size_t(g.n));
   b.knot_val = cv.take<Real>(size_t(g.n) * (g.r + 1));
@@ -163,8 +168,9 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
 
 static crv_status validate_config(const crv_config* c) {
   if (!c) return fail(CRV_EINVAL, "config is NULL");
-  if (c->dim != 2) return fail(CRV_EINVAL, "dim must be 2");
-  if (c->n_elem < 4 || c->n_elem > 1024) return fail(CRV_EINVAL, "n_elem must be in [4, 1024]");
+  if (c->dim != 2 && c->dim != 3) return fail(CRV_EINVAL, "dim must be 2 or 3");
+  if (c->n_elem < 4 || c->n_elem > (c->dim == 2 ? 1024 : 256))
+    return fail(CRV_EINVAL, "n_elem must be in [4, 1024] (2D) or [4, 256] (3D)");
   if (c->degree < 1 || c->degree > 3) return fail(CRV_EINVAL, "degree must be 1, 2 or 3");
   if (!(c->width == 16 || c->width == 32 || c->width == 64 || c->width == 128))
     return fail(CRV_EINVAL, "width must be 16, 32, 64 or 128");
@@ -173,7 +179,8 @@ static crv_status validate_config(const crv_config* c) {
     return fail(CRV_EINVAL, "unknown precision");
   if ((c->precision == CRV_PREC_BF16 || c->precision == CRV_PREC_BF16X3) &&
       !mlp_mfma_supported(c->dim, c->width, c->hidden, net_mode(*c)))
-    return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 also 128) and 3 or 4 hidden layers");
+    return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 also 128) and 3 or 4 "
+                            "hidden layers (4 in 3D)");
   if (!(c->mu_w > 0) || !(c->mu_g > 0)) return fail(CRV_EINVAL, "viscosities must be > 0");
   if (!(c->relperm_exp >= 1)) return fail(CRV_EINVAL, "relperm_exp must be >= 1");
   if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) ||
@@ -365,14 +372,24 @@ struct Solver : SolverBase {
     std::vector<double> dst, lam;
     dst_table(g.m, g.mp, dst, lam);
     if ((s = upload(b.dst, dst.data(), dst.size()))) return s;
-    lam.resize(g.m);
-    if ((s = upload_raw(b.shifts, lam))) return s;
+    // shift of each line: lambda_j (2D), lambda_j + lambda_k (3D, padded
+    // modes get a harmless positive shift; their lines hold zeros)
+    std::vector<double> shifts(size_t(gram_lines(g)));
+    if (g.dim == 2) {
+      for (int j = 0; j < g.m; ++j) shifts[j] = lam[j];
+    } else {
+      for (int k = 0; k < g.m; ++k)
+        for (int j = 0; j < g.mp; ++j) shifts[size_t(k) * g.mp + j] = lam[k] + (j < g.m ? lam[j] : 2.0);
+    }
+    if ((s = upload_raw(b.shifts, shifts))) return s;
     std::vector<double> band = mass_band(g.ne, g.r);
     if ((s = upload_raw(b.band, band))) return s;
 
     // float64 factorisations on the device (eq. 14 mass band, eq. 28 Gram lines)
     launch_factor_band<Real>(b.band, g.nb, g.r, b.band_work, b.m_lt, b.m_invd, b.status, st);
-    launch_factor_shifted<Real>(b.shifts, g.m, g.m, g.mp, 1.0, b.g_lt, b.g_invd, st);
+    // G = L5 in 2D, h L7 in 3D
+    launch_factor_shifted<Real>(b.shifts, int(gram_lines(g)), g.m, g.mp, g.dim == 3 ? h : 1.0,
+                                b.g_lt, b.g_invd, st);
     if ((s = check_launch())) return s;
     refresh();
     pack();
@@ -393,25 +410,51 @@ struct Solver : SolverBase {
 
   // q = G^-1 res: DST-I along y (product with the orthonormal sine basis),
   // shifted tridiagonal solves along x, inverse DST-I along y (eq. 26-28).
+  // 3D: DST-I along z (one product over all (y, x) columns) and along y (one
+  // product per z plane), lines along x with shift lambda_j + lambda_k.
   void gram_solve() {
+    const int mp = g.mp;
+    const int64_t mp2 = int64_t(mp) * mp;
+    if (g.dim == 3) {
+      tb(CRV_K_GRAM_DST);
+      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.res, int(mp2), b.qhat, int(mp2), st);
+      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st);
+      te();
+      tb(CRV_K_GRAM_LINES);
+      launch_band_rows<Real>(b.rhat, b.qhat, g.m, int(gram_lines(g)), mp, 1, b.g_lt, b.g_invd, mp,
+                             mp, st);
+      te();
+      tb(CRV_K_GRAM_DST);
+      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st);
+      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.rhat, int(mp2), b.q, int(mp2), st);
+      te();
+      return;
+    }
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.res, g.mp, b.rhat, g.mp, st);
+    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.res, mp, b.rhat, mp, st);
     te();
     tb(CRV_K_GRAM_LINES);
-    launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, g.mp, 1, b.g_lt, b.g_invd, g.mp, g.mp, st);
+    launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, mp, 1, b.g_lt, b.g_invd, mp, mp, st);
     te();
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(g.mp, g.mp, g.mp, b.dst, g.mp, b.qhat, g.mp, b.q, g.mp, st);
+    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, b.q, mp, st);
     te();
   }
 
-  // dst = (M^x (x) M^y)^-1 src (eq. 14): x-lines src -> dst, then y-lines in place.
+  // dst = (M^x (x) M^y [(x) M^z])^-1 src (eq. 14): x-lines src -> dst, then
+  // y-lines (per z plane) and z-lines in place.
   void mass_solve(const Real* src, Real* dst) {
+    const int nb = g.nb;
+    const int64_t nb2 = int64_t(nb) * nb;
     tb(CRV_K_MASS_ROWS);
-    launch_band_rows<Real>(src, dst, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 0, 0, st);
+    launch_band_rows<Real>(src, dst, nb, g.dim == 3 ? int(nb2) : nb, nb, g.r, b.m_lt, b.m_invd, 0,
+                           0, st);
     te();
     tb(CRV_K_MASS_COLS);
-    launch_band_cols<Real>(dst, dst, g.nb, g.nb, g.nb, g.r, b.m_lt, b.m_invd, 1, 0, st);
+    launch_band_cols<Real>(dst, dst, nb, nb, nb, g.r, b.m_lt, b.m_invd, g.dim == 3 ? nb : 1,
+                           g.dim == 3 ? nb2 : 0, st);
+    if (g.dim == 3)
+      launch_band_cols<Real>(dst, dst, nb, int(nb2), nb2, g.r, b.m_lt, b.m_invd, 1, 0, st);
     te();
   }
 
@@ -690,16 +733,19 @@ struct Solver : SolverBase {
   }
 
   crv_status gram_solve_host(const double* res, double* q) override {
-    std::vector<double> pad(size_t(g.mp) * g.mp, 0.0);
-    for (int j = 0; j < g.m; ++j)
-      for (int i = 0; i < g.m; ++i) pad[size_t(j) * g.mp + i] = res[size_t(j) * g.m + i];
+    const size_t m = g.m, mp = g.mp, nk = g.dim == 3 ? m : 1;
+    std::vector<double> pad(size_t(ipow(g.mp, g.dim)), 0.0);
+    for (size_t k = 0; k < nk; ++k)
+      for (size_t j = 0; j < m; ++j)
+        for (size_t i = 0; i < m; ++i) pad[(k * mp + j) * mp + i] = res[(k * m + j) * m + i];
     crv_status s = upload(b.res, pad.data(), pad.size());
     if (s) return s;
     gram_solve();
     if ((s = check_launch())) return s;
     if ((s = download(pad.data(), b.q, pad.size()))) return s;
-    for (int j = 0; j < g.m; ++j)
-      for (int i = 0; i < g.m; ++i) q[size_t(j) * g.m + i] = pad[size_t(j) * g.mp + i];
+    for (size_t k = 0; k < nk; ++k)
+      for (size_t j = 0; j < m; ++j)
+        for (size_t i = 0; i < m; ++i) q[(k * m + j) * m + i] = pad[(k * mp + j) * mp + i];
     return CRV_OK;
   }
 

@@ -26,8 +26,6 @@ def test_every_declared_symbol_is_exported():
 
 @pytest.mark.parametrize("dim,width,hidden", [(2, 32, 3), (2, 64, 4), (2, 128, 4), (3, 128, 4)])
 def test_param_count_matches_layout(dim, width, hidden):
-    if dim == 3:
-        pytest.skip("3D path not built")
     cfg = crv.config(dim=dim, width=width, hidden=hidden)
     assert crv.param_count(cfg) == inputs.n_params(dim, width, hidden)
     assert crv.param_count(cfg) == inputs.theta_xavier(dim, width, hidden, 0).size
@@ -36,7 +34,8 @@ def test_param_count_matches_layout(dim, width, hidden):
 def test_config_validation_errors():
     bad = [dict(dim=4), dict(n_elem=2), dict(degree=5), dict(width=48), dict(hidden=0),
            dict(mu_g=0.0), dict(lr=-1.0), dict(well_radius=0.0), dict(substeps=0),
-           dict(precision=7)]
+           dict(precision=7), dict(dim=3, n_elem=300),
+           dict(dim=3, width=64, hidden=3, precision="bf16")]
     for kw in bad:
         cfg = crv.config(**kw)
         with pytest.raises(crv.CrvError) as ei:
@@ -50,6 +49,15 @@ def test_workspace_grows_with_grid_and_precision():
     c = crv.workspace_size(crv.config(n_elem=128, width=64, hidden=4, precision="fp64"))
     assert 0 < a < b < c
     assert a % 256 == 0
+
+
+def test_workspace_3d():
+    """3D interior arrays are padded to mp^3 and the Gram lines to m*mp."""
+    w2 = crv.workspace_size(crv.config(dim=2, n_elem=128, width=128, hidden=4, precision="bf16"))
+    w3 = crv.workspace_size(crv.config(dim=3, n_elem=128, width=128, hidden=4, precision="bf16"))
+    assert w3 > w2
+    # nodal, coefficient and interior arrays alone
+    assert w3 > 4 * (10 * 129 ** 3 + 3 * 130 ** 3 + 5 * 128 ** 3)
 
 
 def test_defaults():
