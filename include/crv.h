@@ -148,13 +148,21 @@ crv_status crv_get_fields(crv_ctx* ctx, double* p_nodal, double* s_coefs, double
 crv_status crv_loss_grad(crv_ctx* ctx, double* loss, double* dtheta, double* dlogperm);
 
 /* Training state for checkpoint/resume: theta, Adam m and v (n_params
- * each, nullable) and the Adam step count. */
+ * each, nullable) and the Adam step count.  crv_set_state with t = -1 keeps
+ * the current step count (replacing theta alone, as the differentiation
+ * form does); t < -1 is CRV_EINVAL. */
 crv_status crv_get_state(crv_ctx* ctx, double* theta, double* adam_m, double* adam_v, int64_t* t);
 crv_status crv_set_state(crv_ctx* ctx, const double* theta, const double* adam_m,
                          const double* adam_v, int64_t t);
 
 /* Replace the saturation coefficients (nb^d) and refresh alpha. */
 crv_status crv_set_saturation(crv_ctx* ctx, const double* s_coefs);
+
+/* Replace the nodal log-permeability ((N+1)^d, host, finite, else
+ * CRV_EINVAL) and refresh alpha = lambda_t(S) K (eq. 23, nodal form); the
+ * saturation transport reads the same K.  Used by the differentiation form
+ * to evaluate the loss at a new log K. */
+crv_status crv_set_log_perm(crv_ctx* ctx, const double* log_perm);
 
 /* Loss of each Adam iteration so far (oldest first, at most cap entries,
  * the most recent ones when more were run); *n receives the count. */

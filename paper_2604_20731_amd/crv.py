@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
 EXPORTED = [
     "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
     "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_get_fields", "crv_loss_grad",
-    "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_loss_history",
+    "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
     "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
     "crv_saturation_substeps", "crv_profile_enable", "crv_profile_read", "crv_destroy",
     "crv_last_error",
@@ -76,6 +76,7 @@ def _load() -> C.CDLL:
         "crv_get_state": [vp, dp, dp, dp, C.POINTER(C.c_int64)],
         "crv_set_state": [vp, dp, dp, dp, C.c_int64],
         "crv_set_saturation": [vp, dp],
+        "crv_set_log_perm": [vp, dp],
         "crv_loss_history": [vp, dp, C.c_int, C.POINTER(C.c_int)],
         "crv_gram_solve": [vp, dp, dp],
         "crv_mass_solve": [vp, dp, dp],
@@ -227,7 +228,24 @@ class Scenario:
                                  _dp(None if v is None else _f64(v)), int(t)))
 
     def set_saturation(self, s_coefs):
-        _check(LIB.crv_set_saturation(self.ctx, _dp(_f64(s_coefs).ravel())))
+        a = _f64(s_coefs).ravel()
+        if a.size != self.nc:
+            raise ValueError(f"s_coefs has {a.size} entries, expected {self.nc}")
+        _check(LIB.crv_set_saturation(self.ctx, _dp(a)))
+
+    def set_log_perm(self, log_perm):
+        """Replace the nodal log-permeability; alpha follows."""
+        a = _f64(log_perm).ravel()
+        if a.size != self.nn:
+            raise ValueError(f"log_perm has {a.size} entries, expected {self.nn}")
+        _check(LIB.crv_set_log_perm(self.ctx, _dp(a)))
+
+    def set_theta(self, theta):
+        """Replace the network parameters, keeping the Adam moments and step count."""
+        a = _f64(theta).ravel()
+        if a.size != self.P:
+            raise ValueError(f"theta has {a.size} entries, expected {self.P}")
+        _check(LIB.crv_set_state(self.ctx, _dp(a), None, None, -1))
 
     def loss_history(self, cap: int = 1 << 16) -> np.ndarray:
         out = np.empty(cap)

@@ -249,6 +249,7 @@ struct SolverBase {
   virtual crv_status get_state(double*, double*, double*, int64_t*) = 0;
   virtual crv_status set_state(const double*, const double*, const double*, int64_t) = 0;
   virtual crv_status set_saturation(const double*) = 0;
+  virtual crv_status set_log_perm(const double*) = 0;
   virtual crv_status loss_history(double*, int, int*) = 0;
   virtual crv_status gram_solve_host(const double*, double*) = 0;
   virtual crv_status mass_solve_host(const double*, double*) = 0;
@@ -696,7 +697,7 @@ struct Solver : SolverBase {
   }
 
   crv_status set_state(const double* th, const double* m, const double* v, int64_t t) override {
-    if (t < 0) return fail(CRV_EINVAL, "t must be >= 0");
+    if (t < -1) return fail(CRV_EINVAL, "t must be >= 0 (or -1 to keep it)");
     crv_status s;
     CRV_HIP(hipStreamSynchronize(st));
     if (th && (s = upload(b.theta, th, size_t(P)))) return s;
@@ -704,10 +705,25 @@ struct Solver : SolverBase {
     if (v && (s = upload(b.av, v, size_t(P)))) return s;
     pack();
     if ((s = check_launch())) return s;
-    long long tt = t;
-    CRV_HIP(hipMemcpy(b.t_dev, &tt, sizeof(tt), hipMemcpyHostToDevice));
-    pretrained = true;
+    if (t >= 0) {
+      long long tt = t;
+      CRV_HIP(hipMemcpy(b.t_dev, &tt, sizeof(tt), hipMemcpyHostToDevice));
+      pretrained = true;
+    }
     return CRV_OK;
+  }
+
+  crv_status set_log_perm(const double* lk) override {
+    std::vector<double> perm(nn);
+    for (size_t i = 0; i < nn; ++i) {
+      if (!std::isfinite(lk[i])) return fail(CRV_EINVAL, "log_perm has non-finite entries");
+      perm[i] = std::exp(lk[i]);
+    }
+    CRV_HIP(hipStreamSynchronize(st));
+    crv_status s = upload(b.perm, perm.data(), nn);
+    if (s) return s;
+    refresh();
+    return check_launch();
   }
 
   crv_status set_saturation(const double* sc) override {
@@ -939,6 +955,12 @@ crv_status crv_set_saturation(crv_ctx* c, const double* s_coefs) {
   CRV_CTX(c);
   if (!s_coefs) return fail(CRV_EINVAL, "s_coefs is NULL");
   return sv.set_saturation(s_coefs);
+}
+
+crv_status crv_set_log_perm(crv_ctx* c, const double* log_perm) {
+  CRV_CTX(c);
+  if (!log_perm) return fail(CRV_EINVAL, "log_perm is NULL");
+  return sv.set_log_perm(log_perm);
 }
 
 crv_status crv_loss_history(crv_ctx* c, double* out, int cap, int* n) {

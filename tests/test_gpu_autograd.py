@@ -1,0 +1,65 @@
+"""Differentiation form: torch autograd through the libcrv loss (CRVLoss)
+against the oracle's analytic gradients (themselves pinned to central
+differences on the CPU), at parameters and log K away from the initial
+ones.  Relative errors over 32 seeded coordinates and over the whole
+vectors."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import oracle_for, problem, rel, say, scenario_for
+
+pytestmark = pytest.mark.gpu
+
+WELLS3 = np.array([[0.25, 0.25, 1.0], [0.75, 0.75, -1.0]])
+
+
+def _check(prob, prec, tol, n_coords=32):
+    from paper_2604_20731_amd.autograd import crv_loss
+    sc = scenario_for(prob, prec)
+    orc = oracle_for(prob)
+    rng = np.random.default_rng(7)
+    th = prob.theta0 + 0.05 * rng.standard_normal(prob.theta0.size)
+    lk = prob.log_perm + 0.1 * rng.standard_normal(prob.log_perm.shape)
+    t_before = sc.get_state()[3]
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    log_perm = torch.tensor(lk, dtype=torch.float64, requires_grad=True)
+    loss = crv_loss(theta, log_perm, sc)
+    (2.0 * loss).backward()          # the incoming gradient scales both
+    orc.perm = np.exp(lk)
+    orc.refresh()
+    lref, gref = orc.loss_and_grad(th)
+    glref = orc.loss_grad_logperm(th)
+    g = theta.grad.numpy() / 2.0
+    gl = log_perm.grad.numpy() / 2.0
+    it = rng.choice(th.size, size=n_coords, replace=False)
+    ik = rng.choice(lk.size, size=n_coords, replace=False)
+    e = dict(loss=abs(float(loss.detach()) - lref) / abs(lref), dtheta32=rel(g[it], gref[it]),
+             dlogK32=rel(gl.ravel()[ik], glref.ravel()[ik]), dtheta=rel(g, gref),
+             dlogK=rel(gl, glref))
+    say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert all(v < tol for v in e.values()), e
+    assert sc.get_state()[3] == t_before      # training state untouched
+
+
+@pytest.mark.parametrize("prec,width,tol", [("fp64", 16, 1e-10), ("fp32", 16, 1e-4),
+                                            ("fp32", 32, 1e-4), ("bf16x3", 32, 1e-4)])
+def test_autograd_17cubed(prec, width, tol):
+    """17^3 nodes, 4 hidden layers (matrix cores for width 32)."""
+    say("autograd 17^3", prec, width)
+    prob = problem("c5", n_elem=16, width=width, hidden=4 if width == 32 else 2, wells=WELLS3)
+    _check(prob, prec, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_autograd_2d(prec, tol):
+    say("autograd 2D c1", prec)
+    _check(problem("c1"), prec, tol)
+
+
+@pytest.mark.timeout(600)
+def test_autograd_c5_full():
+    """The 3D workload at full size: 129^3 nodes, 3->4x128->1, two vertical
+    injectors, FP32 network."""
+    say("autograd c5 129^3 fp32")
+    _check(problem("c5"), "fp32", 1e-4)

@@ -69,3 +69,36 @@ def test_pretrain_and_step_invariants():
     assert np.all(u[0] == 0) and np.all(u[-1] == 0) and np.all(u[:, 0] == 0)
     assert s.shape == (p.n_elem + 2,) * 2 and sn.shape == (p.n_elem + 1,) * 2
     assert len(o.loss_history) == 30 + o.adam_iters
+
+
+def _tiny3d():
+    wells = np.array([[0.5, 0.5, 1.0]])
+    p = inputs.make_problem("c5", n_elem=4, width=8, hidden=2, wells=wells)
+    return p, Oracle(p.dim, p.n_elem, p.degree, p.width, p.hidden, p.log_perm,
+                     p.porosity, p.wells, p.theta0)
+
+
+def test_gradients_3d_match_central_differences():
+    """3D (h L7 Gram, h-weighted stencil): dLOSS/dtheta and dLOSS/dlogK
+    against central differences of the whole chain."""
+    p, o = _tiny3d()
+    th = o.theta + 0.05 * np.random.default_rng(3).standard_normal(o.theta.size)
+    _, g = o.loss_and_grad(th)
+    eps = 1e-6
+    for k in np.random.default_rng(4).choice(th.size, size=12, replace=False):
+        e = np.zeros_like(th); e[k] = eps
+        fd = (o.loss_and_grad(th + e)[0] - o.loss_and_grad(th - e)[0]) / (2 * eps)
+        assert abs(g[k] - fd) < 1e-7 * max(1.0, abs(fd)), k
+    gl = o.loss_grad_logperm(th)
+    base = o.perm.copy()
+    for k in np.random.default_rng(5).choice(base.size, size=12, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            lk = np.log(base).ravel().copy(); lk[k] += sgn * eps
+            o.perm = np.exp(lk).reshape(base.shape)
+            o.refresh()
+            vals.append(o.loss_and_grad(th)[0])
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(gl.ravel()[k] - fd) < 1e-7 * max(1.0, abs(fd)), k
+    o.perm = base
+    o.refresh()
