@@ -177,6 +177,9 @@ def main():
     ap.add_argument("--serve", type=int, default=64, help="serving arrivals (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times): the "
+                         "reference kernel that scales the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -185,6 +188,16 @@ def main():
 
     import torch
     from paper_2604_20731_amd import inputs
+
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
+        return
 
     prob = inputs.make_problem(args.workload, seed=0)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)

@@ -353,6 +353,11 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
   };
 
   for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
+    // the weight fragments are re-read from cache each step: an opaque copy
+    // of the pointer keeps the compiler from hoisting every fragment of every
+    // layer into registers for the whole loop (which only spills them)
+    const typename T::felem* fr = frag;
+    asm volatile("" : "+s"(fr));
     const int64_t p = step * NB + col;
     float z[DIM];
     bool interior = false;
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     float d[NR];
-    forward_tile<W, L, MODE, DIM>(sp, frag, z, g, lane, d, sink);
+    forward_tile<W, L, MODE, DIM>(sp, fr, z, g, lane, d, sink);
     const float gv = valid ? gu[p] : 0.f;
     if (g == 0) {
       Gs[col] = gv;
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
           for (int i = 0; i < 16; ++i) c2[i] = 0.f;
 #pragma unroll
           for (int ks = 0; ks < NKS; ++ks)
-            c2 = T::mma(T::frag(frag + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
+            c2 = T::mma(T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const float hv = float(Hall[((l - 2) * W + cfeat(mb * 16 + i, g)) * LD + col]);
