@@ -60,6 +60,37 @@ def algorithmic_work(name, prob, n_launch_units):
     return tab.get(name)
 
 
+NET_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+
+
+def kernel_symbol(name, prob, precision):
+    """Device symbol of the launch the event timer calls `name` (matrix-core
+    network kernels only; 4 waves per backward block)."""
+    if name == "mlp_bwd" and precision in NET_MODE:
+        return f"crv::k_mlp_bwd_mfma<{prob.width}, {prob.hidden}, {NET_MODE[precision]}, {prob.dim}, 4>"
+    if name == "mlp_fwd" and precision in NET_MODE:
+        return f"crv::k_mlp_fwd_mfma<{prob.width}, {prob.hidden}, {NET_MODE[precision]}, {prob.dim}>"
+    return None
+
+
+def measured_traffic(symbol, table=os.path.join(ROOT, "profiles", "b512_hbm_traffic.md")):
+    """HBM bytes per launch of `symbol` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when absent or when the kernel's source file
+    has changed since the counters were taken (sha256 prefix recorded)."""
+    import hashlib
+    if symbol is None or not os.path.exists(table):
+        return None
+    for line in open(table):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0] == f"`{symbol}`":
+            src = os.path.join(ROOT, "paper_2604_20731_amd", "csrc", cells[1])
+            if not os.path.exists(src):
+                return None
+            now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            return float(cells[5]) if now == cells[2] else None
+    return None
+
+
 def cfl_dt_from_pressure(p, perm, poro, ne, n_exp=2.0, mu_g=0.1, cfl=0.5):
     """dt = cfl h phi_min / (max lambda_g' max |K grad_+ p|) with the trained
     network pressure standing in for the direct solve."""
@@ -222,6 +253,7 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         work = algorithmic_work(dom, prob, 1)
         us = kernels[dom]["us_per_launch"]
+        traffic = measured_traffic(kernel_symbol(dom, prob, args.precision))
         if work:
             amount, unit = work
             if unit == "flop":
@@ -230,13 +262,13 @@ def main():
                 achieved = amount / (us * 1e-6) / 1e12
                 roofline = {"kernel": dom, "bound": "alu" if args.precision == "fp64" else "mfma",
                             "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                            "frac": achieved / peak, "traffic": None, "work_per_launch": amount,
+                            "frac": achieved / peak, "traffic": traffic, "work_per_launch": amount,
                             "us_per_launch": us}
             else:
                 achieved = amount / (us * 1e-6) / 1e9
                 roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved,
                             "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                            "frac": achieved / PEAK["hbm_gbs"], "traffic": None,
+                            "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic,
                             "work_per_launch": amount, "us_per_launch": us}
     cpu = None
     if not args.no_cpu_baseline:
