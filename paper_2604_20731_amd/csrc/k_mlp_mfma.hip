@@ -2,34 +2,36 @@
 //
 // Three arithmetic modes for the hidden-to-hidden products (float32
 // accumulation in all of them):
-//   F32   v_mfma_f32_32x32x2f32 on float32 operands;
-//   BF16  v_mfma_f32_32x32x16_bf16 on bf16-rounded operands;
+//   F32   v_mfma_f32_16x16x4f32 on float32 operands;
+//   BF16  v_mfma_f32_16x16x32_bf16 on bf16-rounded operands;
 //   X3    split bf16: every operand a = a_hi + a_lo with a_hi = bf16(a),
 //         a_lo = bf16(a - a_hi), and a.b ~ a_hi.b_hi + a_hi.b_lo + a_lo.b_hi
 //         (three bf16 MFMAs, about 2^-16 relative error per product).
 // The first layer (K = d) and the output (N = 1) run on the vector ALUs in
 // float32, as do tanh and its derivative.
 //
-// Layout.  Activations are kept transposed, features x nodes, in 32 x 32
-// accumulator tiles: a wavefront owns 32 nodes (one per lane column) and lane
-// group g = lane/32 holds, for every 32-feature block mb, the 16 features
-// 32 mb + 8 (i/4) + 4 g + (i%4), i = 0..15 (the accumulator layout of the
-// 32x32 MFMA).  A layer's output registers are directly the B operand of the
-// next layer's product: K-step ks takes the lane's registers
-// ks*S .. ks*S+S-1 (S = 8 for bf16, 1 for fp32), so the contraction index
-// runs over features in a lane-dependent order.  That order is folded into
-// the packed weight fragments, so no data moves between layers.  Bias is
-// added by initialising the accumulators with it.
+// Layout.  Activations are kept transposed, features x nodes, in 16 x 16
+// accumulator tiles: a wavefront owns 16 nodes (lane column r = lane%16) and
+// lane group q = lane/16 holds, for every 16-feature block mb, the four
+// features 16 mb + 4 q + i, i = 0..3 (the accumulator layout of the 16x16
+// MFMA).  A layer's output registers are directly the B operand of the next
+// layer's product: K-step ks takes the lane's registers ks*S .. ks*S+S-1
+// (S = 8 for bf16, 1 for fp32), so the contraction index runs over features
+// in a lane-dependent order.  That order is folded into the packed weight
+// fragments, so no data moves between layers.  Bias is added by initialising
+// the accumulators with it.  Sixteen nodes per wave keep the per-lane state
+// (activations, deltas, weight-gradient tiles) small enough for two or more
+// waves per SIMD, so one wave's tanh work overlaps another's matrix products.
 //
 // Backward.  delta_{l-1} = (W_l^T delta_l) (1 - h_{l-1}^2) uses the same
 // register chain with transposed fragments.  dW_l = sum_nodes delta_l
 // h_{l-1}^T contracts over nodes: the waves of a block write delta_l
 // transposed into LDS next to the recomputed activations (also transposed),
-// and each wave accumulates its share of the dW_l output tiles with MFMAs
-// over the block's nodes.  Biases, first-layer and output weights are summed
-// over nodes inside registers by butterfly reduce-scatters across the 32 node
-// lanes.  All accumulators persist across the block's node tiles; each block
-// writes one partial gradient row, reduced in a fixed order afterwards.
+// and each wave accumulates its share of the 16x16 dW_l output tiles with
+// MFMAs over the block's nodes.  Biases, first-layer and output weights are
+// summed over nodes per thread from LDS.  All accumulators persist across the
+// block's node tiles; each block writes one partial gradient row, reduced in
+// a fixed order afterwards.
 #include <algorithm>
 
 #include "kernels.h"
@@ -37,7 +39,6 @@
 namespace crv {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <int M>
@@ -45,32 +46,36 @@ struct MM;
 
 template <>
 struct MM<NET_F32> {
-  static constexpr int S = 1, KS = 2, NP = 1;  // values per lane, K per MFMA, fragment planes
+  static constexpr int S = 1, KS = 4, NP = 1;  // values per lane, K per MFMA, fragment planes
   using felem = float;                          // fragment storage
   using lelem = float;                          // LDS storage of activations / deltas
-  static constexpr int PAD = 1;
+  static constexpr int PAD = 4;
   using op = float;
-  __device__ static inline f32x16_t mma(op a, op b, f32x16_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static constexpr int NPL = 1;                 // LDS planes per value
   __device__ static inline op frag(const felem* p) { return *p; }
-  __device__ static inline op lds(const lelem* p) { return *p; }
   __device__ static inline op from(const float* v) { return v[0]; }
   __device__ static inline void put(felem* p, float w) { p[0] = w; }
+  __device__ static inline op lds_op(const lelem* p, int) { return *p; }
+  __device__ static inline float lds_get(const lelem* p, int) { return *p; }
+  __device__ static inline void lds_put(lelem* p, int, float v) { *p = v; }
+  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int) { *p = o; }
 };
 
 template <>
 struct MM<NET_BF16> {
-  static constexpr int S = 8, KS = 16, NP = 1;
+  static constexpr int S = 8, KS = 32, NP = 1;
   using felem = __bf16;
   using lelem = __bf16;
   static constexpr int PAD = 8;
   using op = bf16x8_t;
-  __device__ static inline f32x16_t mma(op a, op b, f32x16_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  static constexpr int NPL = 1;
   __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
-  __device__ static inline op lds(const lelem* p) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline op from(const float* v) {
     op o;
 #pragma unroll
@@ -78,23 +83,31 @@ struct MM<NET_BF16> {
     return o;
   }
   __device__ static inline void put(felem* p, float w) { p[0] = (__bf16)w; }
+  __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
+  __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
+  __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
+  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { *p = o[v]; }
 };
 
 struct SplitOp {
   bf16x8_t h, l;
 };
 
+// LDS holds X3 activations and deltas already split: a hi plane and, `plane`
+// elements further, a lo plane, so the weight-gradient products read ready
+// operands and the split is done once per value (by the writer).
 template <>
 struct MM<NET_X3> {
-  static constexpr int S = 8, KS = 16, NP = 2;
+  static constexpr int S = 8, KS = 32, NP = 2;
   using felem = __bf16;
-  using lelem = float;
-  static constexpr int PAD = 4;
+  using lelem = __bf16;
+  static constexpr int PAD = 8;
+  static constexpr int NPL = 2;
   using op = SplitOp;
-  __device__ static inline f32x16_t mma(const op& a, const op& b, f32x16_t c) {
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.l, b.h, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h, b.l, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h, b.h, c, 0, 0, 0);
+  __device__ static inline f32x4_t mma(const op& a, const op& b, f32x4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
   }
   // fragments hold the hi plane, then (64*S further) the lo plane
   __device__ static inline op frag(const felem* p) {
@@ -110,27 +123,34 @@ struct MM<NET_X3> {
     }
     return o;
   }
-  __device__ static inline op lds(const lelem* p) {
-    const f32x4_t a = *reinterpret_cast<const f32x4_t*>(p);
-    const f32x4_t b = *reinterpret_cast<const f32x4_t*>(p + 4);
-    const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    return from(v);
-  }
   __device__ static inline void put(felem* p, float w) {
     const __bf16 h = (__bf16)w;
     p[0] = h;
     p[64 * S] = (__bf16)(w - float(h));
   }
+  __device__ static inline op lds_op(const lelem* p, int plane) {
+    return op{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + plane)};
+  }
+  __device__ static inline float lds_get(const lelem* p, int plane) {
+    return float(p[0]) + float(p[plane]);
+  }
+  __device__ static inline void lds_put(lelem* p, int plane, float v) {
+    const __bf16 h = (__bf16)v;
+    p[0] = h;
+    p[plane] = (__bf16)(v - float(h));
+  }
+  __device__ static inline void lds_put_elem(lelem* p, int plane, const op& o, int v) {
+    p[0] = o.h[v];
+    p[plane] = o.l[v];
+  }
 };
 
-// feature held by lane group g in its flat accumulator register t (t = 16 mb + i)
-__host__ __device__ inline int cfeat(int t, int g) {
-  return 32 * (t >> 4) + 8 * ((t & 15) >> 2) + 4 * g + (t & 3);
-}
-// inverse: register t and lane group g holding feature f
-__host__ __device__ inline void cfeat_inv(int f, int* t, int* g) {
-  *g = (f >> 2) & 1;
-  *t = 16 * (f >> 5) + 4 * ((f & 31) >> 3) + (f & 3);
+// feature held by lane group q in its flat accumulator register t (t = 4 mb + i)
+__host__ __device__ inline int cfeat(int t, int q) { return 16 * (t >> 2) + 4 * q + (t & 3); }
+// inverse: register t and lane group q holding feature f
+__host__ __device__ inline void cfeat_inv(int f, int* t, int* q) {
+  *q = (f >> 2) & 3;
+  *t = 4 * (f >> 4) + (f & 3);
 }
 
 __host__ __device__ inline int64_t off_layer(int l, int dim, int W) {
@@ -139,14 +159,14 @@ __host__ __device__ inline int64_t off_layer(int l, int dim, int W) {
 }
 
 // Packed fragments: for hidden-to-hidden layer hl (layer l = hl + 2), block mb
-// and K-step ks, lane (r = lane%32, g = lane/32) holds S consecutive values
-//   forward  (dir 0): W_l[32 mb + r][cfeat(ks*S + v, g)]
-//   backward (dir 1): W_l[cfeat(ks*S + v, g)][32 mb + r]      (= W_l^T)
-// at (((hl*2 + dir) * (W/32) + mb) * (W/KS) + ks) * NP*64*S + plane*64*S + lane*S + v.
+// and K-step ks, lane (r = lane%16, q = lane/16) holds S consecutive values
+//   forward  (dir 0): W_l[16 mb + r][cfeat(ks*S + v, q)]
+//   backward (dir 1): W_l[cfeat(ks*S + v, q)][16 mb + r]      (= W_l^T)
+// at (((hl*2 + dir) * (W/16) + mb) * (W/KS) + ks) * NP*64*S + plane*64*S + lane*S + v.
 template <int MODE>
 __host__ __device__ inline int64_t frag_index(int hl, int dir, int mb, int ks, int lane, int v, int W) {
   using T = MM<MODE>;
-  return (((((int64_t(hl) * 2 + dir) * (W / 32) + mb) * (W / T::KS) + ks) * T::NP) * 64 + lane) * T::S + v;
+  return (((((int64_t(hl) * 2 + dir) * (W / 16) + mb) * (W / T::KS) + ks) * T::NP) * 64 + lane) * T::S + v;
 }
 
 template <int MODE>
@@ -162,13 +182,13 @@ __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, i
   const int nks = W / T::KS;
   const int ks = int(rest % nks);
   rest /= nks;
-  const int mb = int(rest % (W / 32));
-  rest /= (W / 32);
+  const int mb = int(rest % (W / 16));
+  rest /= (W / 16);
   const int dir = int(rest % 2);
   const int hl = int(rest / 2);
-  const int r = lane & 31, g = lane >> 5;
-  const int a = 32 * mb + r;                 // row of the A operand
-  const int k = cfeat(ks * T::S + v, g);     // contraction feature
+  const int r = lane & 15, q = lane >> 4;
+  const int a = 16 * mb + r;                 // row of the A operand
+  const int k = cfeat(ks * T::S + v, q);     // contraction feature
   const float* Wl = th + off_layer(hl + 2, dim, W);
   const float w = dir == 0 ? Wl[int64_t(a) * W + k] : Wl[int64_t(k) * W + a];
   T::put(frag + frag_index<MODE>(hl, dir, mb, ks, lane, v, W), w);
@@ -213,28 +233,27 @@ struct NoSink {
   __device__ void operator()(int, const H&) const {}
 };
 
-// Forward of one 32-node tile held by this wave.  Hidden layer l's
-// activations (accumulator layout, float32) go to sink(l, h) as soon as they
-// are computed; on return h holds the last hidden layer.
+// Forward of one 16-node tile held by this wave.  The operands that hidden
+// layer l (0-based, l < L-1) feeds into the next product go to sink(l, bop)
+// as soon as they are built; on return h holds the last hidden layer.
 template <int W, int L, int MODE, int DIM, typename Sink>
 __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::felem* __restrict__ frag,
-                                    const float* z, int g, int lane, float (&h)[W / 2],
+                                    const float* z, int q, int lane, float (&h)[W / 4],
                                     const Sink& sink) {
   using T = MM<MODE>;
   using SM = Small<W, L, DIM>;
-  constexpr int NR = W / 2, NKS = W / T::KS, NMB = W / 32;
+  constexpr int NR = W / 4, NKS = W / T::KS, NMB = W / 16;
   {
     const float* W1 = sp + SM::W1;
     const float* b1 = sp + SM::B1;
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
-      const int f = cfeat(t, g);
+      const int f = cfeat(t, q);
       float a = b1[f];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) a += W1[f * DIM + c] * z[c];
       h[t] = tanh_fast(a);
     }
-    sink(0, h);
   }
 #pragma unroll
   for (int l = 1; l < L; ++l) {
@@ -242,19 +261,19 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
     typename T::op bop[NKS];
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&h[ks * T::S]);
-    f32x16_t acc[NMB];
+    sink(l - 1, bop);
+    f32x4_t acc[NMB];
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[mb][i] = bl[cfeat(mb * 16 + i, g)];
+      for (int i = 0; i < 4; ++i) acc[mb][i] = bl[cfeat(mb * 4 + i, q)];
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
         acc[mb] = T::mma(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
 #pragma unroll
-    for (int t = 0; t < NR; ++t) h[t] = tanh_fast(acc[t >> 4][t & 15]);
-    sink(l, h);
+    for (int t = 0; t < NR; ++t) h[t] = tanh_fast(acc[t >> 2][t & 3]);
   }
 }
 
@@ -262,34 +281,35 @@ template <int W, int L, int MODE, int DIM>
 __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __restrict__ th,
                                                       const typename MM<MODE>::felem* __restrict__ frag,
                                                       float* __restrict__ u, long long* t_bump) {
-  constexpr int NR = W / 2;
+  constexpr int NR = W / 4;
   using SM = Small<W, L, DIM>;
   if (t_bump && blockIdx.x == 0 && threadIdx.x == 0) *t_bump = *t_bump + 1;  // new Adam iteration
   __shared__ float sp[SM::SIZE];
   SM::stage(th, sp, threadIdx.x, blockDim.x);
   __syncthreads();
-  const int lane = threadIdx.x & 63, g = lane >> 5, n = lane & 31;
+  const int lane = threadIdx.x & 63, q = lane >> 4, n = lane & 15;
   const int64_t total = ipow(geo.n, DIM);
   const int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const int64_t p = tile * 32 + n;
-  if (tile * 32 >= total) return;  // whole wave leaves together
+  const int64_t p = tile * 16 + n;
+  if (tile * 16 >= total) return;  // whole wave leaves together
   float z[DIM];
   bool interior = false;
   if (p < total) node_z<DIM>(p, geo.n, geo.ne, z, &interior);
   else
     for (int c = 0; c < DIM; ++c) z[c] = 0.f;
   float h[NR];
-  forward_tile<W, L, MODE, DIM>(sp, frag, z, g, lane, h, NoSink());
+  forward_tile<W, L, MODE, DIM>(sp, frag, z, q, lane, h, NoSink());
   const float* wo = sp + SM::WO;
   float s = 0.f;
 #pragma unroll
-  for (int t = 0; t < NR; ++t) s += wo[cfeat(t, g)] * h[t];
+  for (int t = 0; t < NR; ++t) s += wo[cfeat(t, q)] * h[t];
+  s += __shfl_xor(s, 16, 64);
   s += __shfl_xor(s, 32, 64);
-  if (g == 0 && p < total) u[p] = interior ? s + wo[W] : 0.f;
+  if (q == 0 && p < total) u[p] = interior ? s + wo[W] : 0.f;
 }
 
 // ---------------------------------------------------------------------------
-// Backward.  Block = NW waves, a block step covers NB = 32*NW nodes.
+// Backward.  Block = NW waves, a block step covers NB = 16*NW nodes.
 // Hall[l][feature][node] holds the recomputed activations of hidden layers
 // 1..L-1 (the B operands of dW_2..dW_L and the source of the derivative);
 // the last layer stays in registers and passes through Dt once for the
@@ -298,45 +318,58 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 // NTH/4) and a quarter of the block's nodes.
 // ---------------------------------------------------------------------------
 template <int W, int L, int MODE, int DIM, int NW>
-__global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
-                                                          const float* __restrict__ th,
-                                                          const typename MM<MODE>::felem* __restrict__ frag,
-                                                          const float* __restrict__ gu,
-                                                          float* __restrict__ partials) {
+struct BwdShape {
   using T = MM<MODE>;
   using E = typename T::lelem;
+  static constexpr int NB = 16 * NW;           // nodes per block step
+  static constexpr int LD = NB + T::PAD;       // row pitch of the transposed buffers
+  static constexpr int NTH = 64 * NW;
+  static constexpr size_t lds_bytes() {
+    return sizeof(E) * size_t(T::NPL * L * W * LD) +
+           sizeof(float) * size_t(Small<W, L, DIM>::SIZE + NB + DIM * NB + NTH);
+  }
+};
+
+template <int W, int L, int MODE, int DIM, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P,
+                                                             const float* __restrict__ th,
+                                                             const typename MM<MODE>::felem* __restrict__ frag,
+                                                             const float* __restrict__ gu,
+                                                             float* __restrict__ partials) {
+  using T = MM<MODE>;
+  using BS = BwdShape<W, L, MODE, DIM, NW>;
+  using E = typename BS::E;
   using SM = Small<W, L, DIM>;
-  constexpr int NR = W / 2, NKS = W / T::KS, NMB = W / 32;
-  constexpr int NB = 32 * NW;                 // nodes per block step
-  constexpr int LD = NB + T::PAD;             // row pitch of the transposed buffers
-  constexpr int NOB = NMB * NMB;              // 32x32 output tiles of one dW_l
+  constexpr int NR = W / 4, NKS = W / T::KS, NMB = W / 16;
+  constexpr int NB = BS::NB, LD = BS::LD, NTH = BS::NTH;
+  constexpr int NOB = NMB * NMB;              // 16x16 output tiles of one dW_l
   constexpr int OWN = (NOB + NW - 1) / NW;    // tiles owned by each wave
-  constexpr int NTH = 64 * NW;
   constexpr int FPT = (W * 4 + NTH - 1) / NTH;  // features per thread
   constexpr int QN = NB / 4;                  // nodes per quarter
-  __shared__ __attribute__((aligned(16))) E Hall[(L - 1) * W * LD];
-  __shared__ __attribute__((aligned(16))) E Dt[W * LD];
+  constexpr int HPL = (L - 1) * W * LD, DPL = W * LD;  // plane strides (split storage)
+  __shared__ __attribute__((aligned(16))) E Hall[T::NPL * HPL];
+  __shared__ __attribute__((aligned(16))) E Dt[T::NPL * DPL];
   __shared__ float sp[SM::SIZE];
   __shared__ float Gs[NB];
   __shared__ float Zs[DIM][NB];
   __shared__ float Red[NTH];
 
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 5, n = lane & 31;
-  const int col = w * 32 + n;  // this lane's node column in the block step
-  const int q = tid & 3;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, n = lane & 15;
+  const int col = w * 16 + n;  // this lane's node column in the block step
+  const int q4 = tid & 3;
   SM::stage(th, sp, tid, NTH);
   __syncthreads();
   const int64_t total = ipow(geo.n, DIM);
   const int64_t nsteps = (total + NB - 1) / NB;
   const float* wo = sp + SM::WO;
 
-  f32x16_t acc[L - 1][OWN];
+  f32x4_t acc[L - 1][OWN];
 #pragma unroll
   for (int a = 0; a < L - 1; ++a)
 #pragma unroll
     for (int o = 0; o < OWN; ++o)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[a][o][i] = 0.f;
+      for (int i = 0; i < 4; ++i) acc[a][o][i] = 0.f;
   float s_wout[FPT], s_b[L][FPT], s_w1[DIM][FPT], s_bout = 0.f;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -346,10 +379,12 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
 #pragma unroll
     for (int c = 0; c < DIM; ++c) s_w1[c][f] = 0.f;
   }
-  auto sink = [&](int l, const float(&hv)[NR]) {
-    if (l < L - 1)
+  auto sink = [&](int l, const typename T::op(&bo)[NKS]) {
 #pragma unroll
-      for (int t = 0; t < NR; ++t) Hall[(l * W + cfeat(t, g)) * LD + col] = E(hv[t]);
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int v = 0; v < T::S; ++v)
+        T::lds_put_elem(Hall + (l * W + cfeat(ks * T::S + v, q)) * LD + col, HPL, bo[ks], v);
   };
 
   for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
@@ -366,9 +401,9 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     float d[NR];
-    forward_tile<W, L, MODE, DIM>(sp, fr, z, g, lane, d, sink);
+    forward_tile<W, L, MODE, DIM>(sp, fr, z, q, lane, d, sink);
     const float gv = valid ? gu[p] : 0.f;
-    if (g == 0) {
+    if (q == 0) {
       Gs[col] = gv;
 #pragma unroll
       for (int c = 0; c < DIM; ++c) Zs[c][col] = z[c];
@@ -376,8 +411,8 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     // h_L through Dt for the output layer; then delta_L = g w_out (1 - h_L^2)
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
-      const int f = cfeat(t, g);
-      Dt[f * LD + col] = E(d[t]);
+      const int f = cfeat(t, q);
+      T::lds_put(Dt + f * LD + col, DPL, d[t]);
       d[t] = gv * wo[f] * (1.f - d[t] * d[t]);
     }
     __syncthreads();
@@ -385,9 +420,9 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     for (int f = 0; f < FPT; ++f) {
       const int fq = (tid >> 2) + f * (NTH / 4);
       if (fq < W) {
-        const E* hr = Dt + fq * LD + q * QN;
+        const E* hr = Dt + fq * LD + q4 * QN;
         float s = 0.f;
-        for (int k = 0; k < QN; ++k) s += float(hr[k]) * Gs[q * QN + k];
+        for (int k = 0; k < QN; ++k) s += T::lds_get(hr + k, DPL) * Gs[q4 * QN + k];
         s_wout[f] += s;
       }
     }
@@ -399,8 +434,20 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
     __syncthreads();
 #pragma unroll
     for (int l = L; l >= 1; --l) {
+      // delta_l into Dt; for l >= 2 as the split operands the chain below uses
+      typename T::op bop[NKS];
+      if (l >= 2) {
 #pragma unroll
-      for (int t = 0; t < NR; ++t) Dt[cfeat(t, g) * LD + col] = E(d[t]);
+        for (int ks = 0; ks < NKS; ++ks) {
+          bop[ks] = T::from(&d[ks * T::S]);
+#pragma unroll
+          for (int v = 0; v < T::S; ++v)
+            T::lds_put_elem(Dt + cfeat(ks * T::S + v, q) * LD + col, DPL, bop[ks], v);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < NR; ++t) T::lds_put(Dt + cfeat(t, q) * LD + col, DPL, d[t]);
+      }
       __syncthreads();
       if (l >= 2) {
         // dW_l[o][i] += sum_nodes delta_l[o][node] h_{l-1}[i][node]
@@ -409,11 +456,12 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
           const int tileid = w * OWN + o;
           if (tileid < NOB) {
             const int ob = tileid / NMB, ib = tileid % NMB;
-            const E* arow = Dt + (ob * 32 + n) * LD + T::S * g;
-            const E* brow = Hall + ((l - 2) * W + ib * 32 + n) * LD + T::S * g;
+            const E* arow = Dt + (ob * 16 + n) * LD + T::S * q;
+            const E* brow = Hall + ((l - 2) * W + ib * 16 + n) * LD + T::S * q;
 #pragma unroll
             for (int ks = 0; ks < NB / T::KS; ++ks)
-              acc[l - 2][o] = T::mma(T::lds(arow + ks * T::KS), T::lds(brow + ks * T::KS), acc[l - 2][o]);
+              acc[l - 2][o] = T::mma(T::lds_op(arow + ks * T::KS, DPL), T::lds_op(brow + ks * T::KS, HPL),
+                                     acc[l - 2][o]);
           }
         }
       }
@@ -422,17 +470,17 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
       for (int f = 0; f < FPT; ++f) {
         const int fq = (tid >> 2) + f * (NTH / 4);
         if (fq < W) {
-          const E* dr = Dt + fq * LD + q * QN;
+          const E* dr = Dt + fq * LD + q4 * QN;
           float sb = 0.f;
           float sw[DIM];
 #pragma unroll
           for (int c = 0; c < DIM; ++c) sw[c] = 0.f;
           for (int k = 0; k < QN; ++k) {
-            const float dv = float(dr[k]);
+            const float dv = T::lds_get(dr + k, DPL);
             sb += dv;
             if (l == 1)
 #pragma unroll
-              for (int c = 0; c < DIM; ++c) sw[c] += dv * Zs[c][q * QN + k];
+              for (int c = 0; c < DIM; ++c) sw[c] += dv * Zs[c][q4 * QN + k];
           }
           s_b[l - 1][f] += sb;
           if (l == 1)
@@ -442,21 +490,18 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
       }
       if (l >= 2) {
         // delta_{l-1} = (W_l^T delta_l) (1 - h_{l-1}^2)
-        typename T::op bop[NKS];
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&d[ks * T::S]);
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
-          f32x16_t c2;
+          f32x4_t c2;
 #pragma unroll
-          for (int i = 0; i < 16; ++i) c2[i] = 0.f;
+          for (int i = 0; i < 4; ++i) c2[i] = 0.f;
 #pragma unroll
           for (int ks = 0; ks < NKS; ++ks)
             c2 = T::mma(T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const float hv = float(Hall[((l - 2) * W + cfeat(mb * 16 + i, g)) * LD + col]);
-            d[mb * 16 + i] = c2[i] * (1.f - hv * hv);
+          for (int i = 0; i < 4; ++i) {
+            const float hv = T::lds_get(Hall + ((l - 2) * W + cfeat(mb * 4 + i, q)) * LD + col, HPL);
+            d[mb * 4 + i] = c2[i] * (1.f - hv * hv);
           }
         }
       }
@@ -475,9 +520,9 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
       if (tileid < NOB) {
         const int ob = tileid / NMB, ib = tileid % NMB;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int orow = ob * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-          row[off + int64_t(orow) * W + ib * 32 + n] = acc[l - 2][o][i];
+        for (int i = 0; i < 4; ++i) {
+          const int orow = ob * 16 + 4 * q + i;
+          row[off + int64_t(orow) * W + ib * 16 + n] = acc[l - 2][o][i];
         }
       }
     }
@@ -486,7 +531,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bwd_mfma(Geom geo, int64_t P,
   auto reduce4 = [&](float v, int64_t dst, bool ok) {
     Red[tid] = v;
     __syncthreads();
-    if (ok && q == 0) row[dst] = ((Red[tid] + Red[tid + 1]) + Red[tid + 2]) + Red[tid + 3];
+    if (ok && q4 == 0) row[dst] = ((Red[tid] + Red[tid + 1]) + Red[tid + 2]) + Red[tid + 3];
     __syncthreads();
   };
 #pragma unroll
@@ -566,11 +611,11 @@ __global__ __launch_bounds__(256) void k_reduce_adam_pack(
   const int64_t within = rel % per;
   if (hl >= hidden - 1 || within >= int64_t(W) * W) return;
   const int o = int(within / W), i = int(within % W);
-  int tt, g;
-  cfeat_inv(i, &tt, &g);  // forward fragment: row o, contraction feature i
-  T::put(frag + frag_index<MODE>(hl, 0, o >> 5, tt / T::S, (o & 31) + 32 * g, tt % T::S, W), nw);
-  cfeat_inv(o, &tt, &g);  // backward fragment: row i, contraction feature o
-  T::put(frag + frag_index<MODE>(hl, 1, i >> 5, tt / T::S, (i & 31) + 32 * g, tt % T::S, W), nw);
+  int tt, qq;
+  cfeat_inv(i, &tt, &qq);  // forward fragment: row o, contraction feature i
+  T::put(frag + frag_index<MODE>(hl, 0, o >> 4, tt / T::S, (o & 15) + 16 * qq, tt % T::S, W), nw);
+  cfeat_inv(o, &tt, &qq);  // backward fragment: row i, contraction feature o
+  T::put(frag + frag_index<MODE>(hl, 1, i >> 4, tt / T::S, (i & 15) + 16 * qq, tt % T::S, W), nw);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +664,7 @@ template <int W, int L, int MODE>
 static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, long long* tb,
                      hipStream_t st) {
   const int64_t total = ipow(g.n, g.dim);
-  const int64_t tiles = (total + 31) / 32;
+  const int64_t tiles = (total + 15) / 16;
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   if constexpr (L == 4) {
     if (g.dim == 3) {
@@ -644,14 +689,53 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 #undef CRV_FW
 }
 
-// waves per backward block: bf16 activations let 4 waves' worth of nodes fit
-// in LDS, float32-sized ones 2 (with two blocks per CU)
-constexpr int bwd_nw(int mode) { return 4; }
+// waves per backward block: 4 (64 nodes per block step); width 128 takes 8
+// so that its weight-gradient tiles spread over more waves
+constexpr int bwd_nw(int width) { return width >= 128 ? 8 : 4; }
 
-int mlp_bwd_mfma_blocks(const Geom& g, int mode, int cu_count) {
+// resident blocks per CU that the LDS of one block allows (160 KB per CU)
+template <int W, int L, int MODE, int DIM>
+static int bwd_lds_blocks() {
+  const size_t lds = BwdShape<W, L, MODE, DIM, bwd_nw(W)>::lds_bytes();
+  return int(std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / lds)));
+}
+
+// blocks per CU: what the LDS allows, capped by the occupancy the compiled
+// kernel reaches (registers) when a device is present
+template <int W, int L, int MODE>
+static int bwd_per_cu(int dim, bool query) {
+  constexpr int NW = bwd_nw(W);
+  int lds_blocks = 1, occ = 0;
+  hipError_t e = hipSuccess;
+  if (dim == 3) {
+    if constexpr (L == 4) {
+      lds_blocks = bwd_lds_blocks<W, L, MODE, 3>();
+      if (query)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_mlp_bwd_mfma<W, L, MODE, 3, NW>, 64 * NW, 0);
+    }
+  } else {
+    lds_blocks = bwd_lds_blocks<W, L, MODE, 2>();
+    if (query)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_mlp_bwd_mfma<W, L, MODE, 2, NW>, 64 * NW, 0);
+  }
+  if (!query) return lds_blocks;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return std::max(1, std::min(lds_blocks, occ));
+}
+
+int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count,
+                        bool query) {
+  int per_cu = 1;
+  const int nw = bwd_nw(width);
+#define CRV_BB(WW, LL, MM_) \
+  if (width == WW && hidden == LL && mode == MM_) per_cu = bwd_per_cu<WW, LL, MM_>(g.dim, query);
+  CRV_FOR_SHAPES(CRV_BB)
+#undef CRV_BB
   const int64_t total = ipow(g.n, g.dim);
-  const int nb = 32 * bwd_nw(mode);
-  const int per_cu = 1;
+  const int nb = 16 * nw;
   const int64_t steps = (total + nb - 1) / nb;
   return int(std::max<int64_t>(1, std::min<int64_t>(steps, int64_t(cu_count) * per_cu)));
 }
@@ -659,7 +743,7 @@ int mlp_bwd_mfma_blocks(const Geom& g, int mode, int cu_count) {
 template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* gu,
                      float* partials, int blocks, hipStream_t st) {
-  constexpr int NW = bwd_nw(MODE);
+  constexpr int NW = bwd_nw(W);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   if constexpr (L == 4) {
     if (g.dim == 3) {

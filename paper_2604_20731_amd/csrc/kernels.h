@@ -126,7 +126,9 @@ void launch_pack_fragments(const float* theta, int dim, int width, int hidden, i
                            void* frag, hipStream_t st);
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
                              const void* frag, float* u, long long* t_bump, hipStream_t st);
-int mlp_bwd_mfma_blocks(const Geom& g, int mode, int cu_count);
+// backward blocks: at most cu_count x the blocks per CU that one block's LDS
+// allows; with query, also capped by the occupancy the compiled kernel reaches
+int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count, bool query);
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
                               const float* theta, const void* frag, const float* gu,
                               float* partials, int blocks, hipStream_t st);

@@ -151,7 +151,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.av = cv.take<Real>(P);
   b.grad = cv.take<Real>(P);
   b.frag = cv.take<char>(size_t(std::max<int64_t>(4, mlp_fragment_bytes(c.width, c.hidden))));
-  b.bwd_rows = uses_mfma(c) ? mlp_bwd_mfma_blocks(g, net_mode(c), kMaxCUs)
+  b.bwd_rows = uses_mfma(c) ? mlp_bwd_mfma_blocks(g, c.width, c.hidden, net_mode(c), kMaxCUs, false)
                             : mlp_backward_rows(g, ms, int(sizeof(Real)));
   b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
@@ -314,7 +314,8 @@ struct Solver : SolverBase {
       int dev = 0, cus = kMaxCUs;
       CRV_HIP(hipGetDevice(&dev));
       CRV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      bwd_blocks = std::min(b.bwd_rows, mlp_bwd_mfma_blocks(g, mode, std::min(cus, kMaxCUs)));
+      bwd_blocks = std::min(b.bwd_rows, mlp_bwd_mfma_blocks(g, cfg.width, cfg.hidden, mode,
+                                                            std::min(cus, kMaxCUs), true));
     }
     for (size_t i = 0; i < nn; ++i) {
       if (!std::isfinite(log_perm[i])) return fail(CRV_EINVAL, "log_perm has non-finite entries");
