@@ -553,25 +553,27 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
 }
 
 // ---------------------------------------------------------------------------
-// Fused gradient reduction + Adam + fragment update.  Block = 4 waves over
-// 64 parameters (one per lane); wave w sums partial rows w, w+4, ... and the
-// four wave sums are added in a fixed order.  The updated weight of a
+// Fused gradient reduction + Adam + fragment update.  Block = RW waves over
+// 64 parameters (one per lane); wave w sums partial rows w, w+RW, ... and the
+// RW wave sums are added in a fixed order.  The updated weight of a
 // hidden-to-hidden layer is written straight into its two fragment slots.
 // One extra block sums the iteration's loss partials.
 // ---------------------------------------------------------------------------
+constexpr int RW = 16;  // waves per reduction block
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce_adam_pack(
+__global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
     const float* __restrict__ part, int rows, int64_t P, float* __restrict__ th,
     float* __restrict__ m, float* __restrict__ v, double lr, double b1, double b2, double eps,
     const long long* __restrict__ t_dev, int dim, int W, int hidden,
     typename MM<MODE>::felem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
     double* __restrict__ hist, int cap) {
   using T = MM<MODE>;
-  __shared__ float red[4][64];
+  __shared__ float red[RW][64];
   if (blockIdx.x == gridDim.x - 1) {
-    __shared__ double lb[256];
+    __shared__ double lb[64 * RW];
     double s = 0;
-    for (int k = threadIdx.x; k < loss_np; k += 256) s += double(loss_part[k]);
+    for (int k = threadIdx.x; k < loss_np; k += 64 * RW) s += double(loss_part[k]);
     const double tot = block_sum(s, lb);
     if (threadIdx.x == 0) hist[(*t_dev - 1) % cap] = tot;
     return;
@@ -581,20 +583,22 @@ __global__ __launch_bounds__(256) void k_reduce_adam_pack(
   float s = 0.f;
   if (p < P) {
     int r = w;
-    for (; r + 12 < rows; r += 16) {
-      const float a0 = part[int64_t(r) * P + p], a1 = part[int64_t(r + 4) * P + p];
-      const float a2 = part[int64_t(r + 8) * P + p], a3 = part[int64_t(r + 12) * P + p];
+    for (; r + 3 * RW < rows; r += 4 * RW) {
+      const float a0 = part[int64_t(r) * P + p], a1 = part[int64_t(r + RW) * P + p];
+      const float a2 = part[int64_t(r + 2 * RW) * P + p], a3 = part[int64_t(r + 3 * RW) * P + p];
       s += a0;
       s += a1;
       s += a2;
       s += a3;
     }
-    for (; r < rows; r += 4) s += part[int64_t(r) * P + p];
+    for (; r < rows; r += RW) s += part[int64_t(r) * P + p];
   }
   red[w][lane] = s;
   __syncthreads();
   if (w != 0 || p >= P) return;
-  const float gg = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  float gg = red[0][lane];
+#pragma unroll
+  for (int k = 1; k < RW; ++k) gg += red[k][lane];
   const double t = double(*t_dev);
   const float c1 = float(1.0 - pow(b1, t)), c2 = float(1.0 - pow(b2, t));
   const float mm = float(b1) * m[p] + float(1.0 - b1) * gg;
@@ -651,7 +655,7 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* 
                              int cap, hipStream_t st) {
   const int blocks = cdiv(P, 64) + 1;
 #define CRV_RA(MM_, TT)                                                                           \
-  k_reduce_adam_pack<MM_><<<blocks, 256, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps, \
+  k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps, \
                                                   t_dev, dim, width, hidden, static_cast<TT*>(frag), \
                                                   loss_part, loss_np, loss_hist, cap)
   if (mode == NET_F32) CRV_RA(NET_F32, float);

@@ -13,6 +13,8 @@
 // 6-step wavefront scan of the composed maps gives every lane its incoming
 // state, and the lane re-runs its chunk from that state.  The backward sweep
 // x_j = y_j / D_j - sum_t L(j+t, j) x_{j+t} is the same scan in reverse.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace crv {
@@ -436,6 +438,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* _
 // their partial tiles are summed in a fixed order through LDS.  Lane
 // (r = lane%32, g = lane/32) feeds A[m0+r][k+g] and B[k+g][n0+r] per step.
 typedef float gemm_f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
                                                        const float* __restrict__ A, int lda,
@@ -474,11 +477,70 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
   }
 }
 
+// float32 C = A B with A supplied as packed 32x32x2 fragments (A is a
+// constant operand, packed once): chunk kc of row block mb holds, for lane
+// (r = lane%32, g = lane/32), A[32 mb + r][16 kc + 2u + g], u = 0..7, as 8
+// consecutive floats, so every A load of a wave is one contiguous 2 KB read.
+// One 32x32 output tile per block; its NW waves split K into NW contiguous
+// ranges and the partial tiles are summed in a fixed order through LDS.
+__global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
+                                                     const float* __restrict__ Af,
+                                                     const float* __restrict__ B, int ldb,
+                                                     int64_t sb, float* __restrict__ C, int ldc,
+                                                     int64_t sc) {
+  B += int64_t(blockIdx.z) * sb;
+  C += int64_t(blockIdx.z) * sc;
+  __shared__ float part[8][32 * 33];
+  const int nw = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, g = lane >> 5;
+  const int mb = blockIdx.y, n0 = blockIdx.x * 32;
+  const int kq = K / nw;  // multiple of 16
+  const float* a = Af + ((int64_t(mb) * (K / 16) + (w * kq) / 16) * 64 + lane) * 8;
+  const float* b = B + int64_t(w * kq + g) * ldb + n0 + r;
+  gemm_f32x16_t acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int kc = 0; kc < kq / 16; ++kc) {
+    const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(a + kc * 512);
+    const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(a + kc * 512 + 4);
+    float bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bv[u] = b[int64_t(kc * 16 + 2 * u) * ldb];
+    const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) part[w][(8 * (i >> 2) + 4 * g + (i & 3)) * 33 + r] = acc[i];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int row = e >> 5, col = e & 31;
+    float v = part[0][row * 33 + col];
+    for (int k = 1; k < nw; ++k) v += part[k][row * 33 + col];
+    C[int64_t(mb * 32 + row) * ldc + n0 + col] = v;
+  }
+}
+
 template <typename Real>
 void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
-                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st) {
+                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
+                         const Real* a_packed) {
   if (batch <= 0) return;
   if constexpr (sizeof(Real) == 4) {
+    if (a_packed) {
+      // K split over nw waves (the largest divisor of K/64 up to 8), so that
+      // every wave's range is a multiple of 16
+      const int units = K / 64;
+      int nw = 1;
+      for (int d = 8; d >= 1; --d)
+        if (units % d == 0) {
+          nw = d;
+          break;
+        }
+      dim3 grid(N / 32, M / 32, batch);
+      k_gemm_pa_f32<<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc);
+      return;
+    }
     // dims are multiples of 64, so K/4 is a multiple of 16
     dim3 grid(N / 32, M / 32, batch);
     k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
@@ -490,8 +552,8 @@ void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real
 
 template <typename Real>
 void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
-                 int ldc, hipStream_t st) {
-  launch_gemm_batched<Real>(M, N, K, A, lda, B, ldb, 0, C, ldc, 0, 1, st);
+                 int ldc, hipStream_t st, const Real* a_packed) {
+  launch_gemm_batched<Real>(M, N, K, A, lda, B, ldb, 0, C, ldc, 0, 1, st, a_packed);
 }
 
 #define CRV_INST(R)                                                                            \
@@ -499,9 +561,10 @@ void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int
                                     int64_t, int64_t, hipStream_t);                           \
   template void launch_band_cols<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
                                     int64_t, int64_t, hipStream_t);                           \
-  template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t); \
+  template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t, \
+                               const R*);                                                     \
   template void launch_gemm_batched<R>(int, int, int, const R*, int, const R*, int, int64_t, R*, \
-                                       int, int64_t, int, hipStream_t);
+                                       int, int64_t, int, hipStream_t, const R*);
 CRV_INST(float)
 CRV_INST(double)
 

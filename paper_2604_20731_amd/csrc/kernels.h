@@ -84,13 +84,16 @@ void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_str
                       hipStream_t st);
 
 // C = A B, row-major, all dims multiples of 64, pitches in elements.
+// a_packed (nullable, float32 only): A as packed matrix-core fragments
+// (pack_gemm_a in tables.h), used instead of A when given.
 template <typename Real>
 void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Real* C,
-                 int ldc, hipStream_t st);
+                 int ldc, hipStream_t st, const Real* a_packed = nullptr);
 // batch products sharing A: C_z = A B_z, B_z = B + z sb, C_z = C + z sc
 template <typename Real>
 void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
-                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st);
+                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
+                         const Real* a_packed = nullptr);
 
 // ---- network (k_mlp.hip) ---------------------------------------------------
 struct MlpShape {

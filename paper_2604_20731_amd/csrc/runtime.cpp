@@ -75,7 +75,7 @@ struct Buffers {
   // coefficients nb^d
   Real *s, *p, *bvec;
   // interior, padded to mp per axis
-  Real *res, *rhat, *qhat, *q, *dst;
+  Real *res, *rhat, *qhat, *q, *dst, *dst_pk;
   // Gram lines (pitch mp) and mass factors
   Real *g_lt, *g_invd, *m_lt, *m_invd;
   double *band, *band_work, *shifts;
@@ -131,6 +131,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.qhat = cv.take<Real>(ni);
   b.q = cv.take<Real>(ni);
   b.dst = cv.take<Real>(size_t(g.mp) * g.mp);
+  b.dst_pk = cv.take<Real>(size_t(g.mp) * g.mp);
   b.g_lt = cv.take<Real>(nl * g.mp);
   b.g_invd = cv.take<Real>(nl * g.mp);
   b.m_lt = cv.take<Real>(size_t(g.nb) * g.r);
@@ -374,6 +375,10 @@ struct Solver : SolverBase {
     std::vector<double> dst, lam;
     dst_table(g.m, g.mp, dst, lam);
     if ((s = upload(b.dst, dst.data(), dst.size()))) return s;
+    {
+      const std::vector<double> pk = pack_gemm_a(dst, g.mp, g.mp);
+      if ((s = upload(b.dst_pk, pk.data(), pk.size()))) return s;
+    }
     // shift of each line: lambda_j (2D), lambda_j + lambda_k (3D, padded
     // modes get a harmless positive shift; their lines hold zeros)
     std::vector<double> shifts(size_t(gram_lines(g)));
@@ -419,27 +424,27 @@ struct Solver : SolverBase {
     const int64_t mp2 = int64_t(mp) * mp;
     if (g.dim == 3) {
       tb(CRV_K_GRAM_DST);
-      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.res, int(mp2), b.qhat, int(mp2), st);
-      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st);
+      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.res, int(mp2), b.qhat, int(mp2), st, b.dst_pk);
+      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st, b.dst_pk);
       te();
       tb(CRV_K_GRAM_LINES);
       launch_band_rows<Real>(b.rhat, b.qhat, g.m, int(gram_lines(g)), mp, 1, b.g_lt, b.g_invd, mp,
                              mp, st);
       te();
       tb(CRV_K_GRAM_DST);
-      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st);
-      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.rhat, int(mp2), b.q, int(mp2), st);
+      launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, mp2, b.rhat, mp, mp2, mp, st, b.dst_pk);
+      launch_gemm<Real>(mp, int(mp2), mp, b.dst, mp, b.rhat, int(mp2), b.q, int(mp2), st, b.dst_pk);
       te();
       return;
     }
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.res, mp, b.rhat, mp, st);
+    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.res, mp, b.rhat, mp, st, b.dst_pk);
     te();
     tb(CRV_K_GRAM_LINES);
     launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, mp, 1, b.g_lt, b.g_invd, mp, mp, st);
     te();
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, b.q, mp, st);
+    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, b.q, mp, st, b.dst_pk);
     te();
   }
 

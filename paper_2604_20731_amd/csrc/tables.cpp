@@ -275,4 +275,16 @@ bool well_sources(const double* wells, int n_wells, int ne, int dim, double radi
   return true;
 }
 
+std::vector<double> pack_gemm_a(const std::vector<double>& a, int M, int K) {
+  std::vector<double> out(size_t(M) * K);
+  for (int mb = 0; mb < M / 32; ++mb)
+    for (int kc = 0; kc < K / 16; ++kc)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int u = 0; u < 8; ++u) {
+          const int row = 32 * mb + (lane & 31), col = 16 * kc + 2 * u + (lane >> 5);
+          out[((size_t(mb) * (K / 16) + kc) * 64 + lane) * 8 + u] = a[size_t(row) * K + col];
+        }
+  return out;
+}
+
 }  // namespace crv

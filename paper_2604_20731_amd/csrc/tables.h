@@ -42,6 +42,10 @@ void gauss_tables(int ne, int r, std::vector<double>& gb, std::vector<double>& g
 // Orthonormal DST-I basis of size m, padded to mp x mp with zeros:
 // S(k, j) = sqrt(2/(m+1)) sin((k+1)(j+1) pi/(m+1)); lam[k] = 4 sin^2((k+1) pi/(2(m+1))).
 void dst_table(int m, int mp, std::vector<double>& s, std::vector<double>& lam);
+// A (M x K row-major, M multiple of 32, K of 16) rearranged into the packed
+// operand order of the float32 32x32x2 matrix-core product: index
+// ((mb * K/16 + kc) * 64 + lane) * 8 + u holds A[32 mb + lane%32][16 kc + 2u + lane/32].
+std::vector<double> pack_gemm_a(const std::vector<double>& a, int M, int K);
 
 // Well sources on the nodal grid (injectors and producers separate).
 // Returns false with a message if a well covers no node or a boundary node.
