@@ -60,7 +60,7 @@ def algorithmic_work(name, prob, n_launch_units):
     return tab.get(name)
 
 
-NET_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+NET_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x3f": 3}
 
 
 def kernel_symbol(name, prob, precision):
@@ -69,7 +69,8 @@ def kernel_symbol(name, prob, precision):
     if name == "mlp_bwd" and precision in NET_MODE:
         return f"crv::k_mlp_bwd_mfma<{prob.width}, {prob.hidden}, {NET_MODE[precision]}, {prob.dim}, 4>"
     if name == "mlp_fwd" and precision in NET_MODE:
-        return f"crv::k_mlp_fwd_mfma<{prob.width}, {prob.hidden}, {NET_MODE[precision]}, {prob.dim}>"
+        mode = 2 if precision == "bf16x3f" else NET_MODE[precision]   # split-bf16 forward
+        return f"crv::k_mlp_fwd_mfma<{prob.width}, {prob.hidden}, {mode}, {prob.dim}>"
     return None
 
 
@@ -200,9 +201,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3", "fp64"],
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3", "bf16x3f", "fp64"],
                     help="network arithmetic of the headline (batched) run")
     ap.add_argument("--batch", type=int, default=8, help="concurrent 512^2 scenarios")
+    ap.add_argument("--alt-precision", default="bf16x3f",
+                    help="second network arithmetic timed beside the headline ('' to skip)")
     ap.add_argument("--workload", default="b512")
     ap.add_argument("--pretrain", type=int, default=100)
     ap.add_argument("--serve", type=int, default=64, help="serving arrivals (0: skip)")
@@ -240,6 +243,14 @@ def main():
     log(f"{args.precision} batched: {args.batch} scenarios x {args.steps} steps")
     batched = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
                           args.pretrain)
+    alt = None
+    if args.alt_precision:
+        log(f"{args.alt_precision}: single scenario and {args.batch} batched, {args.steps} steps")
+        alt_single, _ = run_single(prob, args.alt_precision, args.steps, args.warmup, args.pretrain,
+                                   False)
+        alt_batched = run_batched(list(range(args.batch)), args.alt_precision, args.steps,
+                                  args.warmup, args.pretrain)
+        alt = {"precision": args.alt_precision, "single": alt_single, "batched": alt_batched}
     serving = None
     if args.serve > 0:
         from paper_2604_20731_amd.serve import Server
@@ -258,7 +269,8 @@ def main():
             amount, unit = work
             if unit == "flop":
                 peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"],
-                        "bf16x3": PEAK["bf16_tflops"], "fp64": PEAK["fp64_tflops"]}[args.precision]
+                        "bf16x3": PEAK["bf16_tflops"], "bf16x3f": PEAK["bf16_tflops"],
+                        "fp64": PEAK["fp64_tflops"]}[args.precision]
                 achieved = amount / (us * 1e-6) / 1e12
                 roofline = {"kernel": dom, "bound": "alu" if args.precision == "fp64" else "mfma",
                             "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -286,6 +298,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16 (network) / f32", "bf16x3": "bf16x3 (network) / f32",
+                  "bf16x3f": "bf16x3 forward, bf16 backward (network) / f32",
                   "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload} x{args.batch}: {args.batch} concurrent scenarios, "
@@ -297,6 +310,7 @@ def main():
         "single": single,
         "batched": batched,
         "vs_plain": batched["value"] / plain["value"],
+        "alt_precision": alt,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -70,9 +70,13 @@ typedef enum {
   CRV_PREC_BF16 = 1,   /* hidden-layer products on bf16 MFMA, float32
                           accumulate; everything else float32 */
   CRV_PREC_FP64 = 2,   /* everything in float64 (verification mode) */
-  CRV_PREC_BF16X3 = 3  /* hidden-layer products as three bf16 MFMAs on
+  CRV_PREC_BF16X3 = 3, /* hidden-layer products as three bf16 MFMAs on
                           hi/lo-split operands (about 2^-16 relative error),
                           float32 accumulate; everything else float32 */
+  CRV_PREC_BF16X3F = 4 /* split-bf16 forward (the pressure that the residual,
+                          loss and projection see), plain bf16 products in the
+                          network backward (gradient about 2^-9 relative);
+                          everything else float32 */
 } crv_precision;
 
 typedef struct {

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcrv.so")
 
 CRV_OK, CRV_EINVAL, CRV_ENOMEM, CRV_EHIP, CRV_ENUMERIC, CRV_ESTATE = 0, -1, -2, -3, -4, -5
-PREC = {"fp32": 0, "bf16": 1, "fp64": 2, "bf16x3": 3}
+PREC = {"fp32": 0, "bf16": 1, "fp64": 2, "bf16x3": 3, "bf16x3f": 4}
 STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
                 -4: "CRV_ENUMERIC", -5: "CRV_ESTATE"}
 

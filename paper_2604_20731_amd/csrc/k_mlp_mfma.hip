@@ -145,6 +145,34 @@ struct MM<NET_X3> {
   }
 };
 
+// Backward of the mixed form: plain bf16 products on the split-bf16 fragments
+// (hi plane only); stores both planes when Adam updates a weight, so the
+// split-bf16 forward keeps reading exact splits.
+template <>
+struct MM<NET_MIX> {
+  static constexpr int S = 8, KS = 32, NP = 2;
+  using felem = __bf16;
+  using lelem = __bf16;
+  static constexpr int PAD = 8;
+  static constexpr int NPL = 1;
+  using op = bf16x8_t;
+  __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
+  __device__ static inline op from(const float* v) {
+    op o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (__bf16)v[k];
+    return o;
+  }
+  __device__ static inline void put(felem* p, float w) { MM<NET_X3>::put(p, w); }
+  __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
+  __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
+  __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
+  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { *p = o[v]; }
+};
+
 // feature held by lane group q in its flat accumulator register t (t = 4 mb + i)
 __host__ __device__ inline int cfeat(int t, int q) { return 16 * (t >> 2) + 4 * q + (t & 3); }
 // inverse: register t and lane group q holding feature f
@@ -627,6 +655,7 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
 // ---------------------------------------------------------------------------
 bool mlp_mfma_supported(int dim, int width, int hidden, int mode) {
   if (dim == 3 ? hidden != 4 : (dim != 2 || !(hidden == 3 || hidden == 4))) return false;
+  if (mode == NET_MIX) mode = NET_X3;
   if (mode == NET_BF16) return width == 32 || width == 64 || width == 128;
   return width == 32 || width == 64;
 }
@@ -637,6 +666,7 @@ int64_t mlp_fragment_bytes(int width, int hidden) {
 
 void launch_pack_fragments(const float* theta, int dim, int width, int hidden, int mode,
                            void* frag, hipStream_t st) {
+  if (mode == NET_MIX) mode = NET_X3;  // same fragments
   const int64_t total = 2 * int64_t(width) * width * (hidden - 1);
   if (total <= 0) return;
   const int blocks = cdiv(total, 256);
@@ -654,6 +684,7 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* 
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
                              int cap, hipStream_t st) {
   const int blocks = cdiv(P, 64) + 1;
+  if (mode == NET_MIX) mode = NET_X3;  // same fragments
 #define CRV_RA(MM_, TT)                                                                           \
   k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps, \
                                                   t_dev, dim, width, hidden, static_cast<TT*>(frag), \
@@ -683,10 +714,12 @@ static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u,
   X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
   X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
   X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
-  X(32, 3, NET_X3) X(64, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)
+  X(32, 3, NET_X3) X(64, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)                        \
+  X(32, 3, NET_MIX) X(64, 3, NET_MIX) X(32, 4, NET_MIX) X(64, 4, NET_MIX)
 
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
                              const void* frag, float* u, long long* t_bump, hipStream_t st) {
+  if (mode == NET_MIX) mode = NET_X3;  // the forward of the mixed form is split bf16
 #define CRV_FW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) return fwd_inst<WW, LL, MM_>(g, theta, frag, u, t_bump, st);
   CRV_FOR_SHAPES(CRV_FW)

@@ -121,7 +121,9 @@ void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double
 
 // ---- network on matrix cores (k_mlp_mfma.hip), float32 parameters ----------
 // arithmetic of the hidden-to-hidden products
-enum NetMode : int { NET_F32 = 0, NET_BF16 = 1, NET_X3 = 2 };
+// NET_MIX: split-bf16 forward (the pressure the loss sees), plain bf16
+// backward products; its fragments are the split-bf16 ones
+enum NetMode : int { NET_F32 = 0, NET_BF16 = 1, NET_X3 = 2, NET_MIX = 3 };
 bool mlp_mfma_supported(int dim, int width, int hidden, int mode);
 int64_t mlp_fragment_bytes(int width, int hidden);
 // rearrange theta into the MFMA operand fragments of the mode

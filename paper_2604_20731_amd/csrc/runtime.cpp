@@ -97,7 +97,10 @@ struct Buffers {
 constexpr int kMaxCUs = 256;  // compute units sized for (MI355X); persistent grids use at most this
 
 static int net_mode(const crv_config& c) {
-  return c.precision == CRV_PREC_BF16 ? NET_BF16 : c.precision == CRV_PREC_BF16X3 ? NET_X3 : NET_F32;
+  return c.precision == CRV_PREC_BF16     ? NET_BF16
+         : c.precision == CRV_PREC_BF16X3 ? NET_X3
+         : c.precision == CRV_PREC_BF16X3F ? NET_MIX
+                                           : NET_F32;
 }
 
 static bool uses_mfma(const crv_config& c) {
@@ -176,9 +179,10 @@ static crv_status validate_config(const crv_config* c) {
   if (!(c->width == 16 || c->width == 32 || c->width == 64 || c->width == 128))
     return fail(CRV_EINVAL, "width must be 16, 32, 64 or 128");
   if (c->hidden < 1 || c->hidden > 8) return fail(CRV_EINVAL, "hidden must be in [1, 8]");
-  if (c->precision < CRV_PREC_FP32 || c->precision > CRV_PREC_BF16X3)
+  if (c->precision < CRV_PREC_FP32 || c->precision > CRV_PREC_BF16X3F)
     return fail(CRV_EINVAL, "unknown precision");
-  if ((c->precision == CRV_PREC_BF16 || c->precision == CRV_PREC_BF16X3) &&
+  if ((c->precision == CRV_PREC_BF16 || c->precision == CRV_PREC_BF16X3 ||
+       c->precision == CRV_PREC_BF16X3F) &&
       !mlp_mfma_supported(c->dim, c->width, c->hidden, net_mode(*c)))
     return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 also 128) and 3 or 4 "
                             "hidden layers (4 in 3D)");

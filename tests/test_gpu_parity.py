@@ -42,7 +42,7 @@ GRAD_CASES = [("tiny", {}), ("c1", {}), ("c1", dict(n_elem=40, width=64, hidden=
               ("c1", dict(n_elem=100, width=32, hidden=4))]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3", "bf16x3f"])
 @pytest.mark.parametrize("name,over", GRAD_CASES)
 def test_loss_and_gradients(prec, name, over):
     """Robust loss, dLOSS/dtheta and dLOSS/dlogK of the same parameters.
@@ -50,7 +50,7 @@ def test_loss_and_gradients(prec, name, over):
     (257^2 and 101^2 nodes leave a partial last 32-node tile)."""
     say("loss_grad", prec, name, over)
     prob = problem(name, **over)
-    if prec in ("bf16", "bf16x3") and not (prob.width in (32, 64) and prob.hidden in (3, 4)):
+    if prec.startswith("bf16") and not (prob.width in (32, 64) and prob.hidden in (3, 4)):
         pytest.skip("bf16 network paths cover widths 32/64 with 3-4 hidden layers")
     sc = scenario_for(prob, prec)
     orc = oracle_for(prob)
@@ -59,8 +59,10 @@ def test_loss_and_gradients(prec, name, over):
     glref = orc.loss_grad_logperm()
     el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
     say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
-    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4}[prec]
-    assert el <= tol and eg < tol and egl < tol
+    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4, "bf16x3f": 1e-4}[prec]
+    # mixed form: loss and dlogK come from the split-bf16 forward (1e-4); the
+    # network backward runs on bf16 products (2^-9 per product), so dtheta gets 3e-2
+    assert el <= tol and egl < tol and eg < (3e-2 if prec == "bf16x3f" else tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -105,7 +107,8 @@ def test_saturation_substeps(prec, nsub, ne, r, wells):
     assert rel(s_gpu - s0, orc.s - s0) < (1e-10 if prec == "fp64" else 1e-3)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 5e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 5e-3),
+                                      ("bf16x3f", 5e-3)])
 def test_coupled_trajectory_c1(prec, tol):
     """C1 geometry: pretraining then coupled steps, fields after every step."""
     say("coupled c1", prec)
