@@ -240,27 +240,29 @@ void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_st
 }
 
 // Strided lines (element j of line c at x[j*row_stride + c]), shared
-// coefficients.  A block owns 64 consecutive lines (one per lane, so every
-// row access is coalesced) and splits their length into NWV chunks, one per
-// wavefront.  Each wave composes the affine maps of its chunk (particular
-// solution + r homogeneous ones), wave 0 scans the NWV chunk maps through LDS
-// in order, and every wave re-runs its chunk from its incoming state; the
-// backward sweep repeats this from the far end.
+// coefficients.  A block owns 16 consecutive lines and splits their length
+// into 64 chunks: wave w, lane group s = lane/16 takes chunk 4w + s of line
+// lane%16 (so a row access reads 4 runs of 16 consecutive values).  Each
+// chunk composes its affine map (particular solution + r homogeneous ones),
+// 16 lanes of wave 0 chain the 64 chunk maps of their line through LDS in
+// order, and every chunk re-runs from its incoming state; the backward sweep
+// repeats this from the far end.
 template <typename Real, int R>
 __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict__ b, Real* x, int n,
                                                          int ncols, int64_t rs,
                                                          const Real* __restrict__ lt,
                                                          const Real* __restrict__ invd,
                                                          int64_t batch_stride) {
-  constexpr int NWV = 16;
-  constexpr int NM = R * R + R;  // one affine map
-  __shared__ Real maps[NWV][NM][64];
-  __shared__ Real instate[NWV][R][64];
+  constexpr int NCH = 64, CW = 16;  // chunks per line, lines per block
+  constexpr int NM = R * R + R;      // one affine map
+  __shared__ Real maps[NCH][NM][CW];
+  __shared__ Real instate[NCH][R][CW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + lane;
+  const int cl = lane & (CW - 1), kc = w * 4 + (lane >> 4);  // line in block, chunk
+  const int c = blockIdx.x * CW + cl;
   const bool colok = c < ncols;
-  const int ch = (n + NWV - 1) / NWV;        // rows per chunk
-  const int j0 = w * ch, j1 = min(n, j0 + ch);
+  const int ch = (n + NCH - 1) / NCH;        // rows per chunk
+  const int j0 = min(n, kc * ch), j1 = min(n, j0 + ch);
   const Real* bb = b + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
   Real* xx = x + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
 
@@ -296,27 +298,28 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      maps[w][R * R + i][lane] = cc[i];
+      maps[kc][R * R + i][cl] = cc[i];
 #pragma unroll
-      for (int k = 0; k < R; ++k) maps[w][i * R + k][lane] = a[i][k];
+      for (int k = 0; k < R; ++k) maps[kc][i * R + k][cl] = a[i][k];
     }
   };
-  // wave 0 chains the chunk maps in order (dir 0: first to last chunk)
+  // lanes 0..15 of wave 0 chain their line's chunk maps in order (dir 0:
+  // first to last chunk)
   auto scan = [&](int dir) {
-    if (w != 0) return;
+    if (w != 0 || lane >= CW) return;
     Real st[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) st[t] = 0;
-    for (int k = 0; k < NWV; ++k) {
-      const int q = dir == 0 ? k : NWV - 1 - k;
+    for (int k = 0; k < NCH; ++k) {
+      const int q = dir == 0 ? k : NCH - 1 - k;
 #pragma unroll
-      for (int t = 0; t < R; ++t) instate[q][t][lane] = st[t];
+      for (int t = 0; t < R; ++t) instate[q][t][cl] = st[t];
       Real nx[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        Real acc = maps[q][R * R + i][lane];
+        Real acc = maps[q][R * R + i][cl];
 #pragma unroll
-        for (int k2 = 0; k2 < R; ++k2) acc += maps[q][i * R + k2][lane] * st[k2];
+        for (int k2 = 0; k2 < R; ++k2) acc += maps[q][i * R + k2][cl] * st[k2];
         nx[i] = acc;
       }
 #pragma unroll
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
   if (colok) {
     Real st[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) st[t] = instate[w][t][lane];
+    for (int t = 0; t < R; ++t) st[t] = instate[kc][t][cl];
     for (int j = j0; j < j1; ++j) {
       Real y = bb[int64_t(j) * rs];
 #pragma unroll
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
   if (colok) {
     Real st[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) st[t] = instate[w][t][lane];
+    for (int t = 0; t < R; ++t) st[t] = instate[kc][t][cl];
     for (int j = j1 - 1; j >= j0; --j) {
       Real xv = xx[int64_t(j) * rs];
 #pragma unroll
@@ -368,7 +371,7 @@ template <typename Real, int R>
 static void band_cols_dispatch(const Real* b, Real* x, int n, int nlines, int64_t rs,
                                const Real* lt, const Real* inv_d, int64_t batch,
                                int64_t batch_stride, hipStream_t st) {
-  dim3 grid(cdiv(nlines, 64), unsigned(batch));
+  dim3 grid(cdiv(nlines, 16), unsigned(batch));
   k_band_cols_scan<Real, R><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
 }
 
