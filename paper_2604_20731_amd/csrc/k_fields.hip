@@ -5,6 +5,7 @@
 // Layouts: nodal arrays (N+1)^d with x fastest; interior arrays padded to a
 // pitch mp per row, row index j-1 (2D); coefficient arrays nb^d.
 #include "kernels.h"
+#include "stencil.h"
 
 namespace crv {
 
@@ -151,68 +152,23 @@ void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real
 // boundary entries are zero because the trial functions vanish there), and
 // per-block partial sums of LOSS = RES . q (eq. 27).
 // ---------------------------------------------------------------------------
-template <typename Real>
-__device__ inline Real qext(const Real* q, const Geom& g, int i, int j) {
-  return (i >= 1 && i <= g.m && j >= 1 && j <= g.m) ? q[int64_t(j - 1) * g.mp + (i - 1)] : Real(0);
-}
-
-template <typename Real>
-__global__ __launch_bounds__(256) void k_adjoint2(Geom g, const Real* __restrict__ q,
-                                                  const Real* __restrict__ alpha,
-                                                  const Real* __restrict__ res,
-                                                  Real* __restrict__ gu,
-                                                  Real* __restrict__ partials) {
-  __shared__ Real sbuf[256];
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int n = g.n;
-  Real lpart = 0;
-  if (i < n && j < n) {
-    const int64_t p = int64_t(j) * n + i;
-    Real out = 0;
-    if (i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
-      const Real qp = qext(q, g, i, j), ap = alpha[p];
-      out = Real(2) * (alpha[p - 1] * (qp - qext(q, g, i - 1, j)) - ap * (qext(q, g, i + 1, j) - qp) +
-                       alpha[p - n] * (qp - qext(q, g, i, j - 1)) - ap * (qext(q, g, i, j + 1) - qp));
-      lpart = res[int64_t(j - 1) * g.mp + (i - 1)] * qp;
-    }
-    gu[p] = out;
-  }
-  const Real tot = block_sum(lpart, sbuf);
-  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
-}
-
-template <typename Real>
-__device__ inline Real qext3(const Real* q, const Geom& g, int i, int j, int k) {
-  return (i >= 1 && i <= g.m && j >= 1 && j <= g.m && k >= 1 && k <= g.m)
-             ? q[(int64_t(k - 1) * g.mp + (j - 1)) * g.mp + (i - 1)]
-             : Real(0);
-}
-
-template <typename Real>
-__global__ __launch_bounds__(256) void k_adjoint3(Geom g, const Real* __restrict__ q,
-                                                  const Real* __restrict__ alpha,
-                                                  const Real* __restrict__ res, Real h,
-                                                  Real* __restrict__ gu,
-                                                  Real* __restrict__ partials) {
+template <typename Real, int DIM>
+__global__ __launch_bounds__(256) void k_adjoint(Geom g, const Real* __restrict__ q,
+                                                 const Real* __restrict__ alpha,
+                                                 const Real* __restrict__ res,
+                                                 Real* __restrict__ gu,
+                                                 Real* __restrict__ partials) {
   __shared__ Real sbuf[256];
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int k = blockIdx.z;
-  const int64_t n = g.n, n2 = n * n;
+  const int n = g.n;
   Real lpart = 0;
   if (i < n && j < n) {
     const int64_t p = (int64_t(k) * n + j) * n + i;
-    Real out = 0;
-    if (i >= 1 && i <= g.m && j >= 1 && j <= g.m && k >= 1 && k <= g.m) {
-      const Real qp = qext3(q, g, i, j, k), ap = alpha[p];
-      const Real sx = alpha[p - 1] * (qp - qext3(q, g, i - 1, j, k)) - ap * (qext3(q, g, i + 1, j, k) - qp);
-      const Real sy = alpha[p - n] * (qp - qext3(q, g, i, j - 1, k)) - ap * (qext3(q, g, i, j + 1, k) - qp);
-      const Real sz = alpha[p - n2] * (qp - qext3(q, g, i, j, k - 1)) - ap * (qext3(q, g, i, j, k + 1) - qp);
-      out = Real(2) * h * (sx + sy + sz);
-      lpart = res[(int64_t(k - 1) * g.mp + (j - 1)) * g.mp + (i - 1)] * qp;
-    }
-    gu[p] = out;
+    int64_t iq;
+    gu[p] = adjoint_at<Real, DIM>(g, q, alpha, p, &iq);
+    if (iq >= 0) lpart = res[iq] * q[iq];
   }
   const Real tot = block_sum(lpart, sbuf);
   if (threadIdx.x == 0) partials[(int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
@@ -227,11 +183,11 @@ int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* 
                    Real* partials, hipStream_t st) {
   if (g.dim == 3) {
     dim3 grid3(cdiv(g.n, 64), cdiv(g.n, 4), g.n);
-    k_adjoint3<Real><<<grid3, 256, 0, st>>>(g, q, alpha, res, Real(1.0 / g.ne), gu, partials);
+    k_adjoint<Real, 3><<<grid3, 256, 0, st>>>(g, q, alpha, res, gu, partials);
     return grid3.x * grid3.y * grid3.z;
   }
   dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
-  k_adjoint2<Real><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials);
+  k_adjoint<Real, 2><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials);
   return grid.x * grid.y;
 }
 
@@ -265,10 +221,10 @@ __global__ __launch_bounds__(256) void k_grad_logperm2(Geom g, const Real* __res
   const int n = g.n;
   if (i >= n || j >= n) return;
   const int64_t p = int64_t(j) * n + i;
-  const Real qp = qext(q, g, i, j);
+  const Real qp = q_ext(q, g, i, j, 1);
   Real s = 0;
-  if (i + 1 < n) s += (u[p + 1] - u[p]) * (qext(q, g, i + 1, j) - qp);
-  if (j + 1 < n) s += (u[p + n] - u[p]) * (qext(q, g, i, j + 1) - qp);
+  if (i + 1 < n) s += (u[p + 1] - u[p]) * (q_ext(q, g, i + 1, j, 1) - qp);
+  if (j + 1 < n) s += (u[p + n] - u[p]) * (q_ext(q, g, i, j + 1, 1) - qp);
   out[p] = Real(2) * s * alpha[p];
 }
 
@@ -283,11 +239,11 @@ __global__ __launch_bounds__(256) void k_grad_logperm3(Geom g, const Real* __res
   const int64_t n = g.n, n2 = n * n;
   if (i >= n || j >= n) return;
   const int64_t p = (int64_t(k) * n + j) * n + i;
-  const Real qp = qext3(q, g, i, j, k);
+  const Real qp = q_ext(q, g, i, j, k);
   Real s = 0;
-  if (i + 1 < n) s += (u[p + 1] - u[p]) * (qext3(q, g, i + 1, j, k) - qp);
-  if (j + 1 < n) s += (u[p + n] - u[p]) * (qext3(q, g, i, j + 1, k) - qp);
-  if (k + 1 < n) s += (u[p + n2] - u[p]) * (qext3(q, g, i, j, k + 1) - qp);
+  if (i + 1 < n) s += (u[p + 1] - u[p]) * (q_ext(q, g, i + 1, j, k) - qp);
+  if (j + 1 < n) s += (u[p + n] - u[p]) * (q_ext(q, g, i, j + 1, k) - qp);
+  if (k + 1 < n) s += (u[p + n2] - u[p]) * (q_ext(q, g, i, j, k + 1) - qp);
   out[p] = Real(2) * h * s * alpha[p];
 }
 

@@ -35,6 +35,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "stencil.h"
 
 namespace crv {
 
@@ -337,7 +338,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// Backward.  Block = NW waves, a block step covers NB = 16*NW nodes.
+// Backward.  Block = NW waves, a block step covers NB = 16*NW nodes.  The
+// adjoint field g_u = 2 A^T q is evaluated per node from q and alpha (no g_u
+// array), and each block also sums its share of LOSS = RES . q into
+// loss_part[block].
 // Hall[l][feature][node] holds the recomputed activations of hidden layers
 // 1..L-1 (the B operands of dW_2..dW_L and the source of the derivative);
 // the last layer stays in registers and passes through Dt once for the
@@ -362,8 +366,11 @@ template <int W, int L, int MODE, int DIM, int NW>
 __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P,
                                                              const float* __restrict__ th,
                                                              const typename MM<MODE>::felem* __restrict__ frag,
-                                                             const float* __restrict__ gu,
-                                                             float* __restrict__ partials) {
+                                                             const float* __restrict__ qg,
+                                                             const float* __restrict__ alpha,
+                                                             const float* __restrict__ res,
+                                                             float* __restrict__ partials,
+                                                             float* __restrict__ loss_part) {
   using T = MM<MODE>;
   using BS = BwdShape<W, L, MODE, DIM, NW>;
   using E = typename BS::E;
@@ -390,6 +397,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
   const int64_t total = ipow(geo.n, DIM);
   const int64_t nsteps = (total + NB - 1) / NB;
   const float* wo = sp + SM::WO;
+  float lacc = 0.f;  // this lane's share of RES . q (lane group 0 only)
 
   f32x4_t acc[L - 1][OWN];
 #pragma unroll
@@ -430,7 +438,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     float d[NR];
     forward_tile<W, L, MODE, DIM>(sp, fr, z, q, lane, d, sink);
-    const float gv = valid ? gu[p] : 0.f;
+    int64_t iq = -1;
+    const float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
+    if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
     if (q == 0) {
       Gs[col] = gv;
 #pragma unroll
@@ -578,6 +588,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
   Red[tid] = (tid < 4) ? s_bout : 0.f;  // threads 0..3 summed one node quarter of g each
   __syncthreads();
   if (tid == 0) row[off_layer(L + 1, DIM, W) + W] = ((Red[0] + Red[1]) + Red[2]) + Red[3];
+  __syncthreads();
+  const float lt = block_sum(lacc, Red);
+  if (tid == 0) loss_part[blockIdx.x] = lt;
 }
 
 // ---------------------------------------------------------------------------
@@ -778,24 +791,29 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 }
 
 template <int W, int L, int MODE>
-static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* gu,
-                     float* partials, int blocks, hipStream_t st) {
+static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* q,
+                     const float* alpha, const float* res, float* partials, float* loss_part,
+                     int blocks, hipStream_t st) {
   constexpr int NW = bwd_nw(W);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, gu, partials);
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, q, alpha, res,
+                                                                    partials, loss_part);
       return;
     }
   }
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, gu, partials);
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, q, alpha, res,
+                                                                partials, loss_part);
 }
 
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
-                              const float* theta, const void* frag, const float* gu,
-                              float* partials, int blocks, hipStream_t st) {
+                              const float* theta, const void* frag, const float* q,
+                              const float* alpha, const float* res, float* partials,
+                              float* loss_part, int blocks, hipStream_t st) {
 #define CRV_BW(WW, LL, MM_) \
-  if (width == WW && hidden == LL && mode == MM_) return bwd_inst<WW, LL, MM_>(g, P, theta, frag, gu, partials, blocks, st);
+  if (width == WW && hidden == LL && mode == MM_) \
+    return bwd_inst<WW, LL, MM_>(g, P, theta, frag, q, alpha, res, partials, loss_part, blocks, st);
   CRV_FOR_SHAPES(CRV_BW)
 #undef CRV_BW
 }

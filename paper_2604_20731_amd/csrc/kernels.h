@@ -134,9 +134,12 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 // backward blocks: at most cu_count x the blocks per CU that one block's LDS
 // allows; with query, also capped by the occupancy the compiled kernel reaches
 int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count, bool query);
+// partial gradient rows of sum_p g_u(p) NN(z_p) with g_u = 2 A^T q evaluated
+// per node from q and alpha; loss_part[block] = the block's share of RES . q
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
-                              const float* theta, const void* frag, const float* gu,
-                              float* partials, int blocks, hipStream_t st);
+                              const float* theta, const void* frag, const float* q,
+                              const float* alpha, const float* res, float* partials,
+                              float* loss_part, int blocks, hipStream_t st);
 // fixed-order sum of the partial rows + Adam + fragment update; one extra
 // block sums the loss partials into loss_hist[(t-1) % cap]
 void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,

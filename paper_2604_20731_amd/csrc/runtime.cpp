@@ -159,7 +159,8 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
                             : mlp_backward_rows(g, ms, int(sizeof(Real)));
   b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
-  b.loss_np = adjoint_partials(g);
+  // loss partials: from the adjoint kernel, or one per fused network-backward block
+  b.loss_np = std::max(adjoint_partials(g), b.bwd_rows);
   b.loss_part = cv.take<Real>(size_t(b.loss_np));
   b.loss_hist = cv.take<double>(kLossCap);
   b.loss_scalar = cv.take<double>(1);
@@ -491,27 +492,31 @@ struct Solver : SolverBase {
     te();
   }
 
-  // forward, residual, Gram solve and adjoint: b.u, b.res, b.q, b.gu and the
-  // per-block loss partials
+  // forward, residual, Gram solve and (unless the matrix-core backward fuses
+  // it) the adjoint: b.u, b.res, b.q, b.gu and the per-block loss partials
   void loss_pass(long long* t_bump) {
     forward(t_bump);
     tb(CRV_K_RESIDUAL);
     launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st);
     te();
     gram_solve();
+    if (mfma) return;
     tb(CRV_K_ADJOINT);
-    launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
+    adj_np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
     te();
   }
 
-  // partial gradient rows of the network backward; returns the row count
+  // partial gradient rows of the network backward; returns the row count.
+  // The matrix-core backward also leaves bwd_blocks loss partials.
+  int adj_np = 0;
+  int loss_count() const { return mfma ? bwd_blocks : adj_np; }
   int backward() {
     tb(CRV_K_MLP_BWD);
     int rows = 0;
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, P, b.theta, b.frag, b.gu,
-                                 b.partials, bwd_blocks, st);
+        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, P, b.theta, b.frag, b.q, b.alpha,
+                                 b.res, b.partials, b.loss_part, bwd_blocks, st);
         rows = bwd_blocks;
       }
     }
@@ -537,13 +542,13 @@ struct Solver : SolverBase {
         tb(CRV_K_ADAM);
         launch_reduce_adam_pack(b.partials, rows, P, b.theta, b.am, b.av, cfg.lr, cfg.beta1,
                                 cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, mode,
-                                b.frag, b.loss_part, b.loss_np, b.loss_hist, kLossCap, st);
+                                b.frag, b.loss_part, loss_count(), b.loss_hist, kLossCap, st);
         te();
         return;
       }
     }
     tb(CRV_K_LOSS);
-    launch_loss_finalize<Real>(b.loss_part, b.loss_np, b.loss_hist, kLossCap, b.t_dev, -1, st);
+    launch_loss_finalize<Real>(b.loss_part, loss_count(), b.loss_hist, kLossCap, b.t_dev, -1, st);
     te();
     grad_pass();
     tb(CRV_K_ADAM);
@@ -680,8 +685,8 @@ struct Solver : SolverBase {
 
   crv_status loss_grad(double* loss, double* dtheta, double* dlogperm) override {
     loss_pass(nullptr);
-    launch_loss_finalize<Real>(b.loss_part, b.loss_np, b.loss_scalar, 1, b.t_zero, 0, st);
     grad_pass();
+    launch_loss_finalize<Real>(b.loss_part, loss_count(), b.loss_scalar, 1, b.t_zero, 0, st);
     if (dlogperm) launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, b.tmp_nodal, st);
     crv_status s = check_launch();
     if (s) return s;
