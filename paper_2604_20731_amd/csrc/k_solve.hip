@@ -226,12 +226,127 @@ static int pick_p(int n) {
   return -1;
 }
 
+// Tridiagonal contiguous lines (r = 1) without LDS: lane l reads its P
+// entries of b, L and 1/D straight from memory (16-byte loads when the
+// pitches allow), composes its chunk's map y -> a y + c, a 6-step shuffle
+// scan gives it the incoming y, and the backward sweep
+// x_j = y_j / D_j - L(j+1, j) x_{j+1} repeats this from the far end.
+template <typename Real, int P>
+__device__ inline void load_chunk(const Real* __restrict__ src, int j0, int n, bool vec, Real (&v)[P]) {
+  constexpr int V = 16 / sizeof(Real);
+  if constexpr (P % V == 0) {
+    if (vec) {
+      typedef Real vec_t __attribute__((ext_vector_type(V)));
+#pragma unroll
+      for (int e = 0; e < P; e += V) {
+        const vec_t w = *reinterpret_cast<const vec_t*>(src + j0 + e);
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[e + k] = w[k];
+      }
+#pragma unroll
+      for (int e = 0; e < P; ++e)
+        if (j0 + e >= n) v[e] = Real(0);
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = (j0 + e < n) ? src[j0 + e] : Real(0);
+}
+
+template <typename Real, int P>
+__global__ __launch_bounds__(256) void k_tridiag_rows(const Real* __restrict__ b,
+                                                      Real* __restrict__ x, int n, int nlines,
+                                                      int64_t ls, const Real* __restrict__ lt,
+                                                      const Real* __restrict__ invd, int64_t cs,
+                                                      int64_t csd, bool vec) {
+  const int lane = threadIdx.x & 63;
+  const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (line >= nlines) return;  // the wave leaves as a whole; no block barriers here
+  const int j0 = lane * P;
+  Real v[P], l[P], d[P];
+  load_chunk<Real, P>(b + int64_t(line) * ls, j0, n, vec, v);
+  load_chunk<Real, P>(lt + int64_t(line) * cs, j0, n, vec, l);
+  load_chunk<Real, P>(invd + int64_t(line) * csd, j0, n, vec, d);
+  // forward: y_j = b_j - l_j y_{j-1}; chunk map y_out = a y_in + c
+  Real a = 1, c = 0;
+#pragma unroll
+  for (int e = 0; e < P; ++e)
+    if (j0 + e < n) {
+      c = v[e] - l[e] * c;
+      a = -l[e] * a;
+    }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Real pa = shfl_up(a, off), pc = shfl_up(c, off);
+    if (lane >= off) {
+      c = a * pc + c;
+      a = a * pa;
+    }
+  }
+  Real y = shfl_up(c, 1);
+  if (lane == 0) y = 0;
+#pragma unroll
+  for (int e = 0; e < P; ++e)
+    if (j0 + e < n) {
+      y = v[e] - l[e] * y;
+      v[e] = y * d[e];  // z_j
+    }
+  // backward: x_j = z_j - l_{j+1} x_{j+1}; l_{j+1} of the last entry is the next lane's first
+  Real lnext = shfl_down(l[0], 1);
+  if (lane == 63) lnext = 0;
+  a = 1;
+  c = 0;
+#pragma unroll
+  for (int e = P - 1; e >= 0; --e)
+    if (j0 + e < n) {
+      const Real le = (e == P - 1) ? lnext : l[e + 1];
+      c = v[e] - le * c;
+      a = -le * a;
+    }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Real na = shfl_down(a, off), nc = shfl_down(c, off);
+    if (lane + off < 64) {
+      c = a * nc + c;
+      a = a * na;
+    }
+  }
+  Real xv = shfl_down(c, 1);
+  if (lane == 63) xv = 0;
+  Real* xl = x + int64_t(line) * ls;
+#pragma unroll
+  for (int e = P - 1; e >= 0; --e)
+    if (j0 + e < n) {
+      const Real le = (e == P - 1) ? lnext : l[e + 1];
+      xv = v[e] - le * xv;
+      xl[j0 + e] = xv;
+    }
+}
+
 template <typename Real>
 void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t coef_stride,
                       int64_t coef_stride_d, hipStream_t st) {
   const int P = pick_p(n);
   if (P < 0 || nlines <= 0) return;
+  if (r == 1 && coef_stride > 0 && coef_stride_d > 0) {
+    // 16-byte loads need every lane's P entries inside each line's pitch and
+    // 16-byte aligned line starts
+    const int64_t V = 16 / int64_t(sizeof(Real));
+    const int64_t span = 64 * int64_t(P);
+    const bool vec = line_stride % V == 0 && coef_stride % V == 0 && coef_stride_d % V == 0 &&
+                     span <= line_stride && span <= coef_stride && span <= coef_stride_d &&
+                     reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(lt) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(inv_d) % 16 == 0;
+    dim3 grid(cdiv(nlines, 4));
+#define CRV_T(PP) \
+  case PP: k_tridiag_rows<Real, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, vec); return;
+    switch (P) {
+      CRV_T(1) CRV_T(2) CRV_T(3) CRV_T(4) CRV_T(5) CRV_T(8) CRV_T(9) CRV_T(12) CRV_T(16) CRV_T(17)
+      default: break;
+    }
+#undef CRV_T
+  }
   switch (r) {
     case 1: band_rows_dispatch<Real, 1>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
     case 2: band_rows_dispatch<Real, 2>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
