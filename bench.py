@@ -92,14 +92,11 @@ def measured_traffic(symbol, table=os.path.join(ROOT, "profiles", "b512_hbm_traf
     return None
 
 
-def cfl_dt_from_pressure(p, perm, poro, ne, n_exp=2.0, mu_g=0.1, cfl=0.5):
-    """dt = cfl h phi_min / (max lambda_g' max |K grad_+ p|) with the trained
-    network pressure standing in for the direct solve."""
-    g = np.zeros((ne, ne))
-    g += (np.diff(p, axis=1)[:ne, :ne] * ne) ** 2
-    g += (np.diff(p, axis=0)[:ne, :ne] * ne) ** 2
-    kmax = np.max(perm[:ne, :ne] * np.sqrt(g))
-    return float(cfl * (1.0 / ne) * poro.min() / ((n_exp / mu_g) * kmax))
+def cfl_dt_from_pressure(p, perm, poro, ne):
+    """dt = 0.5 h phi_min / (max lambda_g' max |K grad_+ p|) with the trained
+    network pressure standing in for the direct solve (the serving rule)."""
+    from paper_2604_20731_amd.serve import cfl_dt
+    return cfl_dt(p, np.log(perm), poro, ne)
 
 
 def cpu_baseline(prob, seconds=20.0):

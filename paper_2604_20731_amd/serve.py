@@ -32,10 +32,11 @@ from . import crv, inputs
 def cfl_dt(p: np.ndarray, log_perm: np.ndarray, poro: np.ndarray, ne: int, n_exp: float = 2.0,
            mu_g: float = 0.1, cfl: float = 0.5) -> float:
     """Step length cfl * h * phi_min / (max lambda_g' * max |K grad_+ p|) from
-    the pretrained network pressure."""
+    the pretrained network pressure (2D or 3D nodal arrays)."""
     k = np.exp(log_perm)
-    g = (np.diff(p, axis=1)[:ne, :ne] * ne) ** 2 + (np.diff(p, axis=0)[:ne, :ne] * ne) ** 2
-    kmax = float(np.max(k[:ne, :ne] * np.sqrt(g)))
+    cut = tuple(slice(0, ne) for _ in range(p.ndim))
+    g = sum((np.diff(p, axis=a)[cut] * ne) ** 2 for a in range(p.ndim))
+    kmax = float(np.max(k[cut] * np.sqrt(g)))
     return cfl * (1.0 / ne) * float(poro.min()) / ((n_exp / mu_g) * max(kmax, 1e-30))
 
 
