@@ -59,6 +59,7 @@ struct MM<NET_F32> {
   __device__ static inline op frag(const felem* p) { return *p; }
   __device__ static inline op from(const float* v) { return v[0]; }
   __device__ static inline void put(felem* p, float w) { p[0] = w; }
+  __device__ static inline f32x4_t row_sum(op a, f32x4_t c) { return mma(a, 1.0f, c); }
   __device__ static inline op lds_op(const lelem* p, int) { return *p; }
   __device__ static inline float lds_get(const lelem* p, int) { return *p; }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = v; }
@@ -84,6 +85,12 @@ struct MM<NET_BF16> {
     return o;
   }
   __device__ static inline void put(felem* p, float w) { p[0] = (__bf16)w; }
+  __device__ static inline f32x4_t row_sum(op a, f32x4_t c) {
+    op one;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) one[k] = (__bf16)1.0f;
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, one, c, 0, 0, 0);
+  }
   __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
@@ -129,6 +136,13 @@ struct MM<NET_X3> {
     p[0] = h;
     p[64 * S] = (__bf16)(w - float(h));
   }
+  __device__ static inline f32x4_t row_sum(const op& a, f32x4_t c) {
+    bf16x8_t one;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) one[k] = (__bf16)1.0f;
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, one, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, one, c, 0, 0, 0);
+  }
   __device__ static inline op lds_op(const lelem* p, int plane) {
     return op{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + plane)};
   }
@@ -168,6 +182,13 @@ struct MM<NET_MIX> {
     return o;
   }
   __device__ static inline void put(felem* p, float w) { MM<NET_X3>::put(p, w); }
+  __device__ static inline f32x4_t row_sum(op a, f32x4_t c) {
+    op one;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) one[k] = (__bf16)1.0f;
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, one, c, 0, 0, 0);
+  }
+
   __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
@@ -362,8 +383,15 @@ struct BwdShape {
   }
 };
 
+// waves per SIMD the register allocation must leave room for: plain-bf16
+// operands at width <= 64 fit three, everything else two
+template <int W, int MODE>
+constexpr int bwd_min_waves() {
+  return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64) ? 3 : 2;
+}
+
 template <int W, int L, int MODE, int DIM, int NW>
-__global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P,
+__global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd_mfma(Geom geo, int64_t P,
                                                              const float* __restrict__ th,
                                                              const typename MM<MODE>::felem* __restrict__ frag,
                                                              const float* __restrict__ qg,
@@ -400,18 +428,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
   float lacc = 0.f;  // this lane's share of RES . q (lane group 0 only)
 
   f32x4_t acc[L - 1][OWN];
+  f32x4_t bacc[L - 1];  // db_2..db_L of the wave's output rows (tile column ib = 0 only)
 #pragma unroll
-  for (int a = 0; a < L - 1; ++a)
+  for (int a = 0; a < L - 1; ++a) {
 #pragma unroll
     for (int o = 0; o < OWN; ++o)
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[a][o][i] = 0.f;
-  float s_wout[FPT], s_b[L][FPT], s_w1[DIM][FPT], s_bout = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bacc[a][i] = 0.f;
+  }
+  float s_wout[FPT], s_b[1][FPT], s_w1[DIM][FPT], s_bout = 0.f;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
     s_wout[f] = 0.f;
-#pragma unroll
-    for (int l = 0; l < L; ++l) s_b[l][f] = 0.f;
+    s_b[0][f] = 0.f;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) s_w1[c][f] = 0.f;
   }
@@ -497,17 +528,20 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
             const E* arow = Dt + (ob * 16 + n) * LD + T::S * q;
             const E* brow = Hall + ((l - 2) * W + ib * 16 + n) * LD + T::S * q;
 #pragma unroll
-            for (int ks = 0; ks < NB / T::KS; ++ks)
-              acc[l - 2][o] = T::mma(T::lds_op(arow + ks * T::KS, DPL), T::lds_op(brow + ks * T::KS, HPL),
-                                     acc[l - 2][o]);
+            for (int ks = 0; ks < NB / T::KS; ++ks) {
+              const typename T::op av = T::lds_op(arow + ks * T::KS, DPL);
+              acc[l - 2][o] = T::mma(av, T::lds_op(brow + ks * T::KS, HPL), acc[l - 2][o]);
+              // db_l = delta_l times a ones column, once per output row block
+              if (ib == 0) bacc[l - 2] = T::row_sum(av, bacc[l - 2]);
+            }
           }
         }
       }
-      // db_l[f] = sum_n delta_l[f][n]; layer 1 also dW_1[f][c] = sum_n delta_1[f][n] z_c[n]
+      // layer 1: db_1[f] = sum_n delta_1[f][n], dW_1[f][c] = sum_n delta_1[f][n] z_c[n]
 #pragma unroll
       for (int f = 0; f < FPT; ++f) {
         const int fq = (tid >> 2) + f * (NTH / 4);
-        if (fq < W) {
+        if (l == 1 && fq < W) {
           const E* dr = Dt + fq * LD + q4 * QN;
           float sb = 0.f;
           float sw[DIM];
@@ -520,10 +554,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
 #pragma unroll
               for (int c = 0; c < DIM; ++c) sw[c] += dv * Zs[c][q4 * QN + k];
           }
-          s_b[l - 1][f] += sb;
-          if (l == 1)
+          s_b[0][f] += sb;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) s_w1[c][f] += sw[c];
+          for (int c = 0; c < DIM; ++c) s_w1[c][f] += sw[c];
         }
       }
       if (l >= 2) {
@@ -561,6 +594,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
         for (int i = 0; i < 4; ++i) {
           const int orow = ob * 16 + 4 * q + i;
           row[off + int64_t(orow) * W + ib * 16 + n] = acc[l - 2][o][i];
+          if (ib == 0 && n == 0) row[off + int64_t(W) * W + orow] = bacc[l - 2][i];
         }
       }
     }
@@ -577,11 +611,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_mlp_bwd_mfma(Geom geo, int64_t P
     const int fq = (tid >> 2) + f * (NTH / 4);
     const bool ok = fq < W;
     reduce4(s_wout[f], off_layer(L + 1, DIM, W) + fq, ok);
-#pragma unroll
-    for (int l = 1; l <= L; ++l) {
-      const int in_dim = l == 1 ? DIM : W;
-      reduce4(s_b[l - 1][f], off_layer(l, DIM, W) + int64_t(W) * in_dim + fq, ok);
-    }
+    reduce4(s_b[0][f], off_layer(1, DIM, W) + int64_t(W) * DIM + fq, ok);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) reduce4(s_w1[c][f], int64_t(fq) * DIM + c, ok);
   }
