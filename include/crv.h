@@ -74,9 +74,10 @@ typedef enum {
                           hi/lo-split operands (about 2^-16 relative error),
                           float32 accumulate; everything else float32 */
   CRV_PREC_BF16X3F = 4 /* split-bf16 forward (the pressure that the residual,
-                          loss and projection see), plain bf16 products in the
-                          network backward (gradient about 2^-9 relative);
-                          everything else float32 */
+                          loss and projection see); in the network backward
+                          the weights stay split and activations and deltas
+                          are rounded to bf16 (gradient error about 2^-9,
+                          random across nodes); everything else float32 */
 } crv_precision;
 
 typedef struct {

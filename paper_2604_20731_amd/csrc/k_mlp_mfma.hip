@@ -55,6 +55,8 @@ struct MM<NET_F32> {
   __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  using wop = op;  // weight operand
+  __device__ static inline f32x4_t mma_w(wop a, op b, f32x4_t c) { return mma(a, b, c); }
   static constexpr int NPL = 1;                 // LDS planes per value
   __device__ static inline op frag(const felem* p) { return *p; }
   __device__ static inline op from(const float* v) { return v[0]; }
@@ -76,6 +78,8 @@ struct MM<NET_BF16> {
   __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  using wop = op;
+  __device__ static inline f32x4_t mma_w(wop a, op b, f32x4_t c) { return mma(a, b, c); }
   static constexpr int NPL = 1;
   __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline op from(const float* v) {
@@ -117,6 +121,8 @@ struct MM<NET_X3> {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
   }
+  using wop = op;
+  __device__ static inline f32x4_t mma_w(const wop& a, const op& b, f32x4_t c) { return mma(a, b, c); }
   // fragments hold the hi plane, then (64*S further) the lo plane
   __device__ static inline op frag(const felem* p) {
     return op{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + 64 * S)};
@@ -160,9 +166,12 @@ struct MM<NET_X3> {
   }
 };
 
-// Backward of the mixed form: plain bf16 products on the split-bf16 fragments
-// (hi plane only); stores both planes when Adam updates a weight, so the
-// split-bf16 forward keeps reading exact splits.
+// Backward of the mixed form: activations and deltas rounded to bf16, weights
+// kept split (hi and lo planes of the split-bf16 fragments), so a weight
+// product is w_hi.a + w_lo.a (two bf16 MFMAs) and the products of
+// activations with deltas (dW, db) are single bf16 MFMAs.  The rounding left is
+// that of the activations and deltas (2^-9, not systematic across nodes); the
+// weights the backward differentiates are the forward's to 2^-16.
 template <>
 struct MM<NET_MIX> {
   static constexpr int S = 8, KS = 32, NP = 2;
@@ -174,7 +183,14 @@ struct MM<NET_MIX> {
   __device__ static inline f32x4_t mma(op a, op b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
-  __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
+  using wop = SplitOp;
+  __device__ static inline f32x4_t mma_w(const wop& w, op b, f32x4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.l, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.h, b, c, 0, 0, 0);
+  }
+  __device__ static inline wop frag(const felem* p) {
+    return wop{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + 64 * S)};
+  }
   __device__ static inline op from(const float* v) {
     op o;
 #pragma unroll
@@ -321,7 +337,7 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
-        acc[mb] = T::mma(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
+        acc[mb] = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
 #pragma unroll
     for (int t = 0; t < NR; ++t) h[t] = tanh_fast(acc[t >> 2][t & 3]);
   }
@@ -568,7 +584,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
           for (int i = 0; i < 4; ++i) c2[i] = 0.f;
 #pragma unroll
           for (int ks = 0; ks < NKS; ++ks)
-            c2 = T::mma(T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
+            c2 = T::mma_w(T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float hv = T::lds_get(Hall + ((l - 2) * W + cfeat(mb * 4 + i, q)) * LD + col, HPL);

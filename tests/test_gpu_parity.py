@@ -61,8 +61,9 @@ def test_loss_and_gradients(prec, name, over):
     say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
     tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4, "bf16x3f": 1e-4}[prec]
     # mixed form: loss and dlogK come from the split-bf16 forward (1e-4); the
-    # network backward runs on bf16 products (2^-9 per product), so dtheta gets 3e-2
-    assert el <= tol and egl < tol and eg < (3e-2 if prec == "bf16x3f" else tol)
+    # network backward rounds activations and deltas to bf16 (2^-9 each, random
+    # across nodes), so dtheta gets 3e-3 (measured up to 1.0e-3)
+    assert el <= tol and egl < tol and eg < (3e-3 if prec == "bf16x3f" else tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
