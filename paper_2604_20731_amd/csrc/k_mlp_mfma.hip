@@ -211,6 +211,19 @@ struct MM<NET_MIX> {
   __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { *p = o[v]; }
 };
 
+// tanh(a) = 1 - 2 / (2^(K a) + 1) with K = 2 / ln 2.  Every weight and bias
+// that feeds a hidden pre-activation on the forward side (first-layer W1, b1,
+// hidden biases, and the forward fragments of the hidden-to-hidden weights)
+// is stored pre-multiplied by K, so the products deliver K a directly and the
+// activation costs one exp2, one add, one reciprocal and one fma.  The
+// transposed (backward) fragments and the output layer are not scaled.
+constexpr float kTanhScale = 2.8853900817779268f;
+
+__device__ inline float tanh_of_scaled(float ka) {
+  const float e = __builtin_amdgcn_exp2f(ka);
+  return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+}
+
 // feature held by lane group q in its flat accumulator register t (t = 4 mb + i)
 __host__ __device__ inline int cfeat(int t, int q) { return 16 * (t >> 2) + 4 * q + (t & 3); }
 // inverse: register t and lane group q holding feature f
@@ -256,7 +269,7 @@ __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, i
   const int a = 16 * mb + r;                 // row of the A operand
   const int k = cfeat(ks * T::S + v, q);     // contraction feature
   const float* Wl = th + off_layer(hl + 2, dim, W);
-  const float w = dir == 0 ? Wl[int64_t(a) * W + k] : Wl[int64_t(k) * W + a];
+  const float w = dir == 0 ? kTanhScale * Wl[int64_t(a) * W + k] : Wl[int64_t(k) * W + a];
   T::put(frag + frag_index<MODE>(hl, dir, mb, ks, lane, v, W), w);
 }
 
@@ -276,7 +289,8 @@ __device__ inline void node_z(int64_t p, int n, int ne, float* z, bool* interior
 }
 
 // Small parameters staged in LDS per block: W1 (W x DIM), b1, the hidden
-// biases b_2..b_L, w_out, b_out -- W (DIM + L + 1) + 1 floats.
+// biases b_2..b_L (these three scaled by kTanhScale), w_out, b_out --
+// W (DIM + L + 1) + 1 floats.
 template <int W, int L, int DIM>
 struct Small {
   static constexpr int W1 = 0, B1 = W * DIM, BH = B1 + W, WO = BH + (L - 1) * W, BO = WO + W;
@@ -289,7 +303,7 @@ struct Small {
         const int l = (k - BH) / W + 2, f = (k - BH) % W;          // bias of hidden layer l
         v = th[off_layer(l, DIM, W) + int64_t(W) * W + f];
       } else v = th[off_layer(L + 1, DIM, W) + (k - WO)];          // w_out, b_out
-      sp[k] = v;
+      sp[k] = k < WO ? kTanhScale * v : v;
     }
   }
 };
@@ -318,7 +332,7 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
       float a = b1[f];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) a += W1[f * DIM + c] * z[c];
-      h[t] = tanh_fast(a);
+      h[t] = tanh_of_scaled(a);
     }
   }
 #pragma unroll
@@ -339,7 +353,7 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
       for (int ks = 0; ks < NKS; ++ks)
         acc[mb] = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
 #pragma unroll
-    for (int t = 0; t < NR; ++t) h[t] = tanh_fast(acc[t >> 2][t & 3]);
+    for (int t = 0; t < NR; ++t) h[t] = tanh_of_scaled(acc[t >> 2][t & 3]);
   }
 }
 
@@ -703,8 +717,9 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
   if (hl >= hidden - 1 || within >= int64_t(W) * W) return;
   const int o = int(within / W), i = int(within % W);
   int tt, qq;
-  cfeat_inv(i, &tt, &qq);  // forward fragment: row o, contraction feature i
-  T::put(frag + frag_index<MODE>(hl, 0, o >> 4, tt / T::S, (o & 15) + 16 * qq, tt % T::S, W), nw);
+  cfeat_inv(i, &tt, &qq);  // forward fragment (scaled): row o, contraction feature i
+  T::put(frag + frag_index<MODE>(hl, 0, o >> 4, tt / T::S, (o & 15) + 16 * qq, tt % T::S, W),
+         kTanhScale * nw);
   cfeat_inv(o, &tt, &qq);  // backward fragment: row i, contraction feature o
   T::put(frag + frag_index<MODE>(hl, 1, i >> 4, tt / T::S, (i & 15) + 16 * qq, tt % T::S, W), nw);
 }
