@@ -162,7 +162,8 @@ def run_single(prob, precision, steps, warmup, pretrain, profile):
 
 def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
     """Aggregate coupled steps/s of several 512^2 scenarios, each on its own
-    stream, their captured steps overlapping on the device."""
+    stream, stepped together by crv_step_batch (their captured steps overlap
+    on the device)."""
     import torch
     from paper_2604_20731_amd import crv, inputs
     scs = []
@@ -175,14 +176,13 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
         sc.pretrain_pressure(pretrain)
         p, _, _ = sc.fields()
         scs.append((sc, cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)))
+    ctxs, dts = [sc for sc, _ in scs], [dt for _, dt in scs]
     for _ in range(warmup):
-        for sc, dt in scs:
-            sc.step(dt)
+        crv.step_batch(ctxs, dts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        for sc, dt in scs:
-            sc.step(dt)
+        crv.step_batch(ctxs, dts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for sc, _ in scs:

@@ -143,6 +143,14 @@ crv_status crv_sync(crv_ctx* ctx);
  * saturation) surface as CRV_ENUMERIC at the next synchronising call. */
 crv_status crv_step(crv_ctx* ctx, double dt);
 
+/* Serving form of crv_step: one coupled step of length dts[i] for each of
+ * the n contexts (all validated first: CRV_EINVAL for a NULL context or a
+ * bad dt, CRV_ESTATE for a context not pretrained; nothing is enqueued
+ * then).  Each step is enqueued on its own context's stream without any host
+ * wait, so contexts on distinct streams advance concurrently on the device;
+ * results are those of n crv_step calls.  Asynchronous like crv_step. */
+crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n);
+
 /* Outputs (any may be NULL): p_nodal (N+1)^d network pressure m*NN,
  * s_coefs nb^d, s_nodal (N+1)^d saturation at the nodes. Synchronises. */
 crv_status crv_get_fields(crv_ctx* ctx, double* p_nodal, double* s_coefs, double* s_nodal);

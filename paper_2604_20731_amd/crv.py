@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
 
 EXPORTED = [
     "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
-    "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_get_fields", "crv_loss_grad",
+    "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_step_batch",
+    "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
     "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
     "crv_saturation_substeps", "crv_profile_enable", "crv_profile_read", "crv_destroy",
@@ -69,6 +70,7 @@ def _load() -> C.CDLL:
         "crv_init": [cfgp, dp, dp, dp, C.c_int, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)],
         "crv_pretrain_pressure": [vp, C.c_int, dp],
         "crv_step": [vp, C.c_double],
+        "crv_step_batch": [C.POINTER(vp), dp, C.c_int],
         "crv_train_async": [vp, C.c_int],
         "crv_sync": [vp],
         "crv_get_fields": [vp, dp, dp, dp],
@@ -284,6 +286,17 @@ class Scenario:
             _check(LIB.crv_profile_read(self.ctx, k, C.byref(ms), C.byref(n)))
             out[name] = (ms.value, n.value)
         return out
+
+
+def step_batch(scenarios, dts):
+    """crv_step_batch: one coupled step for each scenario (each on its own
+    stream, no host wait between them)."""
+    n = len(scenarios)
+    if len(dts) != n:
+        raise ValueError("one dt per scenario")
+    ctxs = (C.c_void_p * n)(*[sc.ctx for sc in scenarios])
+    d = _f64(dts)
+    _check(LIB.crv_step_batch(ctxs, _dp(d), n))
 
 
 def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:

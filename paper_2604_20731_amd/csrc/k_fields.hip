@@ -776,6 +776,14 @@ void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, doub
 }
 
 // ---------------------------------------------------------------------------
+// one float64 into device memory, stream-ordered (the substep length read by
+// a captured step; no host wait)
+__global__ void k_set_f64(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void launch_set_f64(double* p, double v, hipStream_t st) { k_set_f64<<<1, 64, 0, st>>>(p, v); }
+
 __global__ void k_bump(long long* t) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *t = *t + 1;
 }

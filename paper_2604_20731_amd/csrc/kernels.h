@@ -59,6 +59,8 @@ template <typename Real>
 void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, double scale,
                            Real* lt, Real* inv_d, hipStream_t st);
 
+// *p = v on the stream (device memory, no host synchronisation)
+void launch_set_f64(double* p, double v, hipStream_t st);
 template <typename Real>
 void launch_fill(Real* p, size_t n, Real v, hipStream_t st);
 template <typename Src, typename Dst>

@@ -634,13 +634,11 @@ struct Solver : SolverBase {
     for (int i = 0; i < cfg.adam_iters; ++i) iteration();
   }
 
+  // tau into device memory by a one-thread kernel: stream-ordered before the
+  // step that reads it, and the host does not wait
   crv_status set_tau(double tau) {
-    // the host value lives until the copy is done: stream-ordered, then synchronised
-    static thread_local double host_tau;
-    host_tau = tau;
-    CRV_HIP(hipMemcpyAsync(b.tau, &host_tau, sizeof(double), hipMemcpyHostToDevice, st));
-    CRV_HIP(hipStreamSynchronize(st));
-    return CRV_OK;
+    launch_set_f64(b.tau, tau, st);
+    return check_launch();
   }
 
   crv_status step(double dt) override {
@@ -943,6 +941,20 @@ crv_status crv_step(crv_ctx* c, double dt) {
   CRV_CTX(c);
   if (!sv.pretrained) return fail(CRV_ESTATE, "crv_step before crv_pretrain_pressure");
   return sv.step(dt);
+}
+
+crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
+  if (n < 0 || (n > 0 && (!ctxs || !dts))) return fail(CRV_EINVAL, "bad batch arrays");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !ctxs[i]->impl) return fail(CRV_EINVAL, "context is NULL");
+    if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(CRV_EINVAL, "dt must be > 0");
+    if (!ctxs[i]->impl->pretrained) return fail(CRV_ESTATE, "crv_step_batch before crv_pretrain_pressure");
+  }
+  for (int i = 0; i < n; ++i) {
+    const crv_status s = ctxs[i]->impl->step(dts[i]);
+    if (s) return s;
+  }
+  return CRV_OK;
 }
 
 crv_status crv_get_fields(crv_ctx* c, double* p_nodal, double* s_coefs, double* s_nodal) {

@@ -49,3 +49,41 @@ def test_budget_limits_concurrency():
     out = srv.run(arrivals)
     assert out["scenarios"] == len(arrivals)
     assert out["max_queue_wait_s"] >= 0.0
+
+
+def test_step_batch_equals_single_steps():
+    """crv_step_batch over scenarios on their own streams gives bitwise the
+    fields of one crv_step per scenario; invalid batches are rejected before
+    anything is enqueued."""
+    import torch
+    from paper_2604_20731_amd import crv
+    from paper_2604_20731_amd.serve import cfl_dt, scenario_problem
+
+    arrivals = _mix()[:3]
+
+    def build():
+        out = []
+        for a in arrivals:
+            prob = scenario_problem(a)
+            cfg = crv.config(dim=2, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
+                             hidden=prob.hidden, precision="bf16x3")
+            sc = crv.Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0,
+                              stream=torch.cuda.Stream())
+            sc.pretrain_pressure(20)
+            dt = cfl_dt(sc.fields()[0], prob.log_perm, prob.porosity, prob.n_elem)
+            out.append((sc, dt))
+        return out
+
+    batch, single = build(), build()
+    for _ in range(2):
+        crv.step_batch([sc for sc, _ in batch], [dt for _, dt in batch])
+        for sc, dt in single:
+            sc.step(dt)
+    for (sb, _), (ss, _) in zip(batch, single):
+        pb, cb, _ = sb.fields()
+        ps, cs, _ = ss.fields()
+        assert np.array_equal(pb, ps) and np.array_equal(cb, cs)
+    with pytest.raises(crv.CrvError) as ei:
+        crv.step_batch([sc for sc, _ in batch], [1e-3, -1.0, 1e-3])
+    assert ei.value.status == crv.CRV_EINVAL
+    say(f"step_batch: {len(batch)} scenarios bitwise equal to single steps")
