@@ -64,3 +64,26 @@ def test_defaults():
     cfg = crv.config()
     assert cfg.lr == 1e-4 and cfg.adam_iters == 100 and cfg.substeps == 10
     assert cfg.mu_w == 1.0 and cfg.mu_g == 0.1 and cfg.relperm_exp == 2.0
+
+
+def test_batch_and_state_argument_errors():
+    """Argument checks that run before any device work (no GPU needed)."""
+    import ctypes as C
+    assert crv.LIB.crv_step_batch(None, None, -1) == crv.CRV_EINVAL
+    assert crv.LIB.crv_step_batch(None, None, 1) == crv.CRV_EINVAL
+    ctxs = (C.c_void_p * 1)(None)
+    dts = (C.c_double * 1)(1e-3)
+    assert crv.LIB.crv_step_batch(ctxs, dts, 1) == crv.CRV_EINVAL
+    assert crv.LIB.crv_step_batch(None, None, 0) == crv.CRV_OK
+    assert crv.LIB.crv_set_log_perm(None, None) == crv.CRV_EINVAL
+    assert crv.LIB.crv_last_error().decode()  # a message accompanies every error
+
+
+def test_precision_names_cover_the_enum():
+    import re
+    text = open(os.path.join(ROOT, "include", "crv.h")).read()
+    enum = dict((k, int(v)) for k, v in re.findall(r"CRV_PREC_(\w+)\s*=\s*(\d+)", text))
+    assert sorted(enum.values()) == sorted(crv.PREC.values())
+    for name in ("fp32", "bf16", "fp64", "bf16x3", "bf16x3f"):
+        cfg = crv.config(width=64, hidden=4, precision=name)
+        assert crv.workspace_size(cfg) > 0
