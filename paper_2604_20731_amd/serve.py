@@ -64,7 +64,7 @@ class Job:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 16, precision: str = "bf16x3",
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 16, precision: str = "bf16x3f",
                  pretrain_iters: int = 200, steps: int = 20, device: str = "cuda:0",
                  keep_fields: bool = False):
         self.budget = int(hbm_budget_bytes)
@@ -76,8 +76,9 @@ class Server:
         self.keep_fields = keep_fields
 
     def precision_for(self, width: int) -> str:
-        """bf16x3 where that path exists, plain bf16 otherwise."""
-        if self.precision == "bf16x3" and width not in (32, 64):
+        """The split-bf16 forms where they exist (widths 32 and 64), plain bf16
+        otherwise."""
+        if self.precision in ("bf16x3", "bf16x3f") and width not in (32, 64):
             return "bf16"
         return self.precision
 

@@ -132,3 +132,29 @@ def test_coupled_trajectory_c1(prec, tol):
     assert len(hist) == n_pre + n_steps * 100
     say(f"  loss history {rel(hist, np.array(orc.loss_history)):.3e}")
     assert rel(hist, np.array(orc.loss_history)) < tol
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 5e-3),
+                                      ("bf16x3f", 5e-3)])
+def test_coupled_trajectory_c1_full(prec, tol):
+    """The whole C1 configuration: 2000 pretraining iterations, then 10 coupled
+    steps of 100 Adam iterations (lr 1e-4), fields compared after every step."""
+    say("coupled c1 full", prec)
+    prob = problem("c1")
+    sc = scenario_for(prob, prec)
+    orc = oracle_for(prob, lr=1e-4)
+    l_gpu = sc.pretrain_pressure(prob.pretrain_iters)
+    orc.pretrain(prob.pretrain_iters)
+    say(f"  pretrain loss {abs(l_gpu - orc.loss_history[-1]) / abs(orc.loss_history[-1]):.3e}")
+    dt = cfl_dt(orc)
+    worst = 0.0
+    for k in range(prob.steps):
+        sc.step(dt)
+        orc.step(dt)
+        p, s, sn = sc.fields()
+        pr, sr, snr = orc.fields()
+        e = max(rel(p, pr), rel(s, sr), rel(sn, snr))
+        worst = max(worst, e)
+        say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
+    assert worst < tol
