@@ -79,4 +79,37 @@ __device__ inline T block_sum(T v, T* sbuf) {
 
 inline int cdiv(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
+// a = q n + r for 0 <= a < 2^31 without an integer division: q from a float64
+// product with 1/n (off by at most one near multiples of n), then corrected.
+__device__ inline void divmod_u32(uint32_t a, uint32_t n, uint32_t* q, uint32_t* r) {
+  uint32_t qq = uint32_t(double(a) * (1.0 / double(n)));
+  int64_t rr = int64_t(a) - int64_t(qq) * n;
+  if (rr < 0) {
+    --qq;
+    rr += n;
+  } else if (rr >= int64_t(n)) {
+    ++qq;
+    rr -= n;
+  }
+  *q = qq;
+  *r = uint32_t(rr);
+}
+
+// grid indices (i, j[, k]) of node p on n^dim nodes, x fastest (p < 2^31)
+template <int DIM>
+__device__ inline void node_ijk(int64_t p, int n, int* i, int* j, int* k) {
+  uint32_t q1, r1;
+  divmod_u32(uint32_t(p), uint32_t(n), &q1, &r1);
+  *i = int(r1);
+  if (DIM == 3) {
+    uint32_t q2, r2;
+    divmod_u32(q1, uint32_t(n), &q2, &r2);
+    *j = int(r2);
+    *k = int(q2);
+  } else {
+    *j = int(q1);
+    *k = 0;
+  }
+}
+
 }  // namespace crv

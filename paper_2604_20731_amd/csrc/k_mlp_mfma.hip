@@ -275,13 +275,13 @@ __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, i
 
 template <int DIM>
 __device__ inline void node_z(int64_t p, int n, int ne, float* z, bool* interior) {
-  const int i = int(p % n), j = int((p / n) % n);
+  int i, j, k;
+  node_ijk<DIM>(p, n, &i, &j, &k);
   const double inv = 1.0 / double(ne);
   z[0] = float(2.0 * (double(i) * inv) - 1.0);
   z[1] = float(2.0 * (double(j) * inv) - 1.0);
   bool in = i > 0 && i < ne && j > 0 && j < ne;
   if (DIM == 3) {
-    const int k = int(p / (int64_t(n) * n));
     z[DIM - 1] = float(2.0 * (double(k) * inv) - 1.0);
     in = in && k > 0 && k < ne;
   }

@@ -21,7 +21,9 @@ template <typename Real, int DIM>
 __device__ inline Real adjoint_at(const Geom& g, const Real* __restrict__ q,
                                   const Real* __restrict__ alpha, int64_t p, int64_t* iq) {
   const int64_t n = g.n;
-  const int i = int(p % n), j = int((p / n) % n), k = DIM == 3 ? int(p / (n * n)) : 1;
+  int i, j, k;
+  node_ijk<DIM>(p, int(n), &i, &j, &k);
+  if (DIM == 2) k = 1;
   const bool in = i >= 1 && i <= g.m && j >= 1 && j <= g.m && (DIM == 2 || (k >= 1 && k <= g.m));
   if (!in) {
     *iq = -1;
