@@ -247,19 +247,21 @@ int launch_mlp_backward(const Geom& g, const MlpShape& s, const Real* theta, con
 // out[c][p] = sum_{r in chunk c} in[r][p], chunks of 64 rows, fixed order.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_reduce_rows(const Real* __restrict__ in, int rows,
-                                                     int64_t P, Real* __restrict__ out) {
+                                                     int64_t P, int64_t ld,
+                                                     Real* __restrict__ out) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const int r0 = blockIdx.y * 64, r1 = min(rows, r0 + 64);
   Real s = 0;
-  for (int r = r0; r < r1; ++r) s += in[int64_t(r) * P + p];
+  for (int r = r0; r < r1; ++r) s += in[int64_t(r) * ld + p];
   out[int64_t(blockIdx.y) * P + p] = s;
 }
 
 template <typename Real>
-void launch_reduce_rows(const Real* in, int rows, int64_t P, Real* scratch, Real* out,
+void launch_reduce_rows(const Real* in, int rows, int64_t P, int64_t ld, Real* scratch, Real* out,
                         hipStream_t st) {
   const Real* src = in;
+  int64_t src_ld = ld;
   int nrows = rows;
   Real* bufs[2] = {scratch, scratch + int64_t(cdiv(rows, 64)) * P};
   int which = 0;
@@ -267,9 +269,10 @@ void launch_reduce_rows(const Real* in, int rows, int64_t P, Real* scratch, Real
     const int nout = cdiv(nrows, 64);
     Real* dst = (nout == 1) ? out : bufs[which];
     dim3 grid(cdiv(P, 256), nout);
-    k_reduce_rows<Real><<<grid, 256, 0, st>>>(src, nrows, P, dst);
+    k_reduce_rows<Real><<<grid, 256, 0, st>>>(src, nrows, P, src_ld, dst);
     if (nout == 1) break;
     src = dst;
+    src_ld = P;
     nrows = nout;
     which ^= 1;
   }
@@ -306,7 +309,7 @@ void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double
                                       hipStream_t);                                            \
   template int launch_mlp_backward<R>(const Geom&, const MlpShape&, const R*, const R*, R*,    \
                                       hipStream_t);                                            \
-  template void launch_reduce_rows<R>(const R*, int, int64_t, R*, R*, hipStream_t);            \
+  template void launch_reduce_rows<R>(const R*, int, int64_t, int64_t, R*, R*, hipStream_t);            \
   template void launch_adam<R>(int64_t, R*, R*, R*, const R*, double, double, double, double,  \
                                const long long*, hipStream_t);
 CRV_INST(float)

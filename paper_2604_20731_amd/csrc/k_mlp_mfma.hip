@@ -421,7 +421,7 @@ constexpr int bwd_min_waves() {
 }
 
 template <int W, int L, int MODE, int DIM, int NW>
-__global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd_mfma(Geom geo, int64_t P,
+__global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd_mfma(Geom geo, int64_t ldp,
                                                              const float* __restrict__ th,
                                                              const typename MM<MODE>::felem* __restrict__ frag,
                                                              const float* __restrict__ qg,
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   }
 
   // ---- this block's partial gradient row ----
-  float* row = partials + int64_t(blockIdx.x) * P;
+  float* row = partials + int64_t(blockIdx.x) * ldp;
 #pragma unroll
   for (int l = 2; l <= L; ++l) {
     const int64_t off = off_layer(l, DIM, W);
@@ -654,23 +654,53 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
 }
 
 // ---------------------------------------------------------------------------
-// Fused gradient reduction + Adam + fragment update.  Block = RW waves over
-// 64 parameters (one per lane); wave w sums partial rows w, w+RW, ... and the
-// RW wave sums are added in a fixed order.  The updated weight of a
-// hidden-to-hidden layer is written straight into its two fragment slots.
-// One extra block sums the iteration's loss partials.
+// Fused gradient reduction + Adam + fragment update.  Partial rows have pitch
+// ldp (a multiple of 4 floats).  Block = RW waves over 64 parameters: lane
+// (c = lane%16, g = lane/16) of wave w reads parameters 4c..4c+3 (one 16-byte
+// load) of rows 4w+g, 4w+g+4RW, ...; the 4RW partial sums are added in a
+// fixed order.  The updated weight of a hidden-to-hidden layer is written
+// straight into its two fragment slots.  One extra block sums the
+// iteration's loss partials.
 // ---------------------------------------------------------------------------
 constexpr int RW = 16;  // waves per reduction block
 
 template <int MODE>
+__device__ inline void adam_one(int64_t p, float gg, float* __restrict__ th, float* __restrict__ m,
+                                float* __restrict__ v, float lr, float b1, float b2, float eps,
+                                float c1, float c2, int dim, int W, int hidden,
+                                typename MM<MODE>::felem* __restrict__ frag) {
+  using T = MM<MODE>;
+  const float mm = b1 * m[p] + (1.f - b1) * gg;
+  const float vv = b2 * v[p] + (1.f - b2) * gg * gg;
+  m[p] = mm;
+  v[p] = vv;
+  const float nw = th[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  th[p] = nw;
+  // hidden-to-hidden weight? layer l = 2..hidden occupies [off_l, off_l + W*W)
+  // (parameter counts are far below 2^31: 32-bit index arithmetic)
+  const int base = W * dim + W;
+  if (p < base) return;
+  const int rel = int(p) - base, per = W * W + W;
+  const int hl = rel / per;
+  const int within = rel - hl * per;
+  if (hl >= hidden - 1 || within >= W * W) return;
+  const int o = within / W, i = within - o * W;
+  int tt, qq;
+  cfeat_inv(i, &tt, &qq);  // forward fragment (scaled): row o, contraction feature i
+  T::put(frag + frag_index<MODE>(hl, 0, o >> 4, tt / T::S, (o & 15) + 16 * qq, tt % T::S, W),
+         kTanhScale * nw);
+  cfeat_inv(o, &tt, &qq);  // backward fragment: row i, contraction feature o
+  T::put(frag + frag_index<MODE>(hl, 1, i >> 4, tt / T::S, (i & 15) + 16 * qq, tt % T::S, W), nw);
+}
+
+template <int MODE>
 __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
-    const float* __restrict__ part, int rows, int64_t P, float* __restrict__ th,
+    const float* __restrict__ part, int rows, int64_t P, int64_t ldp, float* __restrict__ th,
     float* __restrict__ m, float* __restrict__ v, double lr, double b1, double b2, double eps,
     const long long* __restrict__ t_dev, int dim, int W, int hidden,
     typename MM<MODE>::felem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
     double* __restrict__ hist, int cap) {
-  using T = MM<MODE>;
-  __shared__ float red[RW][64];
+  __shared__ f32x4_t red[4 * RW][16];
   if (blockIdx.x == gridDim.x - 1) {
     __shared__ double lb[64 * RW];
     double s = 0;
@@ -679,49 +709,38 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
     if (threadIdx.x == 0) hist[(*t_dev - 1) % cap] = tot;
     return;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
-  float s = 0.f;
-  if (p < P) {
-    int r = w;
-    for (; r + 3 * RW < rows; r += 4 * RW) {
-      const float a0 = part[int64_t(r) * P + p], a1 = part[int64_t(r + RW) * P + p];
-      const float a2 = part[int64_t(r + 2 * RW) * P + p], a3 = part[int64_t(r + 3 * RW) * P + p];
+  constexpr int RS = 4 * RW;  // row stride
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, c = lane & 15, rg = lane >> 4;
+  const int64_t p0 = int64_t(blockIdx.x) * 64 + 4 * c;
+  f32x4_t s = {0.f, 0.f, 0.f, 0.f};
+  if (p0 < P) {
+    const float* col = part + p0;
+    int r = 4 * w + rg;
+    for (; r + 3 * RS < rows; r += 4 * RS) {
+      const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r) * ldp);
+      const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r + RS) * ldp);
+      const f32x4_t a2 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r + 2 * RS) * ldp);
+      const f32x4_t a3 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r + 3 * RS) * ldp);
       s += a0;
       s += a1;
       s += a2;
       s += a3;
     }
-    for (; r < rows; r += RW) s += part[int64_t(r) * P + p];
+    for (; r < rows; r += RS) s += *reinterpret_cast<const f32x4_t*>(col + int64_t(r) * ldp);
   }
-  red[w][lane] = s;
+  red[4 * w + rg][c] = s;
   __syncthreads();
+  // wave 0: one parameter per lane (lane = 4 c + component)
+  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
   if (w != 0 || p >= P) return;
-  float gg = red[0][lane];
+  const float* rf = reinterpret_cast<const float*>(&red[0][0]);
+  float gg = rf[lane];
 #pragma unroll
-  for (int k = 1; k < RW; ++k) gg += red[k][lane];
+  for (int k = 1; k < RS; ++k) gg += rf[k * 64 + lane];
   const double t = double(*t_dev);
   const float c1 = float(1.0 - pow(b1, t)), c2 = float(1.0 - pow(b2, t));
-  const float mm = float(b1) * m[p] + float(1.0 - b1) * gg;
-  const float vv = float(b2) * v[p] + float(1.0 - b2) * gg * gg;
-  m[p] = mm;
-  v[p] = vv;
-  const float nw = th[p] - float(lr) * (mm / c1) / (sqrtf(vv / c2) + float(eps));
-  th[p] = nw;
-  // hidden-to-hidden weight? layer l = 2..hidden occupies [off_l, off_l + W*W)
-  const int64_t base = int64_t(W) * dim + W;
-  if (p < base) return;
-  const int64_t rel = p - base, per = int64_t(W) * W + W;
-  const int hl = int(rel / per);
-  const int64_t within = rel % per;
-  if (hl >= hidden - 1 || within >= int64_t(W) * W) return;
-  const int o = int(within / W), i = int(within % W);
-  int tt, qq;
-  cfeat_inv(i, &tt, &qq);  // forward fragment (scaled): row o, contraction feature i
-  T::put(frag + frag_index<MODE>(hl, 0, o >> 4, tt / T::S, (o & 15) + 16 * qq, tt % T::S, W),
-         kTanhScale * nw);
-  cfeat_inv(o, &tt, &qq);  // backward fragment: row i, contraction feature o
-  T::put(frag + frag_index<MODE>(hl, 1, i >> 4, tt / T::S, (i & 15) + 16 * qq, tt % T::S, W), nw);
+  adam_one<MODE>(p, gg, th, m, v, float(lr), float(b1), float(b2), float(eps), c1, c2, dim, W,
+                 hidden, frag);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,15 +771,15 @@ void launch_pack_fragments(const float* theta, int dim, int width, int hidden, i
     k_pack_fragments<NET_X3><<<blocks, 256, 0, st>>>(theta, dim, width, hidden, static_cast<__bf16*>(frag));
 }
 
-void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
-                             float* v, double lr, double b1, double b2, double eps,
+void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t ldp, float* theta,
+                             float* m, float* v, double lr, double b1, double b2, double eps,
                              const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
                              int cap, hipStream_t st) {
   const int blocks = cdiv(P, 64) + 1;
   if (mode == NET_MIX) mode = NET_X3;  // same fragments
 #define CRV_RA(MM_, TT)                                                                           \
-  k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, theta, m, v, lr, b1, b2, eps, \
+  k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, ldp, theta, m, v, lr, b1, b2, eps, \
                                                   t_dev, dim, width, hidden, static_cast<TT*>(frag), \
                                                   loss_part, loss_np, loss_hist, cap)
   if (mode == NET_F32) CRV_RA(NET_F32, float);
@@ -852,29 +871,29 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 }
 
 template <int W, int L, int MODE>
-static void bwd_inst(const Geom& g, int64_t P, const float* th, const void* frag, const float* q,
+static void bwd_inst(const Geom& g, int64_t ldp, const float* th, const void* frag, const float* q,
                      const float* alpha, const float* res, float* partials, float* loss_part,
                      int blocks, hipStream_t st) {
   constexpr int NW = bwd_nw(W);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, q, alpha, res,
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
                                                                     partials, loss_part);
       return;
     }
   }
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, P, th, fr, q, alpha, res,
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
                                                                 partials, loss_part);
 }
 
-void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
+void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
                               float* loss_part, int blocks, hipStream_t st) {
 #define CRV_BW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) \
-    return bwd_inst<WW, LL, MM_>(g, P, theta, frag, q, alpha, res, partials, loss_part, blocks, st);
+    return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, st);
   CRV_FOR_SHAPES(CRV_BW)
 #undef CRV_BW
 }

@@ -112,9 +112,9 @@ template <typename Real>
 int launch_mlp_backward(const Geom& g, const MlpShape& s, const Real* theta, const Real* gu,
                         Real* partials, hipStream_t st);
 int mlp_backward_rows(const Geom& g, const MlpShape& s, int real_bytes);
-// fixed-order column sums of partials (rows x P) -> out (P); uses scratch
+// fixed-order column sums of partials (rows x P, row pitch ld) -> out (P); uses scratch
 template <typename Real>
-void launch_reduce_rows(const Real* in, int rows, int64_t P, Real* scratch, Real* out,
+void launch_reduce_rows(const Real* in, int rows, int64_t P, int64_t ld, Real* scratch, Real* out,
                         hipStream_t st);
 template <typename Real>
 void launch_adam(int64_t P, Real* theta, Real* m, Real* v, const Real* g, double lr,
@@ -136,15 +136,16 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 // backward blocks: at most cu_count x the blocks per CU that one block's LDS
 // allows; with query, also capped by the occupancy the compiled kernel reaches
 int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count, bool query);
-// partial gradient rows of sum_p g_u(p) NN(z_p) with g_u = 2 A^T q evaluated
-// per node from q and alpha; loss_part[block] = the block's share of RES . q
-void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t P,
+// partial gradient rows (pitch ldp, a multiple of 4) of sum_p g_u(p) NN(z_p)
+// with g_u = 2 A^T q evaluated per node from q and alpha; loss_part[block] =
+// the block's share of RES . q
+void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
                               float* loss_part, int blocks, hipStream_t st);
 // fixed-order sum of the partial rows + Adam + fragment update; one extra
 // block sums the loss partials into loss_hist[(t-1) % cap]
-void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, float* theta, float* m,
+void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t ldp, float* theta, float* m,
                              float* v, double lr, double b1, double b2, double eps,
                              const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,

@@ -157,7 +157,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.frag = cv.take<char>(size_t(std::max<int64_t>(4, mlp_fragment_bytes(c.width, c.hidden))));
   b.bwd_rows = uses_mfma(c) ? mlp_bwd_mfma_blocks(g, c.width, c.hidden, net_mode(c), kMaxCUs, false)
                             : mlp_backward_rows(g, ms, int(sizeof(Real)));
-  b.partials = cv.take<Real>(size_t(b.bwd_rows) * P);
+  b.partials = cv.take<Real>(size_t(b.bwd_rows) * ((P + 3) / 4 * 4));  // pitch ldp (MFMA) or P
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
   // loss partials: from the adjoint kernel, or one per fused network-backward block
   b.loss_np = std::max(adjoint_partials(g), b.bwd_rows);
@@ -509,13 +509,14 @@ struct Solver : SolverBase {
   // partial gradient rows of the network backward; returns the row count.
   // The matrix-core backward also leaves bwd_blocks loss partials.
   int adj_np = 0;
+  int64_t ldp() const { return (P + 3) / 4 * 4; }  // pitch of the matrix-core partial rows
   int loss_count() const { return mfma ? bwd_blocks : adj_np; }
   int backward() {
     tb(CRV_K_MLP_BWD);
     int rows = 0;
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, P, b.theta, b.frag, b.q, b.alpha,
+        launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, ldp(), b.theta, b.frag, b.q, b.alpha,
                                  b.res, b.partials, b.loss_part, bwd_blocks, st);
         rows = bwd_blocks;
       }
@@ -528,7 +529,7 @@ struct Solver : SolverBase {
   void grad_pass() {
     const int rows = backward();
     tb(CRV_K_GRAD_REDUCE);
-    launch_reduce_rows<Real>(b.partials, rows, P, b.red_scratch, b.grad, st);
+    launch_reduce_rows<Real>(b.partials, rows, P, mfma ? ldp() : P, b.red_scratch, b.grad, st);
     te();
   }
 
@@ -540,7 +541,7 @@ struct Solver : SolverBase {
       if (mfma) {
         const int rows = backward();
         tb(CRV_K_ADAM);
-        launch_reduce_adam_pack(b.partials, rows, P, b.theta, b.am, b.av, cfg.lr, cfg.beta1,
+        launch_reduce_adam_pack(b.partials, rows, P, ldp(), b.theta, b.am, b.av, cfg.lr, cfg.beta1,
                                 cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, mode,
                                 b.frag, b.loss_part, loss_count(), b.loss_hist, kLossCap, st);
         te();
