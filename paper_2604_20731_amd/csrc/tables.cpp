@@ -127,28 +127,6 @@ std::vector<double> mass_band(int ne, int r) {
   return band;
 }
 
-bool ldlt_band(const std::vector<double>& band, int n, int r, std::vector<double>& lt,
-               std::vector<double>& inv_d) {
-  // M(j, j+t) = band[j*(r+1)+t]; M = L D L^T with unit lower L of bandwidth r
-  std::vector<double> d(n, 0.0);
-  lt.assign(size_t(n) * (r > 0 ? r : 1), 0.0);
-  inv_d.assign(n, 0.0);
-  auto L = [&](int i, int j) -> double& { return lt[size_t(i) * r + (i - j - 1)]; };
-  for (int j = 0; j < n; ++j) {
-    double dj = band[size_t(j) * (r + 1)];
-    for (int k = std::max(0, j - r); k < j; ++k) dj -= L(j, k) * L(j, k) * d[k];
-    if (!(dj > 0)) return false;
-    d[j] = dj;
-    inv_d[j] = 1.0 / dj;
-    for (int i = j + 1; i <= std::min(n - 1, j + r); ++i) {
-      double mij = band[size_t(j) * (r + 1) + (i - j)];
-      for (int k = std::max(0, i - r); k < j; ++k) mij -= L(i, k) * L(j, k) * d[k];
-      L(i, j) = mij / dj;
-    }
-  }
-  return true;
-}
-
 void projection_table(int ne, int r, std::vector<int>& first, std::vector<double>& qv) {
   const int nb = ne + r;
   first.assign(nb, 0);

@@ -20,11 +20,6 @@ void local_basis(int ne, int r, double x, double* val, double* der, int* first);
 // Banded 1D mass matrix: band[i*(r+1) + t] = int B_i B_{i+t}, t = 0..r.
 std::vector<double> mass_band(int ne, int r);
 
-// Banded LDL^T of the symmetric band matrix (bandwidth r): L entries
-// lt[j*r + t-1] = L(j, j-t) (t = 1..r), inv_d[j] = 1/D(j).
-bool ldlt_band(const std::vector<double>& band, int n, int r,
-               std::vector<double>& lt, std::vector<double>& inv_d);
-
 // Projection weights Q(k, i) = int B_k(x) hat_i(x) dx; the nonzeros of row k
 // are nodes first(k) .. first(k)+r+1, stored qv[k*(r+2) + t].
 void projection_table(int ne, int r, std::vector<int>& first, std::vector<double>& qv);
