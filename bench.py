@@ -97,6 +97,28 @@ def measured_traffic(symbol, table=os.path.join(ROOT, "profiles", "b512_hbm_traf
     return None
 
 
+def kernel_rooflines(kernels, prob, precision):
+    """Add achieved rate, peak and fraction to every event-timed kernel with an
+    algorithmic work figure (matrix-core kernels in TFLOP/s, the rest in GB/s)."""
+    for name, kv in kernels.items():
+        work = algorithmic_work(name, prob, 1)
+        if not work:
+            continue
+        amount, unit = work
+        sec = kv["us_per_launch"] * 1e-6
+        if unit == "flop":
+            if name == "gram_dst":
+                peak = PEAK["fp32_tflops"]          # float32 matrix cores
+            else:
+                peak = {"fp32": PEAK["fp32_tflops"], "fp64": PEAK["fp64_tflops"]}.get(
+                    precision, PEAK["bf16_tflops"])
+            kv.update(achieved=amount / sec / 1e12, unit="TFLOP/s", peak=peak,
+                      frac=amount / sec / 1e12 / peak)
+        else:
+            kv.update(achieved=amount / sec / 1e9, unit="GB/s", peak=PEAK["hbm_gbs"],
+                      frac=amount / sec / 1e9 / PEAK["hbm_gbs"])
+
+
 def cfl_dt_from_pressure(p, perm, poro, ne):
     """dt = 0.5 h phi_min / (max lambda_g' max |K grad_+ p|) with the trained
     network pressure standing in for the direct solve (the serving rule)."""
@@ -213,6 +235,8 @@ def main():
     ap.add_argument("--serve", type=int, default=64, help="serving arrivals (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-big-kernels", dest="big_kernels", action="store_false",
+                    help="skip the per-kernel rates at 1025^2")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times): the "
                          "reference kernel that scales the HBM byte counters")
@@ -261,6 +285,15 @@ def main():
                      pretrain_iters=200, steps=20)
         out = srv.run(inputs.serving_mix(args.serve))
         serving = {k: v for k, v in out.items() if k != "results"}
+    kernel_rooflines(kernels, prob, args.precision)
+    big = None
+    if args.big_kernels:
+        log("per-kernel rates at 1025^2 (cubic, 2->4x128->1, plain bf16): one profiled step")
+        bprob = inputs.make_problem("c3", seed=0)
+        _, bk = run_single(bprob, "bf16", 1, 0, 10, True)
+        kernel_rooflines(bk, bprob, "bf16")
+        big = {"workload": "c3: 1024^2 cubic elements, 1025^2 nodes, 2->4x128->1, plain bf16 network",
+               "kernels": bk}
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
@@ -317,6 +350,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "kernels_1025": big,
     }
     print(json.dumps(out), flush=True)
 
