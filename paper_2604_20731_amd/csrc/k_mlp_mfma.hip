@@ -748,8 +748,7 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
 // ---------------------------------------------------------------------------
 bool mlp_mfma_supported(int dim, int width, int hidden, int mode) {
   if (dim == 3 ? hidden != 4 : (dim != 2 || !(hidden == 3 || hidden == 4))) return false;
-  if (mode == NET_MIX) mode = NET_X3;
-  if (mode == NET_BF16) return width == 32 || width == 64 || width == 128;
+  if (mode == NET_BF16 || mode == NET_MIX) return width == 32 || width == 64 || width == 128;
   return width == 32 || width == 64;
 }
 
@@ -803,19 +802,28 @@ static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u,
   k_mlp_fwd_mfma<W, L, MODE, 2><<<cdiv(tiles, 4), 256, 0, st>>>(g, th, fr, u, tb);
 }
 
-#define CRV_FOR_SHAPES(X)                                                                    \
+// instantiated shapes: the forward of the mixed form is the split-bf16 one;
+// the split-bf16 backward keeps two LDS planes and stops at width 64
+#define CRV_FWD_SHAPES(X)                                                                    \
+  X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
+  X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
+  X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
+  X(32, 3, NET_X3) X(64, 3, NET_X3) X(128, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)       \
+  X(128, 4, NET_X3)
+#define CRV_BWD_SHAPES(X)                                                                    \
   X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
   X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
   X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
   X(32, 3, NET_X3) X(64, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)                        \
-  X(32, 3, NET_MIX) X(64, 3, NET_MIX) X(32, 4, NET_MIX) X(64, 4, NET_MIX)
+  X(32, 3, NET_MIX) X(64, 3, NET_MIX) X(128, 3, NET_MIX) X(32, 4, NET_MIX) X(64, 4, NET_MIX)  \
+  X(128, 4, NET_MIX)
 
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
                              const void* frag, float* u, long long* t_bump, hipStream_t st) {
   if (mode == NET_MIX) mode = NET_X3;  // the forward of the mixed form is split bf16
 #define CRV_FW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) return fwd_inst<WW, LL, MM_>(g, theta, frag, u, t_bump, st);
-  CRV_FOR_SHAPES(CRV_FW)
+  CRV_FWD_SHAPES(CRV_FW)
 #undef CRV_FW
 }
 
@@ -862,7 +870,7 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
   const int nw = bwd_nw(width);
 #define CRV_BB(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) per_cu = bwd_per_cu<WW, LL, MM_>(g.dim, query);
-  CRV_FOR_SHAPES(CRV_BB)
+  CRV_BWD_SHAPES(CRV_BB)
 #undef CRV_BB
   const int64_t total = ipow(g.n, g.dim);
   const int nb = 16 * nw;
@@ -894,7 +902,7 @@ void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, in
 #define CRV_BW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) \
     return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, st);
-  CRV_FOR_SHAPES(CRV_BW)
+  CRV_BWD_SHAPES(CRV_BW)
 #undef CRV_BW
 }
 

@@ -185,8 +185,8 @@ static crv_status validate_config(const crv_config* c) {
   if ((c->precision == CRV_PREC_BF16 || c->precision == CRV_PREC_BF16X3 ||
        c->precision == CRV_PREC_BF16X3F) &&
       !mlp_mfma_supported(c->dim, c->width, c->hidden, net_mode(*c)))
-    return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 also 128) and 3 or 4 "
-                            "hidden layers (4 in 3D)");
+    return fail(CRV_EINVAL, "bf16 network paths need width 32 or 64 (bf16 and the mixed form also "
+                            "128) and 3 or 4 hidden layers (4 in 3D)");
   if (!(c->mu_w > 0) || !(c->mu_g > 0)) return fail(CRV_EINVAL, "viscosities must be > 0");
   if (!(c->relperm_exp >= 1)) return fail(CRV_EINVAL, "relperm_exp must be >= 1");
   if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) ||

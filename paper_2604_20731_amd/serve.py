@@ -76,9 +76,11 @@ class Server:
         self.keep_fields = keep_fields
 
     def precision_for(self, width: int) -> str:
-        """The split-bf16 forms where they exist (widths 32 and 64), plain bf16
-        otherwise."""
-        if self.precision in ("bf16x3", "bf16x3f") and width not in (32, 64):
+        """The requested form where it exists (split bf16 stops at width 64;
+        the mixed form covers 32, 64 and 128), plain bf16 otherwise."""
+        if self.precision == "bf16x3" and width not in (32, 64):
+            return "bf16"
+        if self.precision == "bf16x3f" and width not in (32, 64, 128):
             return "bf16"
         return self.precision
 

@@ -51,7 +51,8 @@ def test_gram_solve_3d(prec, ne):
 
 @pytest.mark.parametrize("prec,ne,width,hidden", [
     ("fp64", 8, 16, 2), ("fp64", 12, 32, 4), ("fp32", 12, 16, 2), ("fp32", 12, 32, 4),
-    ("fp32", 17, 64, 4), ("bf16x3", 12, 32, 4), ("bf16x3", 17, 64, 4), ("bf16", 12, 128, 4)])
+    ("fp32", 17, 64, 4), ("bf16x3", 12, 32, 4), ("bf16x3", 17, 64, 4), ("bf16", 12, 128, 4),
+    ("bf16x3f", 12, 128, 4)])
 def test_loss_and_gradients_3d(prec, ne, width, hidden):
     """Widths 32/64/128 with 4 hidden layers take the matrix-core network in
     fp32/bf16x3/bf16; 13^3 and 18^3 nodes leave a partial last tile."""
@@ -64,8 +65,9 @@ def test_loss_and_gradients_3d(prec, ne, width, hidden):
     glref = orc.loss_grad_logperm()
     el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
     say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
-    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4}[prec]
-    assert el <= tol and eg < tol and egl < tol
+    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4, "bf16x3f": 1e-4}[prec]
+    # mixed form: bf16 activations and deltas in the backward (dtheta 3e-3)
+    assert el <= tol and egl < tol and eg < (3e-3 if prec == "bf16x3f" else tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

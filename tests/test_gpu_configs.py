@@ -51,13 +51,15 @@ def test_c2_teacher_forced_steps(prec, tol):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 0.15)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 0.15), ("bf16x3f", 5e-3)])
 def test_c3_network_loss_and_fields(prec, tol):
     """bf16: products of bf16-rounded operands; the 0.15 bound on the network
     pressure and dtheta is the plain-bf16 error documented for this network
     shape (the split-bf16 form exists for widths up to 64).  The loss, a small
     difference of large terms (RES = A u - h^2 q), is reported but not bounded
-    in bf16: a 7% error in u moves it by O(1)."""
+    in bf16: a 7% error in u moves it by O(1).  The mixed form (split-bf16
+    forward, bf16 backward products on split weights) is held to the 5e-3
+    field tolerance."""
     say("c3 1025^2 cubic", prec)
     prob = problem("c3")
     sc = scenario_for(prob, prec)

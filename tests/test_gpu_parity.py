@@ -39,7 +39,7 @@ def test_gram_solve(prec, ne):
 
 GRAD_CASES = [("tiny", {}), ("c1", {}), ("c1", dict(n_elem=40, width=64, hidden=4)),
               ("c1", dict(degree=3, width=16, hidden=2)), ("c1", dict(n_elem=256, width=64, hidden=4)),
-              ("c1", dict(n_elem=100, width=32, hidden=4))]
+              ("c1", dict(n_elem=100, width=32, hidden=4)), ("c1", dict(n_elem=64, width=128, hidden=4))]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3", "bf16x3f"])
@@ -50,8 +50,10 @@ def test_loss_and_gradients(prec, name, over):
     (257^2 and 101^2 nodes leave a partial last 32-node tile)."""
     say("loss_grad", prec, name, over)
     prob = problem(name, **over)
-    if prec.startswith("bf16") and not (prob.width in (32, 64) and prob.hidden in (3, 4)):
-        pytest.skip("bf16 network paths cover widths 32/64 with 3-4 hidden layers")
+    widths = (32, 64) if prec == "bf16x3" else (32, 64, 128)
+    if prec.startswith("bf16") and not (prob.width in widths and prob.hidden in (3, 4)):
+        pytest.skip("bf16 network paths: widths 32/64 (bf16 and the mixed form also 128), "
+                    "3-4 hidden layers")
     sc = scenario_for(prob, prec)
     orc = oracle_for(prob)
     loss, g, gl = sc.loss_grad(with_logperm=True)
