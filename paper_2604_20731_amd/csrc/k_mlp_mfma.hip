@@ -342,18 +342,20 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&h[ks * T::S]);
     sink(l - 1, bop);
-    f32x4_t acc[NMB];
+    // one 16-row output block at a time: its activations replace h[4mb..4mb+3]
+    // (the operands of this layer are already in bop), so only one
+    // accumulator tile is live
 #pragma unroll
-    for (int mb = 0; mb < NMB; ++mb)
+    for (int mb = 0; mb < NMB; ++mb) {
+      f32x4_t acc;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[mb][i] = bl[cfeat(mb * 4 + i, q)];
-#pragma unroll
-    for (int mb = 0; mb < NMB; ++mb)
+      for (int i = 0; i < 4; ++i) acc[i] = bl[cfeat(mb * 4 + i, q)];
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
-        acc[mb] = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc[mb]);
+        acc = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc);
 #pragma unroll
-    for (int t = 0; t < NR; ++t) h[t] = tanh_of_scaled(acc[t >> 2][t & 3]);
+      for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(acc[i]);
+    }
   }
 }
 
