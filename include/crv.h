@@ -84,9 +84,9 @@ typedef struct {
   int dim;              /* 2 or 3 */
   int n_elem;           /* Ne per axis, 4 <= Ne <= 1024 (3D: <= 256) */
   int degree;           /* B-spline degree r: 1, 2 or 3 */
-  int width;            /* hidden width: 16, 32, 64 or 128 (bf16 / bf16x3
-                           network paths: 32 or 64, bf16 also 128; 3 or 4
-                           hidden layers) */
+  int width;            /* hidden width: 16, 32, 64 or 128 (bf16 network
+                           paths: 32 or 64 with 3 or 4 hidden layers, 4 in
+                           3D; plain bf16 and the mixed form also 128) */
   int hidden;           /* number of tanh hidden layers, 1..8 */
   int precision;        /* crv_precision */
   double mu_w, mu_g;    /* brine and gas viscosities */
@@ -200,11 +200,15 @@ crv_status crv_saturation_substeps(crv_ctx* ctx, double tau, int n);
  * since the last crv_profile_enable(ctx, 1). */
 typedef enum {
   CRV_K_MLP_FWD = 0,   /* network forward (u at the nodes) */
-  CRV_K_MLP_BWD,       /* network backward (recompute + backprop + partials) */
+  CRV_K_MLP_BWD,       /* network backward (recompute + backprop + partials;
+                          on the matrix cores also the adjoint field and the
+                          loss partials) */
   CRV_K_RESIDUAL,      /* collocation residual */
-  CRV_K_GRAM_DST,      /* DST-I products of the Gram solve (2 per solve) */
+  CRV_K_GRAM_DST,      /* DST-I products of the Gram solve (2 events per
+                          solve; in 3D each spans the z and y products) */
   CRV_K_GRAM_LINES,    /* shifted tridiagonal line solves */
-  CRV_K_ADJOINT,       /* adjoint stencil + loss partials */
+  CRV_K_ADJOINT,       /* adjoint stencil + loss partials (per-node network
+                          path only) */
   CRV_K_LOSS,          /* loss reduction */
   CRV_K_GRAD_REDUCE,   /* gradient partial reduction passes */
   CRV_K_ADAM,          /* fused Adam */
