@@ -489,9 +489,20 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
     // the weight fragments are re-read from cache each step: an opaque copy
     // of the pointer keeps the compiler from hoisting every fragment of every
-    // layer into registers for the whole loop (which only spills them)
+    // layer into registers for the whole loop (which only spills them).  Up
+    // to width 64 the copy stays a global-memory pointer, so the loads remain
+    // global loads (through a generic pointer they are flat loads, which also
+    // hold up every wait for LDS results); at width 128 the generic form
+    // needs fewer registers and spills less
     const typename T::felem* fr = frag;
-    asm volatile("" : "+s"(fr));
+    if constexpr (W <= 64) {
+      using gfelem = __attribute__((address_space(1))) const typename T::felem;
+      gfelem* frg = (gfelem*)frag;
+      asm volatile("" : "+s"(frg));
+      fr = (const typename T::felem*)frg;
+    } else {
+      asm volatile("" : "+s"(fr));
+    }
     const int64_t p = step * NB + col;
     float z[DIM];
     bool interior = false;
