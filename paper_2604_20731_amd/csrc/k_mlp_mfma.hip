@@ -316,7 +316,7 @@ struct NoSink {
 // Forward of one 16-node tile held by this wave.  The operands that hidden
 // layer l (0-based, l < L-1) feeds into the next product go to sink(l, bop)
 // as soon as they are built; on return h holds the last hidden layer.
-template <int W, int L, int MODE, int DIM, typename Sink>
+template <int W, int L, int MODE, int DIM, bool PIPE, typename Sink>
 __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::felem* __restrict__ frag,
                                     const float* z, int q, int lane, float (&h)[W / 4],
                                     const Sink& sink) {
@@ -343,18 +343,41 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
     for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&h[ks * T::S]);
     sink(l - 1, bop);
     // one 16-row output block at a time: its activations replace h[4mb..4mb+3]
-    // (the operands of this layer are already in bop), so only one
-    // accumulator tile is live
-#pragma unroll
-    for (int mb = 0; mb < NMB; ++mb) {
+    // (the operands of this layer are already in bop).  With PIPE the
+    // products of block mb+1 are issued before the tanh of block mb, so the
+    // activation work covers the matrix-core latency (two accumulator tiles
+    // live); without it one tile is live, for register-bound callers
+    auto products = [&](int mb) {
       f32x4_t acc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i] = bl[cfeat(mb * 4 + i, q)];
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
         acc = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc);
+      return acc;
+    };
+    if constexpr (PIPE) {
+      f32x4_t cur = products(0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(acc[i]);
+      for (int mb = 0; mb < NMB; ++mb) {
+        f32x4_t nxt = cur;
+        if (mb + 1 < NMB) nxt = products(mb + 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(cur[i]);
+        cur = nxt;
+      }
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < NMB; ++mb) {
+        f32x4_t acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = bl[cfeat(mb * 4 + i, q)];
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+          acc = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(acc[i]);
+      }
     }
   }
 }
@@ -380,7 +403,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
   else
     for (int c = 0; c < DIM; ++c) z[c] = 0.f;
   float h[NR];
-  forward_tile<W, L, MODE, DIM>(sp, frag, z, q, lane, h, NoSink());
+  forward_tile<W, L, MODE, DIM, true>(sp, frag, z, q, lane, h, NoSink());
   const float* wo = sp + SM::WO;
   float s = 0.f;
 #pragma unroll
@@ -511,7 +534,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     float d[NR];
-    forward_tile<W, L, MODE, DIM>(sp, fr, z, q, lane, d, sink);
+    forward_tile<W, L, MODE, DIM, (W <= 64)>(sp, fr, z, q, lane, d, sink);
     int64_t iq = -1;
     const float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
     if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
