@@ -137,7 +137,11 @@ struct MM<NET_X3> {
     }
     return o;
   }
+  // the subtraction is kept apart from whatever produced w (no fused
+  // multiply-add with a caller's product), so the Adam kernel's in-place
+  // fragment update and a repack from theta store the same two halves
   __device__ static inline void put(felem* p, float w) {
+#pragma clang fp contract(off)
     const __bf16 h = (__bf16)w;
     p[0] = h;
     p[64 * S] = (__bf16)(w - float(h));
