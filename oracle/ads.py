@@ -123,9 +123,15 @@ def project_nodal(space: Space, u_nodal: np.ndarray) -> np.ndarray:
 
 
 def saturation_rhs(space: Space, s_coefs, p_coefs, perm, poro, q_inj, q_prod,
-                   tau, mu_w, mu_g, n_exp):
-    """b_k = int [S B_k + tau phi^-1 (-lambda_g(S) K grad p . grad B_k + q_g B_k)]
-    (eq. 10, first use, with gravity zero)."""
+                   tau, mu_w, mu_g, n_exp, rho_g=0.0, gravity=0.0):
+    """b_k = int [S B_k + tau phi^-1 (-lambda_g(S) K (grad p - rho_g g) . grad B_k
+    + q_g B_k)] (eq. 9-10: the weak form of the explicit gas update, boundary
+    term dropped as in eq. 9).
+
+    Reading: g = -gravity e_v with e_v the last coordinate (y in 2D, z in
+    3D), so only the vertical derivative changes: d_v p -> d_v p + rho_g
+    gravity.  (Eq. 10 writes the term as rho_g g v_y, i.e. with g the signed
+    vertical component; with g = -gravity the two agree.)"""
     dim = space.dim
     s = space.at_gauss(s_coefs)
     kg = space.nodal_at_gauss(perm)
@@ -140,14 +146,16 @@ def saturation_rhs(space: Space, s_coefs, p_coefs, perm, poro, q_inj, q_prod,
     b = space.integrate(s + tau * qg / phig)
     for a in range(dim):
         dp = space.at_gauss(p_coefs, deriv_axis=a)
+        if a == dim - 1:
+            dp = dp + rho_g * gravity
         flux = -tau / phig * lam_g * kg * dp
         b = b + space.integrate(flux, deriv_axis=a)
     return b
 
 
 def saturation_substep(space: Space, s_coefs, p_coefs, perm, poro, q_inj, q_prod,
-                       tau, mu_w, mu_g, n_exp):
+                       tau, mu_w, mu_g, n_exp, rho_g=0.0, gravity=0.0):
     """S^{n+1} = M^{-1} b (eq. 6 as the L2 projection of eq. 10-12)."""
     b = saturation_rhs(space, s_coefs, p_coefs, perm, poro, q_inj, q_prod,
-                       tau, mu_w, mu_g, n_exp)
+                       tau, mu_w, mu_g, n_exp, rho_g, gravity)
     return space.mass_solve(b)

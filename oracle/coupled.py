@@ -27,10 +27,11 @@ class Oracle:
     def __init__(self, dim, n_elem, degree, width, hidden, log_perm, porosity, wells,
                  theta0, s0_coefs=None, mu_w=1.0, mu_g=0.1, relperm_exp=2.0,
                  lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, adam_iters=100,
-                 substeps=10, well_radius=0.06):
+                 substeps=10, well_radius=0.06, gravity=0.0, rho_w=0.0, rho_g=0.0):
         self.dim, self.n_elem, self.r = dim, n_elem, degree
         self.dims = mlp.layer_dims(dim, width, hidden)
         self.mu_w, self.mu_g, self.n_exp = mu_w, mu_g, relperm_exp
+        self.gravity, self.rho_w, self.rho_g = gravity, rho_w, rho_g
         self.adam_iters, self.substeps = adam_iters, substeps
         self.perm = np.exp(np.asarray(log_perm, dtype=np.float64))
         self.poro = np.asarray(porosity, dtype=np.float64)
@@ -52,6 +53,11 @@ class Oracle:
         self.s_nodal = self.space.at_nodes(self.s)
         self.alpha = pressure.alpha_nodal(self.s_nodal, self.perm, self.mu_w,
                                           self.mu_g, self.n_exp)
+        # right-hand side of the pressure system: wells minus the gravity
+        # divergence (zero without gravity)
+        self.q_eff = self.q - pressure.gravity_divergence(
+            self.s_nodal, self.perm, self.mu_w, self.mu_g, self.n_exp, self.rho_w,
+            self.rho_g, self.gravity)
 
     def u_nodal(self, theta=None):
         th = self.theta if theta is None else theta
@@ -63,7 +69,7 @@ class Oracle:
         th = self.theta if theta is None else theta
         acts = mlp.forward(th, self.dims, self.z)
         u = self.mask * acts[-1].reshape(self.mask.shape)
-        res = pressure.residual(u, self.alpha, self.q)
+        res = pressure.residual(u, self.alpha, self.q_eff)
         q = pressure.gram_solve(res)
         lval = pressure.loss(res, q)
         gu = pressure.grad_u(q, self.alpha) * self.mask
@@ -71,12 +77,26 @@ class Oracle:
         return lval, g
 
     def loss_grad_logperm(self, theta=None):
-        """dLOSS/dlogK = dLOSS/dalpha * alpha (alpha is linear in K = e^logK)."""
+        """dLOSS/dlogK = dLOSS/dalpha * alpha (alpha is linear in K = e^logK),
+        plus, with gravity, the part through the right-hand side: RES holds
+        + h^d div_+(g F) with F linear in K, so the term is
+        -2 gravity h^(d-1) F_m (q~_(m-e) - q~_m), q~ = q extended by zero."""
         th = self.theta if theta is None else theta
         u = self.u_nodal(th)
-        res = pressure.residual(u, self.alpha, self.q)
+        res = pressure.residual(u, self.alpha, self.q_eff)
         q = pressure.gram_solve(res)
-        return pressure.grad_alpha(u, q) * self.alpha
+        g = pressure.grad_alpha(u, q) * self.alpha
+        if self.gravity != 0.0:
+            ne = self.n_elem
+            h = 1.0 / ne
+            f = pressure.buoyancy_flux(self.s_nodal, self.perm, self.mu_w, self.mu_g,
+                                       self.n_exp, self.rho_w, self.rho_g)
+            qt = np.zeros_like(u)
+            qt[tuple(slice(1, ne) for _ in range(self.dim))] = q
+            below = np.zeros_like(qt)
+            below[1:] = qt[:-1]          # q~ at m - e_v
+            g = g - 2.0 * self.gravity * h ** (self.dim - 1) * f * (below - qt)
+        return g
 
     def train(self, iters):
         for _ in range(iters):
@@ -96,7 +116,7 @@ class Oracle:
         for _ in range(self.substeps):
             self.s = ads.saturation_substep(self.space, self.s, p, self.perm, self.poro,
                                             self.q_inj, self.q_prod, tau, self.mu_w,
-                                            self.mu_g, self.n_exp)
+                                            self.mu_g, self.n_exp, self.rho_g, self.gravity)
         self.refresh()
         self.train(self.adam_iters)
 
@@ -104,7 +124,7 @@ class Oracle:
         return self.u_nodal(), self.s.copy(), self.space.at_nodes(self.s)
 
     def direct_pressure(self):
-        return pressure.direct_solve(self.alpha, self.q)
+        return pressure.direct_solve(self.alpha, self.q_eff)
 
 
 def cfl_dt(orc: Oracle, cfl: float = 0.5) -> float:

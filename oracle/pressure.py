@@ -12,8 +12,8 @@ Follows the CRVPINN section of the paper:
     LOSS = RES^T G^{-1} RES (eq. 27-28).
 
 Readings taken where the paper is silent or inconsistent:
-  * sign: -div(alpha grad p) = q with q the total injection (q > 0 injects),
-    gravity zero; a_h(u, v) = h^d sum over grid edges (p, p+e) of
+  * sign: -div(alpha grad p) = q with q the total injection (q > 0 injects);
+    with gravity q becomes q - div_+(g F) (gravity_divergence); a_h(u, v) = h^d sum over grid edges (p, p+e) of
     alpha_p nabla_e+ u(p) nabla_e+ v(p) (alpha taken at the edge's lower node);
   * tests delta_kl at interior nodes only, trial functions zero on the boundary;
   * G is built from the paper's own products, so it equals the integer
@@ -45,6 +45,32 @@ def alpha_nodal(s_nodal, perm, mu_w, mu_g, n):
     paper's linear S/mu is the case n = 1)."""
     krw, krg = relperm(s_nodal, n)
     return (krw / mu_w + krg / mu_g) * perm
+
+
+def buoyancy_flux(s_nodal, perm, mu_w, mu_g, n, rho_w, rho_g):
+    """F = K (lambda_w rho_w + lambda_g rho_g) at the nodes, lambda = kr / mu
+    at clamp(s, 0, 1): the density-weighted mobility that gravity multiplies
+    in the pressure equation (eq. 5)."""
+    krw, krg = relperm(s_nodal, n)
+    return perm * (krw / mu_w * rho_w + krg / mu_g * rho_g)
+
+
+def gravity_divergence(s_nodal, perm, mu_w, mu_g, n, rho_w, rho_g, gravity):
+    """div_+ (g K (lambda_w rho_w + lambda_g rho_g)) at the nodes: the gravity
+    part of the collocation right-hand side (the RHS_ij formula of the
+    CRVPINN section and of algorithm steps 2 and 6), forward difference
+    (eq. 22).
+
+    Reading: g = -gravity e_v with gravity >= 0 and e_v the last coordinate
+    (y in 2D, z in 3D; numpy axis 0), i.e. gravity points down; the vector
+    form (grad p - rho g) of eq. 1-2 is taken as the definition.  Nodes on
+    the top face, where the forward difference does not exist, get zero
+    (the residual uses interior nodes only)."""
+    f = buoyancy_flux(s_nodal, perm, mu_w, mu_g, n, rho_w, rho_g)
+    n_elem = f.shape[0] - 1
+    out = np.zeros_like(f)
+    out[:-1] = -gravity * (f[1:] - f[:-1]) * n_elem
+    return out
 
 
 def _diff_1d(n_elem: int):
