@@ -95,13 +95,20 @@ typedef struct {
   int adam_iters;       /* Adam iterations per coupled step (100) */
   int substeps;         /* saturation substeps per coupled step (10) */
   double well_radius;   /* well disc radius */
+  /* Gravity (eq. 5 and 9-10): g = -gravity e_v, e_v the last coordinate
+   * (y in 2D, z in 3D), gravity >= 0; rho_w, rho_g >= 0 the brine and gas
+   * densities.  The pressure right-hand side becomes
+   * q - div_+(g K (kr_w rho_w/mu_w + kr_g rho_g/mu_g)) (forward difference
+   * along e_v), the gas flux lambda_g K (grad p - rho_g g).  0 = off. */
+  double gravity, rho_w, rho_g;
 } crv_config;
 
 typedef struct crv_ctx crv_ctx;
 
 /* Defaults: 2D, Ne 32, r 2, width 32, 3 hidden layers, FP32, mu_w 1,
  * mu_g 0.1, n 2, Adam lr 1e-4 (the paper's value), beta (0.9, 0.999),
- * eps 1e-8, 100 iterations and 10 substeps per step, well radius 0.06. */
+ * eps 1e-8, 100 iterations and 10 substeps per step, well radius 0.06,
+ * no gravity. */
 crv_status crv_config_default(crv_config* cfg);
 
 /* Number of network parameters for cfg. */

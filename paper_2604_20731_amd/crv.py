@@ -42,6 +42,7 @@ class CrvConfig(C.Structure):
         ("mu_w", C.c_double), ("mu_g", C.c_double), ("relperm_exp", C.c_double),
         ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
         ("adam_iters", C.c_int), ("substeps", C.c_int), ("well_radius", C.c_double),
+        ("gravity", C.c_double), ("rho_w", C.c_double), ("rho_g", C.c_double),
     ]
 
 

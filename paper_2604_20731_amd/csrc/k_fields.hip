@@ -17,9 +17,10 @@ __global__ __launch_bounds__(256) void k_refresh2(Geom g, const Real* __restrict
                                                   const int* __restrict__ kf,
                                                   const Real* __restrict__ kv,
                                                   const Real* __restrict__ perm, Real inv_mu_w,
-                                                  Real inv_mu_g, Real nexp,
+                                                  Real inv_mu_g, Real nexp, Real rw_mu, Real rg_mu,
                                                   Real* __restrict__ s_nodal,
-                                                  Real* __restrict__ alpha) {
+                                                  Real* __restrict__ alpha,
+                                                  Real* __restrict__ flux) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int n = g.n;
   if (p >= int64_t(n) * n) return;
@@ -37,6 +38,7 @@ __global__ __launch_bounds__(256) void k_refresh2(Geom g, const Real* __restrict
   const Real krw = powi_or_pow(Real(1) - sc, nexp), krg = powi_or_pow(sc, nexp);
   s_nodal[p] = s;
   alpha[p] = (krw * inv_mu_w + krg * inv_mu_g) * perm[p];
+  if (flux) flux[p] = (krw * rw_mu + krg * rg_mu) * perm[p];
 }
 
 template <typename Real, int R>
@@ -44,9 +46,10 @@ __global__ __launch_bounds__(256) void k_refresh3(Geom g, const Real* __restrict
                                                   const int* __restrict__ kf,
                                                   const Real* __restrict__ kv,
                                                   const Real* __restrict__ perm, Real inv_mu_w,
-                                                  Real inv_mu_g, Real nexp,
+                                                  Real inv_mu_g, Real nexp, Real rw_mu, Real rg_mu,
                                                   Real* __restrict__ s_nodal,
-                                                  Real* __restrict__ alpha) {
+                                                  Real* __restrict__ alpha,
+                                                  Real* __restrict__ flux) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int n = g.n, nb = g.nb;
   if (p >= int64_t(n) * n * n) return;
@@ -70,29 +73,60 @@ __global__ __launch_bounds__(256) void k_refresh3(Geom g, const Real* __restrict
   const Real krw = powi_or_pow(Real(1) - sc, nexp), krg = powi_or_pow(sc, nexp);
   s_nodal[p] = s;
   alpha[p] = (krw * inv_mu_w + krg * inv_mu_g) * perm[p];
+  if (flux) flux[p] = (krw * rw_mu + krg * rg_mu) * perm[p];
 }
 
 template <typename Real>
 void launch_refresh(const Geom& g, const Real* s_coefs, const int* kf, const Real* kv,
-                    const Real* perm, double mu_w, double mu_g, double nexp, Real* s_nodal,
-                    Real* alpha, hipStream_t st) {
+                    const Real* perm, double mu_w, double mu_g, double nexp, double rho_w,
+                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st) {
   const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  const Real rw = Real(rho_w / mu_w), rg = Real(rho_g / mu_g);
   if (g.dim == 3) {
     dim3 grid3(cdiv(ipow(g.n, 3), 256));
     switch (g.r) {
-      case 1: k_refresh3<Real, 1><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
-      case 2: k_refresh3<Real, 2><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
-      default: k_refresh3<Real, 3><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+      case 1: k_refresh3<Real, 1><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
+      case 2: k_refresh3<Real, 2><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
+      default: k_refresh3<Real, 3><<<grid3, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
     }
     return;
   }
   const int64_t tot = int64_t(g.n) * g.n;
   dim3 grid(cdiv(tot, 256));
   switch (g.r) {
-    case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
-    case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
-    default: k_refresh2<Real, 3><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, s_nodal, alpha); break;
+    case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
+    case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
+    default: k_refresh2<Real, 3><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
   }
+}
+
+// Pressure right-hand side with gravity: h^d (q - div_+(g F)) with g = -gravity
+// e_v (e_v: y in 2D, z in 3D) and F the buoyancy flux from the refresh, i.e.
+// hq_p = h^d q_p + gravity h^(d-1) (F_{p+e_v} - F_p) (the RHS_ij formula of
+// the CRVPINN section; forward difference, eq. 22).  Top-face nodes, which no
+// interior residual reads, keep h^d q.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_gravity_rhs(int64_t total, int64_t sv, int64_t top,
+                                                     const Real* __restrict__ flux,
+                                                     const Real* __restrict__ qi,
+                                                     const Real* __restrict__ qp, Real hd,
+                                                     Real gh, Real* __restrict__ hq) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  Real v = hd * (qi[p] + qp[p]);
+  if (p < top) v += gh * (flux[p + sv] - flux[p]);
+  hq[p] = v;
+}
+
+template <typename Real>
+void launch_gravity_rhs(const Geom& g, const Real* flux, const Real* qi, const Real* qp,
+                        double gravity, Real* hq, hipStream_t st) {
+  const int64_t n = g.n, total = ipow(g.n, g.dim);
+  const int64_t sv = g.dim == 3 ? n * n : n;  // stride of the vertical axis
+  const double h = 1.0 / g.ne;
+  k_gravity_rhs<Real><<<cdiv(total, 256), 256, 0, st>>>(total, sv, total - sv, flux, qi, qp,
+                                                         Real(std::pow(h, g.dim)),
+                                                         Real(gravity * std::pow(h, g.dim - 1)), hq);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,11 +244,15 @@ void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int c
 }
 
 // dLOSS/dalpha_p = 2 sum_dir (u_{p+e}-u_p)(q_{p+e}-q_p) (2D, q zero-extended);
-// dLOSS/dlogK = dLOSS/dalpha * alpha.
+// dLOSS/dlogK = dLOSS/dalpha * alpha.  With gravity the right-hand side holds
+// h^d div_+(g F) with F linear in K, which adds
+// -2 gravity h^(d-1) F_p (q_{p-e_v} - q_p) (gf = 2 gravity h^(d-1); flux null
+// without gravity).
 template <typename Real>
 __global__ __launch_bounds__(256) void k_grad_logperm2(Geom g, const Real* __restrict__ u,
                                                        const Real* __restrict__ q,
                                                        const Real* __restrict__ alpha,
+                                                       const Real* __restrict__ flux, Real gf,
                                                        Real* __restrict__ out) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -225,13 +263,16 @@ __global__ __launch_bounds__(256) void k_grad_logperm2(Geom g, const Real* __res
   Real s = 0;
   if (i + 1 < n) s += (u[p + 1] - u[p]) * (q_ext(q, g, i + 1, j, 1) - qp);
   if (j + 1 < n) s += (u[p + n] - u[p]) * (q_ext(q, g, i, j + 1, 1) - qp);
-  out[p] = Real(2) * s * alpha[p];
+  Real r = Real(2) * s * alpha[p];
+  if (flux) r -= gf * flux[p] * (q_ext(q, g, i, j - 1, 1) - qp);
+  out[p] = r;
 }
 
 template <typename Real>
 __global__ __launch_bounds__(256) void k_grad_logperm3(Geom g, const Real* __restrict__ u,
                                                        const Real* __restrict__ q,
                                                        const Real* __restrict__ alpha, Real h,
+                                                       const Real* __restrict__ flux, Real gf,
                                                        Real* __restrict__ out) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -244,19 +285,22 @@ __global__ __launch_bounds__(256) void k_grad_logperm3(Geom g, const Real* __res
   if (i + 1 < n) s += (u[p + 1] - u[p]) * (q_ext(q, g, i + 1, j, k) - qp);
   if (j + 1 < n) s += (u[p + n] - u[p]) * (q_ext(q, g, i, j + 1, k) - qp);
   if (k + 1 < n) s += (u[p + n2] - u[p]) * (q_ext(q, g, i, j, k + 1) - qp);
-  out[p] = Real(2) * h * s * alpha[p];
+  Real r = Real(2) * h * s * alpha[p];
+  if (flux) r -= gf * flux[p] * (q_ext(q, g, i, j, k - 1) - qp);
+  out[p] = r;
 }
 
 template <typename Real>
 void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real* alpha,
-                         Real* out, hipStream_t st) {
+                         const Real* flux, double gravity, Real* out, hipStream_t st) {
+  const Real gf = Real(2.0 * gravity * std::pow(1.0 / g.ne, g.dim - 1));
   if (g.dim == 3) {
     dim3 grid3(cdiv(g.n, 64), cdiv(g.n, 4), g.n);
-    k_grad_logperm3<Real><<<grid3, 256, 0, st>>>(g, u, q, alpha, Real(1.0 / g.ne), out);
+    k_grad_logperm3<Real><<<grid3, 256, 0, st>>>(g, u, q, alpha, Real(1.0 / g.ne), flux, gf, out);
     return;
   }
   dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
-  k_grad_logperm2<Real><<<grid, 256, 0, st>>>(g, u, q, alpha, out);
+  k_grad_logperm2<Real><<<grid, 256, 0, st>>>(g, u, q, alpha, flux, gf, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,7 +394,7 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
     const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
     const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
     const Real* __restrict__ gxi, const Real* __restrict__ gw, const double* __restrict__ tau_dev,
-    Real inv_mu_w, Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+    Real inv_mu_w, Real inv_mu_g, Real nexp, Real gshift, Real* __restrict__ b) {
   const Real tau = Real(*tau_dev);
   constexpr int NG = R + 1;          // Gauss points per element and axis
   constexpr int TE = TC + R;         // elements per tile and axis
@@ -423,7 +467,7 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
       f0 = w * (s + tphi * qg);
       const Real c = -w * tphi * lam_g * kk;
       fx = c * px;
-      fy = c * py;
+      fy = c * (py + gshift);  // grad p - rho_g g, g = -gravity e_y
     }
     sF0[t] = f0;
     sFx[t] = fx;
@@ -474,7 +518,7 @@ __global__ __launch_bounds__(256) void k_ads_assemble3(
     const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
     const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
     const Real* __restrict__ gxi, const Real* __restrict__ gw, const double* __restrict__ tau_dev,
-    Real inv_mu_w, Real inv_mu_g, Real nexp, Real* __restrict__ b) {
+    Real inv_mu_w, Real inv_mu_g, Real nexp, Real gshift, Real* __restrict__ b) {
   constexpr int NG = R + 1;
   constexpr int TE = TC + R;
   constexpr int TCO = TC + 2 * R;
@@ -581,7 +625,7 @@ __global__ __launch_bounds__(256) void k_ads_assemble3(
           const Real c = -w * tphi * lam_g * kk;
           fx = c * px;
           fy = c * py;
-          fz = c * pz;
+          fz = c * (pz + gshift);  // grad p - rho_g g, g = -gravity e_z
         }
         sF0[t] = f0;
         sFx[t] = fx;
@@ -666,44 +710,45 @@ template <typename Real, int R>
 void launch_ads3(const Geom& g, const Real* s, const Real* p, const Real* perm,
                  const Real* poro, const Real* qi, const Real* qp, const Real* gb,
                  const Real* gdb, const Real* gxi, const Real* gw, const double* tau, Real iw,
-                 Real ig, Real ne, Real* b, hipStream_t st) {
+                 Real ig, Real ne, Real gs, Real* b, hipStream_t st) {
   constexpr bool big = sizeof(Real) == 8;
   constexpr int TC = big ? (R == 3 ? 2 : 4) : (R == 3 ? 4 : 8);
   constexpr int ZC = 16;
   dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC), cdiv(g.nb, ZC));
   k_ads_assemble3<Real, R, TC, ZC><<<grid, 256, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb,
-                                                         gxi, gw, tau, iw, ig, ne, b);
+                                                         gxi, gw, tau, iw, ig, ne, gs, b);
 }
 
 template <typename Real>
 void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
                          const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
-                         double mu_w, double mu_g, double nexp, Real* b, hipStream_t st) {
+                         double mu_w, double mu_g, double nexp, double gshift, Real* b,
+                         hipStream_t st) {
   const double* t = tau;
-  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
+  const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp), gs = Real(gshift);
   if (g.dim == 3) {
     if (g.r == 1)
-      launch_ads3<Real, 1>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+      launch_ads3<Real, 1>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, st);
     else if (g.r == 2)
-      launch_ads3<Real, 2>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+      launch_ads3<Real, 2>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, st);
     else
-      launch_ads3<Real, 3>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b, st);
+      launch_ads3<Real, 3>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, st);
     return;
   }
   constexpr bool big = sizeof(Real) == 8;
   if (g.r == 1) {
     constexpr int TC = 16;
     dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 1, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+    k_ads_assemble2<Real, 1, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
   } else if (g.r == 2) {
     constexpr int TC = big ? 8 : 16;
     dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 2, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+    k_ads_assemble2<Real, 2, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
   } else {
     constexpr int TC = 8;
     dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 3, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, b);
+    k_ads_assemble2<Real, 3, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
   }
 }
 
@@ -824,17 +869,20 @@ void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st) {
 
 #define CRV_INST(R)                                                                              \
   template void launch_refresh<R>(const Geom&, const R*, const int*, const R*, const R*, double, \
-                                  double, double, R*, R*, hipStream_t);                          \
+                                  double, double, double, double, R*, R*, R*, hipStream_t);      \
+  template void launch_gravity_rhs<R>(const Geom&, const R*, const R*, const R*, double, R*,     \
+                                      hipStream_t);                                              \
   template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t);  \
   template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t); \
   template void launch_loss_finalize<R>(const R*, int, double*, int, const long long*, int,      \
                                         hipStream_t);                                            \
-  template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t); \
+  template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, const R*, double, \
+                                       R*, hipStream_t);                                         \
   template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t);             \
   template void launch_ads_assemble<R>(const Geom&, const R*, const R*, const R*, const R*,      \
                                        const R*, const R*, const R*, const R*, const R*,         \
-                                       const R*, const double*, double, double, double, R*,      \
-                                       hipStream_t);                                             \
+                                       const R*, const double*, double, double, double, double,  \
+                                       R*, hipStream_t);                                         \
   template void launch_factor_band<R>(const double*, int, int, double*, R*, R*, int*, hipStream_t); \
   template void launch_factor_shifted<R>(const double*, int, int, int, double, R*, R*, hipStream_t); \
   template void launch_fill<R>(R*, size_t, R, hipStream_t);                                      \

@@ -6,11 +6,17 @@ namespace crv {
 
 // ---- fields (k_fields.hip) ------------------------------------------------
 // a1: saturation at the nodes from the spline coefficients (knot values) and
-// alpha = K (kr_w/mu_w + kr_g/mu_g) at clamp(S,0,1).
+// alpha = K (kr_w/mu_w + kr_g/mu_g) at clamp(S,0,1); flux (nullable) receives
+// the buoyancy flux F = K (kr_w rho_w/mu_w + kr_g rho_g/mu_g).
 template <typename Real>
 void launch_refresh(const Geom& g, const Real* s_coefs, const int* knot_first, const Real* knot_val,
-                    const Real* perm, double mu_w, double mu_g, double nexp, Real* s_nodal,
-                    Real* alpha, hipStream_t st);
+                    const Real* perm, double mu_w, double mu_g, double nexp, double rho_w,
+                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st);
+// pressure right-hand side with gravity (g = -gravity e_v, e_v = y in 2D, z in
+// 3D): hq = h^d (qi + qp) + gravity h^(d-1) (F_{p+e_v} - F_p)
+template <typename Real>
+void launch_gravity_rhs(const Geom& g, const Real* flux, const Real* qi, const Real* qp,
+                        double gravity, Real* hq, hipStream_t st);
 
 // a3: RES on the interior nodes (padded layout, pitch mp).
 template <typename Real>
@@ -31,22 +37,25 @@ void launch_loss_finalize(const Real* partials, int np, double* loss_hist, int c
 // ++*t (one thread)
 void launch_bump(long long* t, hipStream_t st);
 
-// a3 differentiation form: dLOSS/dlogK = 2 sum_dir grad+ u . grad+ q h^(d-2) * alpha.
+// a3 differentiation form: dLOSS/dlogK = 2 sum_dir grad+ u . grad+ q h^(d-2) * alpha,
+// with gravity (flux non-null) - 2 gravity h^(d-1) F_p (q_{p-e_v} - q_p).
 template <typename Real>
 void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real* alpha,
-                         Real* out, hipStream_t st);
+                         const Real* flux, double gravity, Real* out, hipStream_t st);
 
 // a8: b_kl = int I_h(u) B_kl (Q1 nodal interpolant, exact Gauss).
 template <typename Real>
 void launch_project(const Geom& g, const Real* u, const Real* proj_val, Real* b, hipStream_t st);
 
-// a10: b_kl = int [S B_kl + tau/phi (-lambda_g K grad p . grad B_kl + q_g B_kl)];
+// a10: b_kl = int [S B_kl + tau/phi (-lambda_g K (grad p - rho_g g) . grad B_kl + q_g B_kl)];
+// gshift = rho_g gravity is added to the vertical derivative of p (g = -gravity e_v);
 // tau is read from device memory so a captured step serves any step length.
 template <typename Real>
 void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real* perm,
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
                          const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
-                         double mu_w, double mu_g, double nexp, Real* b, hipStream_t st);
+                         double mu_w, double mu_g, double nexp, double gshift, Real* b,
+                         hipStream_t st);
 
 // K7f: float64 factorisations on the device.
 // Banded LDL^T of the 1D mass matrix (band (nb, r+1)) -> lt (nb*r), inv_d (nb).

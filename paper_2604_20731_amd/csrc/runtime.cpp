@@ -72,6 +72,7 @@ template <typename Real>
 struct Buffers {
   // nodal (N+1)^d
   Real *perm, *poro, *qi, *qp, *hq, *s_nodal, *alpha, *u, *gu, *tmp_nodal;
+  Real* gflux;     // buoyancy flux K (kr_w rho_w/mu_w + kr_g rho_g/mu_g) (gravity only)
   // coefficients nb^d
   Real *s, *p, *bvec;
   // interior, padded to mp per axis
@@ -126,6 +127,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.u = cv.take<Real>(nn);
   b.gu = cv.take<Real>(nn);
   b.tmp_nodal = cv.take<Real>(nn);
+  b.gflux = cv.take<Real>(c.gravity != 0.0 ? nn : 0);
   b.s = cv.take<Real>(nc);
   b.p = cv.take<Real>(nc);
   b.bvec = cv.take<Real>(nc);
@@ -194,6 +196,9 @@ static crv_status validate_config(const crv_config* c) {
     return fail(CRV_EINVAL, "bad Adam parameters");
   if (c->adam_iters < 0 || c->substeps < 1) return fail(CRV_EINVAL, "bad iteration counts");
   if (!(c->well_radius > 0)) return fail(CRV_EINVAL, "well_radius must be > 0");
+  if (!(c->gravity >= 0 && std::isfinite(c->gravity)) || !(c->rho_w >= 0 && std::isfinite(c->rho_w)) ||
+      !(c->rho_g >= 0 && std::isfinite(c->rho_g)))
+    return fail(CRV_EINVAL, "gravity and densities must be finite and >= 0");
   return CRV_OK;
 }
 
@@ -413,10 +418,15 @@ struct Solver : SolverBase {
     return CRV_OK;
   }
 
+  // alpha (and with gravity the buoyancy flux and the pressure right-hand
+  // side, which then depend on S) from the current saturation
+  bool gravity() const { return cfg.gravity != 0.0; }
   void refresh() {
     tb(CRV_K_REFRESH);
     launch_refresh<Real>(g, b.s, b.knot_first, b.knot_val, b.perm, cfg.mu_w, cfg.mu_g,
-                         cfg.relperm_exp, b.s_nodal, b.alpha, st);
+                         cfg.relperm_exp, cfg.rho_w, cfg.rho_g, b.s_nodal, b.alpha,
+                         gravity() ? b.gflux : nullptr, st);
+    if (gravity()) launch_gravity_rhs<Real>(g, b.gflux, b.qi, b.qp, cfg.gravity, b.hq, st);
     te();
   }
 
@@ -622,7 +632,8 @@ struct Solver : SolverBase {
   void substep() {
     tb(CRV_K_ADS_ASSEMBLE);
     launch_ads_assemble<Real>(g, b.s, b.p, b.perm, b.poro, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
-                              b.tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, b.bvec, st);
+                              b.tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, cfg.rho_g * cfg.gravity,
+                              b.bvec, st);
     te();
     mass_solve(b.bvec, b.s);
   }
@@ -686,7 +697,9 @@ struct Solver : SolverBase {
     loss_pass(nullptr);
     grad_pass();
     launch_loss_finalize<Real>(b.loss_part, loss_count(), b.loss_scalar, 1, b.t_zero, 0, st);
-    if (dlogperm) launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, b.tmp_nodal, st);
+    if (dlogperm)
+      launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, gravity() ? b.gflux : nullptr, cfg.gravity,
+                                b.tmp_nodal, st);
     crv_status s = check_launch();
     if (s) return s;
     CRV_HIP(hipStreamSynchronize(st));
