@@ -154,12 +154,13 @@ def cpu_baseline(prob, seconds=20.0):
                       f"of the same workload, extrapolated to 100 iterations + 10 substeps"}
 
 
-def run_single(prob, precision, steps, warmup, pretrain, profile):
+def run_single(prob, precision, steps, warmup, pretrain, profile, **cfg):
     """Coupled steps/s of one scenario (captured steps replayed); optional
-    per-kernel breakdown from an eager, event-timed pass."""
+    per-kernel breakdown from an eager, event-timed pass.  cfg: config
+    overrides (gravity, densities, ...)."""
     import torch
     from paper_2604_20731_amd import crv
-    sc = crv.scenario_from_problem(prob, precision)
+    sc = crv.scenario_from_problem(prob, precision, **cfg)
     sc.pretrain_pressure(pretrain)
     p, _, _ = sc.fields()
     dt = cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)
@@ -277,6 +278,12 @@ def main():
         alt_batched = run_batched(list(range(args.batch)), args.alt_precision, args.steps,
                                   args.warmup, args.pretrain)
         alt = {"precision": args.alt_precision, "single": alt_single, "batched": alt_batched}
+    # the gravity variant of the same workload (pressure right-hand side and
+    # gas flux with buoyancy; gravity 2, densities 1.2 and 0.4)
+    log(f"{args.precision} single scenario with gravity, {args.steps} steps")
+    grav, _ = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain, False,
+                         gravity=2.0, rho_w=1.2, rho_g=0.4)
+    grav["config"] = {"gravity": 2.0, "rho_w": 1.2, "rho_g": 0.4}
     serving = None
     if args.serve > 0:
         from paper_2604_20731_amd.serve import Server
@@ -346,6 +353,7 @@ def main():
         "batched": batched,
         "vs_plain": batched["value"] / plain["value"],
         "alt_precision": alt,
+        "gravity_single": grav,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
