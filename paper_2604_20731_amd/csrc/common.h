@@ -62,13 +62,40 @@ __device__ inline T shfl(T v, int l) {
   return __shfl(v, l, kWave);
 }
 
-// Fixed-order block sum (blockDim.x threads, power of two <= 1024).
+// Fixed-order block sum over blockDim.x <= 1024 threads (a block size that is
+// not a power of two first folds its top part onto the first threads).
 template <typename T>
 __device__ inline T block_sum(T v, T* sbuf) {
   const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int p2 = 1 << (31 - __builtin_clz(nt));  // largest power of two <= nt
   sbuf[tid] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+  if (tid < nt - p2) sbuf[tid] += sbuf[tid + p2];  // fold the rest (none when nt = p2)
+  if (nt != p2) __syncthreads();
+  for (int s = p2 / 2; s > 0; s >>= 1) {
+    if (tid < s) sbuf[tid] += sbuf[tid + s];
+    __syncthreads();
+  }
+  T out = sbuf[0];
+  __syncthreads();
+  return out;
+}
+
+// The same sum for a block of NT threads known at compile time (no fold code
+// for a power of two).
+template <int NT, typename T>
+__device__ inline T block_sum_n(T v, T* sbuf) {
+  constexpr int p2 = NT >= 512 ? 512 : NT >= 256 ? 256 : NT >= 128 ? 128 : 64;
+  static_assert(NT <= 1023 && NT >= 64, "64 to 1023 threads");
+  const int tid = threadIdx.x;
+  sbuf[tid] = v;
+  __syncthreads();
+  if constexpr (NT != p2) {
+    if (tid < NT - p2) sbuf[tid] += sbuf[tid + p2];
+    __syncthreads();
+  }
+  for (int s = p2 / 2; s > 0; s >>= 1) {
     if (tid < s) sbuf[tid] += sbuf[tid + s];
     __syncthreads();
   }

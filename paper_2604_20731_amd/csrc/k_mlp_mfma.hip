@@ -476,7 +476,15 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   __shared__ float Zs[DIM][NB];
   __shared__ float Red[NTH];
 
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, n = lane & 15;
+  // When a wave's tiles do not start a row block at a fixed slot (OWN not a
+  // multiple of NMB), which slot holds the bias tile depends on the wave: the
+  // wave index is then made a scalar, so that choice is a scalar branch and
+  // never an execution mask around a matrix-core instruction (those run on
+  // every lane whatever the mask).  Otherwise it is known per slot at compile
+  // time and the plain index keeps the register allocation as it is.
+  const int tid = threadIdx.x;
+  const int w = (OWN % NMB != 0) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6);
+  const int lane = tid & 63, q = lane >> 4, n = lane & 15;
   const int col = w * 16 + n;  // this lane's node column in the block step
   const int q4 = tid & 3;
   SM::stage(th, sp, tid, NTH);
@@ -689,7 +697,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   __syncthreads();
   if (tid == 0) row[off_layer(L + 1, DIM, W) + W] = ((Red[0] + Red[1]) + Red[2]) + Red[3];
   __syncthreads();
-  const float lt = block_sum(lacc, Red);
+  const float lt = block_sum_n<NTH>(lacc, Red);
   if (tid == 0) loss_part[blockIdx.x] = lt;
 }
 
@@ -869,12 +877,14 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 
 // waves per backward block: 4 (64 nodes per block step); width 128 takes 8
 // so that its weight-gradient tiles spread over more waves
-constexpr int bwd_nw(int width) { return width >= 128 ? 8 : 4; }
+// (6 waves for the mixed form at width 64, two blocks per CU, measured 1.6x
+// slower than 4 waves at three blocks per CU)
+constexpr int bwd_nw(int width, int) { return width >= 128 ? 8 : 4; }
 
 // resident blocks per CU that the LDS of one block allows (160 KB per CU)
 template <int W, int L, int MODE, int DIM>
 static int bwd_lds_blocks() {
-  const size_t lds = BwdShape<W, L, MODE, DIM, bwd_nw(W)>::lds_bytes();
+  const size_t lds = BwdShape<W, L, MODE, DIM, bwd_nw(W, MODE)>::lds_bytes();
   return int(std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / lds)));
 }
 
@@ -882,7 +892,7 @@ static int bwd_lds_blocks() {
 // kernel reaches (registers) when a device is present
 template <int W, int L, int MODE>
 static int bwd_per_cu(int dim, bool query) {
-  constexpr int NW = bwd_nw(W);
+  constexpr int NW = bwd_nw(W, MODE);
   int lds_blocks = 1, occ = 0;
   hipError_t e = hipSuccess;
   if (dim == 3) {
@@ -907,7 +917,7 @@ static int bwd_per_cu(int dim, bool query) {
 int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count,
                         bool query) {
   int per_cu = 1;
-  const int nw = bwd_nw(width);
+  const int nw = bwd_nw(width, mode);
 #define CRV_BB(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) per_cu = bwd_per_cu<WW, LL, MM_>(g.dim, query);
   CRV_BWD_SHAPES(CRV_BB)
@@ -922,7 +932,7 @@ template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t ldp, const float* th, const void* frag, const float* q,
                      const float* alpha, const float* res, float* partials, float* loss_part,
                      int blocks, hipStream_t st) {
-  constexpr int NW = bwd_nw(W);
+  constexpr int NW = bwd_nw(W, MODE);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   if constexpr (L == 4) {
     if (g.dim == 3) {
