@@ -56,6 +56,11 @@ struct Carve {
 // modes included in 3D so that the line index is the row index of the array
 static int64_t gram_lines(const Geom& g) { return g.dim == 3 ? int64_t(g.m) * g.mp : g.m; }
 
+// pitch of the matrix-core backward's partial gradient rows: P rounded up to
+// 32 floats, so every row starts on a 128-byte line and the reduction's
+// 256-byte slices of a row touch two lines, not three
+static int64_t partial_pitch(int64_t P) { return (P + 31) / 32 * 32; }
+
 static Geom make_geom(const crv_config& c) {
   Geom g;
   g.dim = c.dim;
@@ -159,7 +164,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.frag = cv.take<char>(size_t(std::max<int64_t>(4, mlp_fragment_bytes(c.width, c.hidden))));
   b.bwd_rows = uses_mfma(c) ? mlp_bwd_mfma_blocks(g, c.width, c.hidden, net_mode(c), kMaxCUs, false)
                             : mlp_backward_rows(g, ms, int(sizeof(Real)));
-  b.partials = cv.take<Real>(size_t(b.bwd_rows) * ((P + 3) / 4 * 4));  // pitch ldp (MFMA) or P
+  b.partials = cv.take<Real>(size_t(b.bwd_rows) * partial_pitch(P));  // pitch ldp (MFMA) or P
   b.red_scratch = cv.take<Real>(size_t(2) * cdiv(b.bwd_rows, 64) * P);
   // loss partials: from the adjoint kernel, or one per fused network-backward block
   b.loss_np = std::max(adjoint_partials(g), b.bwd_rows);
@@ -519,7 +524,7 @@ struct Solver : SolverBase {
   // partial gradient rows of the network backward; returns the row count.
   // The matrix-core backward also leaves bwd_blocks loss partials.
   int adj_np = 0;
-  int64_t ldp() const { return (P + 3) / 4 * 4; }  // pitch of the matrix-core partial rows
+  int64_t ldp() const { return partial_pitch(P); }  // pitch of the matrix-core partial rows
   int loss_count() const { return mfma ? bwd_blocks : adj_np; }
   int backward() {
     tb(CRV_K_MLP_BWD);
