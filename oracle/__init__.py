@@ -18,6 +18,8 @@ Modules
             its gradients, direct solve of the discrete pressure system
   mlp       tanh multilayer perceptron forward/backward and Adam
   ads       L2 projection, Kronecker mass solve, explicit saturation substep
+  galerkin  IGA Galerkin pressure system and its sparse direct solve (the
+            paper's direct-solver path)
   wells     well discs -> nodal source arrays
   coupled   the IGA-ADS-CRVPINN algorithm (init, pretrain, step, fields)
 

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ads, mlp, pressure, wells as wells_mod
+from . import ads, galerkin, mlp, pressure, wells as wells_mod
 
 
 class Oracle:
@@ -119,6 +119,26 @@ class Oracle:
                                             self.mu_g, self.n_exp, self.rho_g, self.gravity)
         self.refresh()
         self.train(self.adam_iters)
+
+    # the paper's direct-solver algorithm (IGA-ADS with the Galerkin pressure
+    # system, eq. 15-20, in place of CRVPINN)
+    def galerkin_pressure(self):
+        """Pressure coefficients of the Galerkin system for the current saturation."""
+        return galerkin.pressure_solve(self.space, self.s, self.perm, self.q, self.mu_w,
+                                       self.mu_g, self.n_exp, self.gravity, self.rho_w,
+                                       self.rho_g)
+
+    def step_galerkin(self, dt, p_coefs):
+        """Substeps with the given pressure coefficients, refresh, and the
+        Galerkin pressure of the new saturation (returned): one pass of the
+        saturation update and pressure solve of that algorithm."""
+        tau = dt / self.substeps
+        for _ in range(self.substeps):
+            self.s = ads.saturation_substep(self.space, self.s, p_coefs, self.perm, self.poro,
+                                            self.q_inj, self.q_prod, tau, self.mu_w,
+                                            self.mu_g, self.n_exp, self.rho_g, self.gravity)
+        self.refresh()
+        return self.galerkin_pressure()
 
     def fields(self):
         return self.u_nodal(), self.s.copy(), self.space.at_nodes(self.s)
