@@ -188,6 +188,31 @@ def run_single(prob, precision, steps, warmup, pretrain, profile, **cfg):
     return {"value": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "dt": dt}, kernels
 
 
+def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
+    """The paper's direct-solver path on the same workload: the Galerkin
+    pressure system (matrix-free, preconditioned CG) timed per solve, and
+    coupled steps of that algorithm (substeps + pressure re-solve) per second."""
+    import torch
+    from paper_2604_20731_amd import crv
+    sc = crv.scenario_from_problem(prob, precision)
+    sc.pressure_galerkin(rtol=rtol)                      # allocates, warms up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, iters, rr = sc.pressure_galerkin(rtol=rtol)
+    t_solve = time.perf_counter() - t0
+    nb = prob.n_elem + prob.degree
+    sc.step_galerkin(dt, rtol=rtol)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sc.step_galerkin(dt, rtol=rtol)
+    t_step = (time.perf_counter() - t0) / steps
+    sc.close()
+    return {"precision": precision, "rtol": rtol, "cg_iters": iters, "rel_residual": rr,
+            "ms_per_solve": 1e3 * t_solve, "coupled_steps_per_s": 1.0 / t_step,
+            "note": f"{nb}^2 pressure coefficients; direct-solver algorithm (substeps + "
+                    "Galerkin pressure re-solve, no network)"}
+
+
 def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
     """Aggregate coupled steps/s of several 512^2 scenarios, each on its own
     stream, stepped together by crv_step_batch (their captured steps overlap
@@ -284,6 +309,8 @@ def main():
     grav, _ = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain, False,
                          gravity=2.0, rho_w=1.2, rho_g=0.4)
     grav["config"] = {"gravity": 2.0, "rho_w": 1.2, "rho_g": 0.4}
+    log("direct-solver path: Galerkin pressure solves and steps (fp32)")
+    galerkin = run_galerkin(prob, "fp32", args.steps, single["dt"])
     serving = None
     if args.serve > 0:
         from paper_2604_20731_amd.serve import Server
@@ -354,6 +381,7 @@ def main():
         "vs_plain": batched["value"] / plain["value"],
         "alt_precision": alt,
         "gravity_single": grav,
+        "galerkin_path": galerkin,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

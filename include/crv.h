@@ -143,6 +143,28 @@ crv_status crv_train_async(crv_ctx* ctx, int iters);
  * non-finite saturation was flagged. */
 crv_status crv_sync(crv_ctx* ctx);
 
+/* The paper's direct-solver pressure path (eq. 15-20; 2D only): the IGA
+ * Galerkin system S P = F on the B-spline space, S = int alpha grad B .
+ * grad B, F = int q B + int (g F_b) . grad B with alpha and the buoyancy
+ * flux F_b from the current saturation, P = 0 on the boundary coefficients.
+ * Solved matrix-free by conjugate gradients with the diagonal of S as
+ * preconditioner, from P = 0, until |F - S P| <= rtol |F| (tested every 25
+ * iterations) or max_iters.  The solution replaces the pressure
+ * coefficients the saturation substeps use.  p_coefs (nullable, host,
+ * nb^2) receives them; iters and rel_residual (nullable) the iteration count
+ * and |r|/|F|.  The first call allocates the solver's device arrays (owned
+ * by the context, about 5 (Ne (r+1))^2 + 6 nb^2 values); CRV_EINVAL in 3D or
+ * for max_iters < 0 or a negative rtol; blocks until done. */
+crv_status crv_pressure_galerkin(crv_ctx* ctx, int max_iters, double rtol, double* p_coefs,
+                                 int* iters, double* rel_residual);
+
+/* One pass of that algorithm: cfg.substeps saturation substeps of
+ * tau = dt/substeps with the current pressure coefficients, refresh, and the
+ * Galerkin pressure of the new saturation (crv_pressure_galerkin).  No
+ * network training.  Blocks until done. */
+crv_status crv_step_galerkin(crv_ctx* ctx, double dt, int max_iters, double rtol, int* iters,
+                             double* rel_residual);
+
 /* Algorithm steps 4-7, one coupled step of length dt > 0: project the
  * network pressure, cfg.substeps substeps of tau = dt/substeps, refresh
  * alpha from the new saturation, cfg.adam_iters Adam iterations.

@@ -27,6 +27,7 @@ SOURCES = [
     "k_solve.hip",
     "k_mlp.hip",
     "k_mlp_mfma.hip",
+    "k_galerkin.hip",
 ]
 
 ARCH = os.environ.get("CRV_OFFLOAD_ARCH", "gfx950")

@@ -27,8 +27,8 @@ EXPORTED = [
     "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
     "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
-    "crv_saturation_substeps", "crv_profile_enable", "crv_profile_read", "crv_destroy",
-    "crv_last_error",
+    "crv_saturation_substeps", "crv_pressure_galerkin", "crv_step_galerkin",
+    "crv_profile_enable", "crv_profile_read", "crv_destroy", "crv_last_error",
 ]
 
 KERNELS = ["mlp_fwd", "mlp_bwd", "residual", "gram_dst", "gram_lines", "adjoint", "loss",
@@ -85,6 +85,8 @@ def _load() -> C.CDLL:
         "crv_mass_solve": [vp, dp, dp],
         "crv_project_pressure": [vp, dp],
         "crv_saturation_substeps": [vp, C.c_double, C.c_int],
+        "crv_pressure_galerkin": [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int), dp],
+        "crv_step_galerkin": [vp, C.c_double, C.c_int, C.c_double, C.POINTER(C.c_int), dp],
         "crv_profile_enable": [vp, C.c_int],
         "crv_profile_read": [vp, C.c_int, dp, C.POINTER(C.c_int64)],
         "crv_destroy": [vp],
@@ -275,6 +277,24 @@ class Scenario:
 
     def saturation_substeps(self, tau: float, n: int):
         _check(LIB.crv_saturation_substeps(self.ctx, float(tau), int(n)))
+
+    def pressure_galerkin(self, max_iters: int = 20000, rtol: float = 1e-6):
+        """Galerkin pressure of the current saturation (2D): (coefficients
+        nb^2, CG iterations, |r|/|F|)."""
+        nb = self.cfg.n_elem + self.cfg.degree
+        out = np.zeros(nb ** self.cfg.dim)
+        it, rr = C.c_int(), C.c_double()
+        _check(LIB.crv_pressure_galerkin(self.ctx, int(max_iters), float(rtol), _dp(out),
+                                         C.byref(it), C.byref(rr)))
+        return out, it.value, rr.value
+
+    def step_galerkin(self, dt: float, max_iters: int = 20000, rtol: float = 1e-6):
+        """Substeps with the current pressure coefficients, then the Galerkin
+        pressure of the new saturation: (CG iterations, |r|/|F|)."""
+        it, rr = C.c_int(), C.c_double()
+        _check(LIB.crv_step_galerkin(self.ctx, float(dt), int(max_iters), float(rtol),
+                                     C.byref(it), C.byref(rr)))
+        return it.value, rr.value
 
     def profile_enable(self, on: bool = True):
         _check(LIB.crv_profile_enable(self.ctx, 1 if on else 0))

@@ -57,6 +57,29 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
                          double mu_w, double mu_g, double nexp, double gshift, Real* b,
                          hipStream_t st);
 
+// ---- IGA Galerkin pressure system, 2D (k_galerkin.hip; eq. 15-20) --------
+// Device arrays of one solve (owned by the context): Gauss-point arrays
+// (Ne (r+1))^2, coefficient arrays nb^2, 5 scalars and 2 x 256 partial sums.
+template <typename Real>
+struct GalerkinWork {
+  Real *c, *f0, *fy, *vx, *vy;    // w alpha, w q, -gravity w F_b, fluxes of the product
+  Real *f, *dg, *r, *z, *p, *ap;  // load, diagonal, CG vectors
+  double *sc, *part;
+};
+template <typename Real>
+struct GalerkinArgs {
+  const Real *s, *perm, *qi, *qp, *gb, *gdb, *gxi, *gw;
+  double mu_w, mu_g, nexp, rho_w, rho_g, gravity;
+  Real* x;  // the solution (pressure coefficients; boundary coefficients 0)
+  GalerkinWork<Real> ws;
+};
+// fields at the Gauss points, load, diagonal; x = 0 and the first CG vectors
+template <typename Real>
+void launch_galerkin_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st);
+// iters CG iterations (scalars stay on the device: sc[3] = r.r, sc[4] = F.F)
+template <typename Real>
+void launch_galerkin_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st);
+
 // K7f: float64 factorisations on the device.
 // Banded LDL^T of the 1D mass matrix (band (nb, r+1)) -> lt (nb*r), inv_d (nb).
 template <typename Real>

@@ -272,6 +272,10 @@ struct SolverBase {
   virtual crv_status project_host(double*) = 0;
   virtual crv_status substeps(double tau, int n) = 0;
   virtual crv_status sync() = 0;
+  virtual crv_status pressure_galerkin(int max_iters, double rtol, double* p, int* iters,
+                                       double* relres) = 0;
+  virtual crv_status step_galerkin(double dt, int max_iters, double rtol, int* iters,
+                                   double* relres) = 0;
 };
 
 template <typename Real>
@@ -579,7 +583,92 @@ struct Solver : SolverBase {
   hipGraphExec_t g_train = nullptr, g_step = nullptr;
   bool graphs_off = std::getenv("CRV_NO_GRAPH") != nullptr;
 
+  // ---- IGA Galerkin pressure (the paper's direct-solver path, 2D) ----
+  GalerkinWork<Real> gw{};
+  void* gw_mem = nullptr;
+  crv_status galerkin_alloc() {
+    if (gw_mem) return CRV_OK;
+    const size_t npts = size_t(ipow(int64_t(g.ne) * (g.r + 1), 2)), ncf = size_t(g.nb) * g.nb;
+    auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
+    const size_t bytes = 5 * up(npts * sizeof(Real)) + 6 * up(ncf * sizeof(Real)) +
+                         up(8 * sizeof(double)) + up(2 * 256 * sizeof(double));
+    CRV_HIP(hipMalloc(&gw_mem, bytes));
+    Carve cv(gw_mem);
+    gw.c = cv.take<Real>(npts);
+    gw.f0 = cv.take<Real>(npts);
+    gw.fy = cv.take<Real>(npts);
+    gw.vx = cv.take<Real>(npts);
+    gw.vy = cv.take<Real>(npts);
+    gw.f = cv.take<Real>(ncf);
+    gw.dg = cv.take<Real>(ncf);
+    gw.r = cv.take<Real>(ncf);
+    gw.z = cv.take<Real>(ncf);
+    gw.p = cv.take<Real>(ncf);
+    gw.ap = cv.take<Real>(ncf);
+    gw.sc = cv.take<double>(8);
+    gw.part = cv.take<double>(2 * 256);
+    return CRV_OK;
+  }
+  GalerkinArgs<Real> galerkin_args() {
+    return GalerkinArgs<Real>{b.s, b.perm, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
+                              cfg.mu_w, cfg.mu_g, cfg.relperm_exp, cfg.rho_w, cfg.rho_g,
+                              cfg.gravity, b.p, gw};
+  }
+  // S P = F for the current saturation into b.p by diagonally preconditioned
+  // CG from P = 0, until |r| <= rtol |F| (checked every 25 iterations) or
+  // max_iters
+  crv_status pressure_galerkin(int max_iters, double rtol, double* p_out, int* iters_out,
+                               double* relres_out) override {
+    if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
+    if (max_iters < 0 || !(rtol >= 0) || !std::isfinite(rtol)) return fail(CRV_EINVAL, "bad max_iters or rtol");
+    crv_status s = galerkin_alloc();
+    if (s) return s;
+    const GalerkinArgs<Real> a = galerkin_args();
+    launch_galerkin_setup<Real>(g, a, st);
+    if ((s = check_launch())) return s;
+    double sc[5] = {0, 0, 0, 0, 0};
+    auto read_sc = [&]() -> crv_status {
+      CRV_HIP(hipMemcpyAsync(sc, gw.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+      CRV_HIP(hipStreamSynchronize(st));
+      return CRV_OK;
+    };
+    if ((s = read_sc())) return s;
+    const double ff = sc[4];
+    double rel = ff > 0 ? 1.0 : 0.0;
+    int done = 0;
+    const int chunk = 25;
+    while (ff > 0 && done < max_iters && rel > rtol) {
+      const int k = std::min(chunk, max_iters - done);
+      launch_galerkin_iters<Real>(g, a, k, st);
+      if ((s = check_launch())) return s;
+      if ((s = read_sc())) return s;
+      done += k;
+      rel = std::sqrt(std::max(sc[3], 0.0) / ff);
+      if (!std::isfinite(rel)) return fail(CRV_ENUMERIC, "Galerkin solve produced a non-finite residual");
+    }
+    if (iters_out) *iters_out = done;
+    if (relres_out) *relres_out = rel;
+    if (p_out && (s = download(p_out, b.p, nc))) return s;
+    return CRV_OK;
+  }
+  // the direct-solver algorithm's pass: substeps with the current pressure
+  // coefficients, refresh, and the Galerkin pressure of the new saturation
+  crv_status step_galerkin(double dt, int max_iters, double rtol, int* iters,
+                           double* relres) override {
+    if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CRV_EINVAL, "dt must be > 0");
+    crv_status s = set_tau(dt / cfg.substeps);
+    if (s) return s;
+    for (int k = 0; k < cfg.substeps; ++k) substep();
+    launch_check_finite<Real>(b.s, nc, b.flag, st);
+    refresh();
+    if ((s = check_launch())) return s;
+    if ((s = sync_and_check())) return s;
+    return pressure_galerkin(max_iters, rtol, nullptr, iters, relres);
+  }
+
   ~Solver() override {
+    if (gw_mem) (void)hipFree(gw_mem);
     if (g_train) (void)hipGraphExecDestroy(g_train);
     if (g_step) (void)hipGraphExecDestroy(g_step);
     if (cap) (void)hipStreamDestroy(cap);
@@ -943,6 +1032,18 @@ crv_status crv_pretrain_pressure(crv_ctx* c, int iters, double* final_loss) {
     if (e != hipSuccess) return fail(CRV_EHIP, hipGetErrorString(e));
   }
   return CRV_OK;
+}
+
+crv_status crv_pressure_galerkin(crv_ctx* c, int max_iters, double rtol, double* p_coefs,
+                                 int* iters, double* rel_residual) {
+  CRV_CTX(c);
+  return sv.pressure_galerkin(max_iters, rtol, p_coefs, iters, rel_residual);
+}
+
+crv_status crv_step_galerkin(crv_ctx* c, double dt, int max_iters, double rtol, int* iters,
+                             double* rel_residual) {
+  CRV_CTX(c);
+  return sv.step_galerkin(dt, max_iters, rtol, iters, rel_residual);
 }
 
 crv_status crv_train_async(crv_ctx* c, int iters) {

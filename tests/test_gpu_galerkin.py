@@ -1,0 +1,75 @@
+"""The paper's direct-solver pressure path on the HIP side (matrix-free
+Galerkin operator, diagonally preconditioned CG; 2D) against the oracle's
+sparse direct solve of the same system (eq. 15-20; pinned on the CPU by an
+exactly reproduced polynomial pressure and the gravity load identity)."""
+import numpy as np
+import pytest
+
+from helpers import oracle_for, problem, rel, say, scenario_for
+from oracle import cfl_dt
+
+pytestmark = pytest.mark.gpu
+
+GRAV = dict(gravity=2.0, rho_w=1.2, rho_g=0.4)
+
+
+def _pair(prob, prec, grav, seed=3):
+    nb = prob.n_elem + prob.degree
+    s0 = np.random.default_rng(seed).uniform(0.0, 0.6, (nb, nb))
+    kw = GRAV if grav else {}
+    sc = scenario_for(prob, prec, **kw)
+    orc = oracle_for(prob, **kw)
+    sc.set_saturation(s0)
+    orc.s = s0.copy()
+    orc.refresh()
+    return sc, orc
+
+
+# CG to rtol 1e-12 (FP64) agrees with the direct solve to about the
+# preconditioned condition number times rtol; FP32 to rtol 1e-6 lands within
+# that condition number (~10-100 here) times 2^-24 and rtol (measured <= 8e-7)
+@pytest.mark.parametrize("prec,rtol,tol", [("fp64", 1e-12, 1e-8), ("fp32", 1e-6, 1e-5)])
+@pytest.mark.parametrize("ne,r", [(32, 2), (24, 3), (40, 1), (64, 2)])
+@pytest.mark.parametrize("grav", [False, True])
+def test_galerkin_pressure_matches_direct_solve(prec, rtol, tol, ne, r, grav):
+    say("galerkin", prec, ne, r, grav)
+    prob = problem("c1", n_elem=ne, degree=r)
+    sc, orc = _pair(prob, prec, grav)
+    p, iters, rr = sc.pressure_galerkin(max_iters=20000, rtol=rtol)
+    pref = orc.galerkin_pressure()
+    e = rel(p, pref.ravel())
+    say(f"  iters {iters} |r|/|F| {rr:.2e} rel err {e:.2e}")
+    assert rr <= rtol * 1.0001 or prec == "fp32"
+    assert e < tol
+
+
+# FP32: each substep passes through M^-1 (bound 1e-5 per substep, as for the
+# collocation path's substeps), ten per pass
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
+def test_direct_solver_algorithm_steps(prec, tol):
+    """Two passes of the direct-solver algorithm (substeps with the Galerkin
+    pressure, refresh, new Galerkin pressure) against the oracle."""
+    say("galerkin steps", prec)
+    prob = problem("c1")
+    sc, orc = _pair(prob, prec, grav=True)
+    rtol = 1e-12 if prec == "fp64" else 1e-6
+    sc.pressure_galerkin(rtol=rtol)
+    p = orc.galerkin_pressure()
+    dt = cfl_dt(orc)
+    for k in range(2):
+        sc.step_galerkin(dt, rtol=rtol)
+        p = orc.step_galerkin(dt, p)
+        _, s_gpu, _ = sc.fields()
+        e = rel(s_gpu, orc.s)
+        say(f"  step {k}: S {e:.2e}")
+        assert e < tol
+    p_gpu, _, _ = sc.pressure_galerkin(rtol=rtol)
+    assert rel(p_gpu, p.ravel()) < tol
+
+
+def test_galerkin_path_rejects_3d():
+    from paper_2604_20731_amd import crv
+    prob = problem("c5", n_elem=8, width=16, hidden=2, wells=np.array([[0.5, 0.5, 1.0]]))
+    sc = scenario_for(prob, "fp32")
+    with pytest.raises(crv.CrvError, match="2D"):
+        sc.pressure_galerkin()
