@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3f", choices=["fp32", "bf16", "bf16x3", "bf16x3f", "fp64"],
                     help="network arithmetic of the headline (batched) run")
     ap.add_argument("--batch", type=int, default=8, help="concurrent 512^2 scenarios")
+    ap.add_argument("--batch-sweep", default="32,64",
+                    help="further batch sizes timed for the aggregate rate ('' to skip)")
     ap.add_argument("--alt-precision", default="bf16x3",
                     help="second network arithmetic timed beside the headline ('' to skip)")
     ap.add_argument("--workload", default="b512")
@@ -303,6 +305,11 @@ def main():
         alt_batched = run_batched(list(range(args.batch)), args.alt_precision, args.steps,
                                   args.warmup, args.pretrain)
         alt = {"precision": args.alt_precision, "single": alt_single, "batched": alt_batched}
+    sweep = {}
+    for nb_ in [int(x) for x in args.batch_sweep.split(",") if x.strip()]:
+        log(f"{args.precision} batched: {nb_} scenarios x 3 steps")
+        r_ = run_batched(list(range(nb_)), args.precision, 3, 1, args.pretrain)
+        sweep[str(nb_)] = {"value": r_["value"], "ms_per_round": r_["ms_per_round"]}
     # the gravity variant of the same workload (pressure right-hand side and
     # gas flux with buoyancy; gravity 2, densities 1.2 and 0.4)
     log(f"{args.precision} single scenario with gravity, {args.steps} steps")
@@ -380,6 +387,7 @@ def main():
         "batched": batched,
         "vs_plain": batched["value"] / plain["value"],
         "alt_precision": alt,
+        "batch_sweep": sweep,
         "gravity_single": grav,
         "galerkin_path": galerkin,
         "serving": serving,
