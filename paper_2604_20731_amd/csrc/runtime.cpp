@@ -586,6 +586,7 @@ struct Solver : SolverBase {
   // ---- IGA Galerkin pressure (the paper's direct-solver path, 2D) ----
   GalerkinWork<Real> gw{};
   void* gw_mem = nullptr;
+  hipGraphExec_t g_gal = nullptr;  // one captured chunk of CG iterations
   crv_status galerkin_alloc() {
     if (gw_mem) return CRV_OK;
     const size_t npts = size_t(ipow(int64_t(g.ne) * (g.r + 1), 2)), ncf = size_t(g.nb) * g.nb;
@@ -637,9 +638,14 @@ struct Solver : SolverBase {
     double rel = ff > 0 ? 1.0 : 0.0;
     int done = 0;
     const int chunk = 25;
+    if (use_graphs() && !g_gal && ff > 0 && max_iters >= chunk) {
+      s = capture(&g_gal, [&] { launch_galerkin_iters<Real>(g, a, chunk, st); });
+      if (s) return s;
+    }
     while (ff > 0 && done < max_iters && rel > rtol) {
       const int k = std::min(chunk, max_iters - done);
-      launch_galerkin_iters<Real>(g, a, k, st);
+      if (g_gal && use_graphs() && k == chunk) CRV_HIP(hipGraphLaunch(g_gal, st));
+      else launch_galerkin_iters<Real>(g, a, k, st);
       if ((s = check_launch())) return s;
       if ((s = read_sc())) return s;
       done += k;
@@ -668,6 +674,7 @@ struct Solver : SolverBase {
   }
 
   ~Solver() override {
+    if (g_gal) (void)hipGraphExecDestroy(g_gal);
     if (gw_mem) (void)hipFree(gw_mem);
     if (g_train) (void)hipGraphExecDestroy(g_train);
     if (g_step) (void)hipGraphExecDestroy(g_step);

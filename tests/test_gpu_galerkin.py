@@ -73,3 +73,22 @@ def test_galerkin_path_rejects_3d():
     sc = scenario_for(prob, "fp32")
     with pytest.raises(crv.CrvError, match="2D"):
         sc.pressure_galerkin()
+
+
+def test_captured_cg_chunks_equal_eager_launches():
+    """The CG iterations replayed from a captured graph (chunks of 25, the
+    host reading the residual between replays) give bitwise the result of
+    the same iterations launched one by one."""
+    import os
+    prob = problem("c1", n_elem=48)
+    sc_graph, _ = _pair(prob, "fp32", grav=True)
+    os.environ["CRV_NO_GRAPH"] = "1"
+    try:
+        sc_eager, _ = _pair(prob, "fp32", grav=True)
+    finally:
+        del os.environ["CRV_NO_GRAPH"]
+    for _ in range(2):  # the second solve replays the graph captured by the first
+        pg, ig, rg = sc_graph.pressure_galerkin(rtol=1e-7)
+        pe, ie, re = sc_eager.pressure_galerkin(rtol=1e-7)
+        assert ig == ie and rg == re and np.array_equal(pg, pe)
+        assert ig >= 50
