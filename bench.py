@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="concurrent 512^2 scenarios")
     ap.add_argument("--batch-sweep", default="32,64",
                     help="further batch sizes timed for the aggregate rate ('' to skip)")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the gravity variant and the direct-solver path")
     ap.add_argument("--alt-precision", default="bf16x3",
                     help="second network arithmetic timed beside the headline ('' to skip)")
     ap.add_argument("--workload", default="b512")
@@ -312,12 +314,14 @@ def main():
         sweep[str(nb_)] = {"value": r_["value"], "ms_per_round": r_["ms_per_round"]}
     # the gravity variant of the same workload (pressure right-hand side and
     # gas flux with buoyancy; gravity 2, densities 1.2 and 0.4)
-    log(f"{args.precision} single scenario with gravity, {args.steps} steps")
-    grav, _ = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain, False,
-                         gravity=2.0, rho_w=1.2, rho_g=0.4)
-    grav["config"] = {"gravity": 2.0, "rho_w": 1.2, "rho_g": 0.4}
-    log("direct-solver path: Galerkin pressure solves and steps (fp32)")
-    galerkin = run_galerkin(prob, "fp32", args.steps, single["dt"])
+    grav = galerkin = None
+    if args.variants:
+        log(f"{args.precision} single scenario with gravity, {args.steps} steps")
+        grav, _ = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain, False,
+                             gravity=2.0, rho_w=1.2, rho_g=0.4)
+        grav["config"] = {"gravity": 2.0, "rho_w": 1.2, "rho_g": 0.4}
+        log("direct-solver path: Galerkin pressure solves and steps (fp32)")
+        galerkin = run_galerkin(prob, "fp32", args.steps, single["dt"])
     serving = None
     if args.serve > 0:
         from paper_2604_20731_amd.serve import Server
