@@ -13,13 +13,16 @@
  *   crv_get_fields        the pressure map and the saturation.
  * Further calls expose single pieces of the path (robust loss and its
  * gradients, Gram and mass solves, projection, substeps) and the training
- * state, for verification, differentiation and checkpoint/resume.
+ * state, for verification, differentiation and checkpoint/resume, and the
+ * paper's direct-solver pressure path that CRVPINN replaces (the IGA
+ * Galerkin system of eq. 15-20: crv_pressure_galerkin, crv_step_galerkin).
  *
  * Discretisation (readings of the paper, fixed here):
  *   - unit square/cube, Ne elements per axis; collocation N = Ne, nodes
  *     x_i = i/N, i = 0..N (eq. 21), (N+1)^d nodes;
  *   - B-splines of degree r on open uniform knots, nb = Ne + r per axis;
- *   - pressure -div(alpha grad p) = q, p = 0 on the boundary, gravity zero;
+ *   - pressure -div(alpha grad p) = q - div(g F_b), p = 0 on the boundary,
+ *     g = -gravity e_v (zero unless crv_config.gravity is set; see there);
  *     alpha = K (kr_w(s)/mu_w + kr_g(s)/mu_g), kr_w = (1-s)^n, kr_g = s^n at
  *     s = clamp(S, 0, 1) (second eq. 23 with Brooks-Corey mobilities);
  *   - RES_k = a_h(u, delta_k) - (q, delta_k)_h at interior nodes (eq. 24-25),
