@@ -87,3 +87,24 @@ def test_precision_names_cover_the_enum():
     for name in ("fp32", "bf16", "fp64", "bf16x3", "bf16x3f"):
         cfg = crv.config(width=64, hidden=4, precision=name)
         assert crv.workspace_size(cfg) > 0
+
+
+def test_gravity_config_and_galerkin_argument_errors():
+    """Gravity fields sit at the end of crv_config (the binding's structure
+    matches the header's order), default to zero and are validated; the
+    direct-solver entry points reject a missing context before any device
+    work."""
+    import ctypes as C
+    cfg = crv.config()
+    assert cfg.gravity == 0.0 and cfg.rho_w == 0.0 and cfg.rho_g == 0.0
+    names = [f for f, _ in crv.CrvConfig._fields_]
+    assert names[-3:] == ["gravity", "rho_w", "rho_g"]
+    assert crv.workspace_size(crv.config(gravity=9.81, rho_w=1.0, rho_g=0.5)) > 0
+    for bad in (dict(gravity=-1.0), dict(rho_w=-0.1), dict(rho_g=float("nan"))):
+        n = C.c_size_t()
+        c = crv.config(**bad)
+        assert crv.LIB.crv_workspace_size(C.byref(c), C.byref(n)) == crv.CRV_EINVAL, bad
+    it, rr = C.c_int(), C.c_double()
+    assert crv.LIB.crv_pressure_galerkin(None, 10, 1e-6, None, C.byref(it), C.byref(rr)) == crv.CRV_EINVAL
+    assert crv.LIB.crv_step_galerkin(None, 1e-3, 10, 1e-6, None, None) == crv.CRV_EINVAL
+    assert "context" in crv.LIB.crv_last_error().decode()
