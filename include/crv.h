@@ -151,12 +151,12 @@ crv_status crv_sync(crv_ctx* ctx);
  * grad B, F = int q B + int (g F_b) . grad B with alpha and the buoyancy
  * flux F_b from the current saturation, P = 0 on the boundary coefficients.
  * Solved matrix-free by conjugate gradients with the diagonal of S as
- * preconditioner, from P = 0, until |F - S P| <= rtol |F| (tested every 25
+ * preconditioner, from P = 0, until |F - S P| <= rtol |F| (tested every 24
  * iterations) or max_iters.  The solution replaces the pressure
  * coefficients the saturation substeps use.  p_coefs (nullable, host,
  * nb^2) receives them; iters and rel_residual (nullable) the iteration count
  * and |r|/|F|.  The first call allocates the solver's device arrays (owned
- * by the context, about 5 (Ne (r+1))^2 + 6 nb^2 values); CRV_EINVAL in 3D or
+ * by the context, about 3 (Ne (r+1))^2 + 6 nb^2 values); CRV_EINVAL in 3D or
  * for max_iters < 0 or a negative rtol; blocks until done. */
 crv_status crv_pressure_galerkin(crv_ctx* ctx, int max_iters, double rtol, double* p_coefs,
                                  int* iters, double* rel_residual);

@@ -4,13 +4,14 @@
 // coefficients, solved by conjugate gradients with the diagonal of S as the
 // preconditioner.
 //
-// S is never assembled.  Its product with a coefficient vector is two passes:
-// the gradient of the spline at every Gauss point times w alpha there (one
-// thread per Gauss point), then, for every coefficient, the sum over the
-// Gauss points of its support of that flux against the basis gradient (one
-// thread per coefficient, fixed order, no atomics).  Load and diagonal use the
-// same gather.  Gauss-point arrays are (Ne (r+1))^2, x fastest; coefficient
-// arrays nb^2.
+// S is never assembled.  Its product with a coefficient vector runs on tiles
+// of TC x TC coefficients per block: the block stages the coefficients its
+// elements touch in LDS, evaluates w alpha grad x at the Gauss points of those
+// elements into LDS, and each thread sums its own coefficient's share over its
+// support in a fixed order (no atomics); the same pass leaves the block's part
+// of x . Sx for the CG step.  Load and diagonal are one-off gathers from
+// Gauss-point arrays.  Gauss-point arrays are (Ne (r+1))^2, x fastest;
+// coefficient arrays nb^2.
 #include "kernels.h"
 
 namespace crv {
@@ -52,41 +53,6 @@ __global__ __launch_bounds__(256) void k_gal_fields2(
   c[t] = w * kk * (krw * inv_mu_w + krg * inv_mu_g);
   f0[t] = w * (q1(qi) + q1(qp));
   if (fy) fy[t] = -gravity * w * kk * (krw * rw_mu + krg * rg_mu);
-}
-
-// vx = c d_x x, vy = c d_y x at every Gauss point
-template <typename Real, int R>
-__global__ __launch_bounds__(256) void k_gal_grad2(Geom g, const Real* __restrict__ x,
-                                                   const Real* __restrict__ c,
-                                                   const Real* __restrict__ gb,
-                                                   const Real* __restrict__ gdb,
-                                                   Real* __restrict__ vx, Real* __restrict__ vy) {
-  constexpr int NG = R + 1;
-  const int ng = g.ne * NG;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(ng) * ng) return;
-  const int gxl = int(t % ng), gyl = int(t / ng);
-  const int ex = gxl / NG, gx = gxl % NG, ey = gyl / NG, gy = gyl % NG;
-  const Real* bx = gb + (int64_t(ex) * NG + gx) * (R + 1);
-  const Real* dbx = gdb + (int64_t(ex) * NG + gx) * (R + 1);
-  const Real* by = gb + (int64_t(ey) * NG + gy) * (R + 1);
-  const Real* dby = gdb + (int64_t(ey) * NG + gy) * (R + 1);
-  Real px = 0, py = 0;
-#pragma unroll
-  for (int b = 0; b <= R; ++b) {
-    Real rx = 0, rv = 0;
-#pragma unroll
-    for (int a = 0; a <= R; ++a) {
-      const Real v = x[int64_t(ey + b) * g.nb + ex + a];
-      rx += dbx[a] * v;
-      rv += bx[a] * v;
-    }
-    px += by[b] * rx;
-    py += dby[b] * rv;
-  }
-  const Real cc = c[t];
-  vx[t] = cc * px;
-  vy[t] = cc * py;
 }
 
 // out_kl = sum over the Gauss points of B_kl's support of
@@ -138,8 +104,99 @@ __global__ __launch_bounds__(256) void k_gal_gather2(Geom g, const Real* __restr
   out[t] = acc;
 }
 
+// y = S x on a TC x TC tile of coefficients per block (boundary coefficients
+// 0); part[2 b] = the tile's share of x . y, part[2 b + 1] = 0
+template <typename Real, int R, int TC>
+__global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __restrict__ x,
+                                                      const Real* __restrict__ c,
+                                                      const Real* __restrict__ gb,
+                                                      const Real* __restrict__ gdb,
+                                                      Real* __restrict__ y,
+                                                      double* __restrict__ part) {
+  constexpr int NG = R + 1;
+  constexpr int TE = TC + R;       // elements per tile and axis
+  constexpr int TCO = TC + 2 * R;  // coefficients those elements touch
+  constexpr int GP = TE * NG;      // Gauss points per axis
+  __shared__ Real sX[TCO * TCO], sFx[GP * GP], sFy[GP * GP];
+  __shared__ double red[TC * TC];
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC;
+  const int c0x = k0 - R, c0y = l0 - R;
+  const int nb = g.nb, ne = g.ne, ng = ne * NG;
+  for (int t = tid; t < TCO * TCO; t += TC * TC) {
+    const int a = c0x + t % TCO, bb = c0y + t / TCO;
+    sX[t] = (a >= 0 && a < nb && bb >= 0 && bb < nb) ? x[int64_t(bb) * nb + a] : Real(0);
+  }
+  __syncthreads();
+  for (int t = tid; t < GP * GP; t += TC * TC) {
+    const int gxl = t % GP, gyl = t / GP;
+    const int exl = gxl / NG, gx = gxl % NG, eyl = gyl / NG, gy = gyl % NG;
+    const int ex = c0x + exl, ey = c0y + eyl;
+    Real fx = 0, fy = 0;
+    if (ex >= 0 && ex < ne && ey >= 0 && ey < ne) {
+      const Real* bx = gb + (int64_t(ex) * NG + gx) * (R + 1);
+      const Real* dbx = gdb + (int64_t(ex) * NG + gx) * (R + 1);
+      const Real* by = gb + (int64_t(ey) * NG + gy) * (R + 1);
+      const Real* dby = gdb + (int64_t(ey) * NG + gy) * (R + 1);
+      Real px = 0, py = 0;
+#pragma unroll
+      for (int b = 0; b <= R; ++b) {
+        Real rx = 0, rv = 0;
+#pragma unroll
+        for (int a = 0; a <= R; ++a) {
+          const Real v = sX[(eyl + b) * TCO + exl + a];
+          rx += dbx[a] * v;
+          rv += bx[a] * v;
+        }
+        px += by[b] * rx;
+        py += dby[b] * rv;
+      }
+      const Real cc = c[int64_t(ey * NG + gy) * ng + ex * NG + gx];
+      fx = cc * px;
+      fy = cc * py;
+    }
+    sFx[t] = fx;
+    sFy[t] = fy;
+  }
+  __syncthreads();
+  const int tx = tid % TC, ty = tid / TC;
+  const int k = k0 + tx, l = l0 + ty;
+  double xy = 0;
+  if (k < nb && l < nb) {
+    Real acc = 0;
+    if (k > 0 && l > 0 && k < nb - 1 && l < nb - 1) {
+      for (int ey = max(l - R, 0); ey <= min(l, ne - 1); ++ey) {
+        const int bb = l - ey, eyl = ey - c0y;
+        for (int ex = max(k - R, 0); ex <= min(k, ne - 1); ++ex) {
+          const int a = k - ex, exl = ex - c0x;
+#pragma unroll
+          for (int gy = 0; gy < NG; ++gy) {
+            const Real by = gb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+            const Real dby = gdb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+#pragma unroll
+            for (int gx = 0; gx < NG; ++gx) {
+              const Real bx = gb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+              const Real dbx = gdb[(int64_t(ex) * NG + gx) * (R + 1) + a];
+              const int t = (eyl * NG + gy) * GP + exl * NG + gx;
+              acc += dbx * by * sFx[t] + bx * dby * sFy[t];
+            }
+          }
+        }
+      }
+    }
+    y[int64_t(l) * nb + k] = acc;
+    xy = double(sX[(ty + R) * TCO + tx + R]) * double(acc);
+  }
+  const double t = block_sum_n<TC * TC>(xy, red);
+  if (tid == 0) {
+    const int64_t bid = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    part[2 * bid] = t;
+    part[2 * bid + 1] = 0;
+  }
+}
+
 // ---- conjugate-gradient pieces; scalars live on the device (sc[]):
-//      0 rz, 1 rz_new, 2 pAp, 3 rr, 4 ff
+//      0 and 1 rz of consecutive iterations (alternating), 2 pAp, 3 rr, 4 ff
 constexpr int kDotBlocks = 256;
 
 // fixed-order partial sums of a.b and (if c) c.d, double accumulation
@@ -193,85 +250,89 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const Real* __restr
   p[i] = z[i];
 }
 
-// a = rz / pAp: x += a p, r -= a Ap, z = r / d
+// a = rz / pAp (rz in slot s_rz): x += a p, r -= a Ap, z = r / d, with the
+// block's parts of the new r.z and r.r (grid-stride, kDotBlocks blocks)
 template <typename Real>
 __global__ __launch_bounds__(256) void k_pcg_step1(int64_t n, const double* __restrict__ sc,
-                                                   Real* __restrict__ x, Real* __restrict__ r,
-                                                   Real* __restrict__ z, const Real* __restrict__ p,
+                                                   int s_rz, Real* __restrict__ x,
+                                                   Real* __restrict__ r, Real* __restrict__ z,
+                                                   const Real* __restrict__ p,
                                                    const Real* __restrict__ ap,
-                                                   const Real* __restrict__ dg) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Real a = sc[2] != 0.0 ? Real(sc[0] / sc[2]) : Real(0);  // converged exactly: stay
-  x[i] += a * p[i];
-  const Real ri = r[i] - a * ap[i];
-  r[i] = ri;
-  z[i] = ri / dg[i];
+                                                   const Real* __restrict__ dg,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  const Real a = sc[2] != 0.0 ? Real(sc[s_rz] / sc[2]) : Real(0);  // converged exactly: stay
+  double s1 = 0, s2 = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    x[i] += a * p[i];
+    const Real ri = r[i] - a * ap[i];
+    const Real zi = ri / dg[i];
+    r[i] = ri;
+    z[i] = zi;
+    s1 += double(ri) * double(zi);
+    s2 += double(ri) * double(ri);
+  }
+  const double t1 = block_sum_n<256>(s1, red);
+  const double t2 = block_sum_n<256>(s2, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t1;
+    part[2 * blockIdx.x + 1] = t2;
+  }
 }
 
-// b = rz_new / rz: p = z + b p
+// b = rz_new / rz_old: p = z + b p
 template <typename Real>
 __global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, const double* __restrict__ sc,
-                                                   const Real* __restrict__ z, Real* __restrict__ p) {
+                                                   int s_new, int s_old, const Real* __restrict__ z,
+                                                   Real* __restrict__ p) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Real b = sc[0] != 0.0 ? Real(sc[1] / sc[0]) : Real(0);
+  const Real b = sc[s_old] != 0.0 ? Real(sc[s_new] / sc[s_old]) : Real(0);
   p[i] = z[i] + b * p[i];
 }
 
-__global__ void k_pcg_shift(double* sc) { sc[0] = sc[1]; }
+// tile edge of the operator kernel: 16 (float, r <= 2), else 8 (LDS)
+template <typename Real, int R>
+constexpr int gal_tc() { return (sizeof(Real) == 4 && R <= 2) ? 16 : 8; }
+
+int64_t galerkin_partials(const Geom& g) {
+  const int64_t t = cdiv(g.nb, 8);
+  return std::max<int64_t>(kDotBlocks, t * t);
+}
 
 template <typename Real, int R>
-static void gal_fields(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st) {
+static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st) {
   const int64_t npts = ipow(int64_t(g.ne) * (R + 1), 2);
   k_gal_fields2<Real, R><<<cdiv(npts, 256), 256, 0, st>>>(
       g, a.s, a.perm, a.qi, a.qp, a.gb, a.gxi, a.gw, Real(1.0 / a.mu_w), Real(1.0 / a.mu_g),
       Real(a.nexp), Real(a.rho_w / a.mu_w), Real(a.rho_g / a.mu_g), Real(a.gravity), a.ws.c,
       a.ws.f0, a.gravity != 0.0 ? a.ws.fy : nullptr);
-  const int64_t nc = int64_t(g.nb) * g.nb;
-  k_gal_gather2<Real, R, false><<<cdiv(nc, 256), 256, 0, st>>>(
-      g, a.ws.f0, nullptr, a.gravity != 0.0 ? a.ws.fy : nullptr, a.gb, a.gdb, a.ws.f);
-  k_gal_gather2<Real, R, true><<<cdiv(nc, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
-                                                              a.gdb, a.ws.dg);
-}
-
-template <typename Real, int R>
-static void gal_apply(const Geom& g, const GalerkinArgs<Real>& a, const Real* x, Real* y,
-                      hipStream_t st) {
-  const int64_t npts = ipow(int64_t(g.ne) * (R + 1), 2);
-  k_gal_grad2<Real, R><<<cdiv(npts, 256), 256, 0, st>>>(g, x, a.ws.c, a.gb, a.gdb, a.ws.vx, a.ws.vy);
-  const int64_t nc = int64_t(g.nb) * g.nb;
-  k_gal_gather2<Real, R, false><<<cdiv(nc, 256), 256, 0, st>>>(g, nullptr, a.ws.vx, a.ws.vy, a.gb,
-                                                               a.gdb, y);
-}
-
-template <typename Real>
-static void dot2(int64_t n, const Real* x1, const Real* y1, const Real* x2, const Real* y2,
-                 double* part, double* sc, int s1, int s2, hipStream_t st) {
-  k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, x1, y1, x2, y2, part);
-  k_dot2_fin<<<1, 256, 0, st>>>(part, kDotBlocks, sc, s1, s2);
-}
-
-template <typename Real, int R>
-static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st) {
-  gal_fields<Real, R>(g, a, st);
   const int64_t n = int64_t(g.nb) * g.nb;
+  k_gal_gather2<Real, R, false><<<cdiv(n, 256), 256, 0, st>>>(
+      g, a.ws.f0, nullptr, a.gravity != 0.0 ? a.ws.fy : nullptr, a.gb, a.gdb, a.ws.f);
+  k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
+                                                             a.gdb, a.ws.dg);
   k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.f, a.ws.dg, a.x, a.ws.r, a.ws.z, a.ws.p);
-  dot2<Real>(n, a.ws.r, a.ws.z, a.ws.f, a.ws.f, a.ws.part, a.ws.sc, 0, 4, st);
+  k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.r, a.ws.z, a.ws.f, a.ws.f, a.ws.part);
+  k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, 0, 4);
 }
 
+// iters CG iterations; iteration it starts with rz in slot it & 1
 template <typename Real, int R>
 static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st) {
+  constexpr int TC = gal_tc<Real, R>();
   const int64_t n = int64_t(g.nb) * g.nb;
+  const dim3 tiles(cdiv(g.nb, TC), cdiv(g.nb, TC));
+  const int ntiles = int(tiles.x * tiles.y);
   for (int it = 0; it < iters; ++it) {
-    gal_apply<Real, R>(g, a, a.ws.p, a.ws.ap, st);
-    dot2<Real>(n, a.ws.p, a.ws.ap, static_cast<const Real*>(nullptr), static_cast<const Real*>(nullptr),
-               a.ws.part, a.ws.sc, 2, -1, st);
-    k_pcg_step1<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, a.x, a.ws.r, a.ws.z, a.ws.p, a.ws.ap,
-                                                    a.ws.dg);
-    dot2<Real>(n, a.ws.r, a.ws.z, a.ws.r, a.ws.r, a.ws.part, a.ws.sc, 1, 3, st);
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, a.ws.z, a.ws.p);
-    k_pcg_shift<<<1, 1, 0, st>>>(a.ws.sc);
+    const int s_old = it & 1, s_new = s_old ^ 1;
+    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, a.ws.p, a.ws.c, a.gb, a.gdb, a.ws.ap,
+                                                         a.ws.part);
+    k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, ntiles, a.ws.sc, 2, -1);
+    k_pcg_step1<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z, a.ws.p,
+                                                  a.ws.ap, a.ws.dg, a.ws.part);
+    k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, s_new, 3);
+    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, s_new, s_old, a.ws.z, a.ws.p);
   }
 }
 

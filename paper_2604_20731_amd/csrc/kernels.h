@@ -59,13 +59,16 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
 
 // ---- IGA Galerkin pressure system, 2D (k_galerkin.hip; eq. 15-20) --------
 // Device arrays of one solve (owned by the context): Gauss-point arrays
-// (Ne (r+1))^2, coefficient arrays nb^2, 5 scalars and 2 x 256 partial sums.
+// (Ne (r+1))^2, coefficient arrays nb^2, 5 scalars and 2 x galerkin_partials
+// partial sums.
 template <typename Real>
 struct GalerkinWork {
-  Real *c, *f0, *fy, *vx, *vy;    // w alpha, w q, -gravity w F_b, fluxes of the product
+  Real *c, *f0, *fy;              // w alpha, w q, -gravity w F_b at the Gauss points
   Real *f, *dg, *r, *z, *p, *ap;  // load, diagonal, CG vectors
   double *sc, *part;
 };
+// partial sums a solve writes at most (operator tiles or dot-product blocks)
+int64_t galerkin_partials(const Geom& g);
 template <typename Real>
 struct GalerkinArgs {
   const Real *s, *perm, *qi, *qp, *gb, *gdb, *gxi, *gw;
@@ -76,7 +79,9 @@ struct GalerkinArgs {
 // fields at the Gauss points, load, diagonal; x = 0 and the first CG vectors
 template <typename Real>
 void launch_galerkin_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st);
-// iters CG iterations (scalars stay on the device: sc[3] = r.r, sc[4] = F.F)
+// iters CG iterations from rz in slot 0 (they alternate the slot, so a
+// further call continues correctly only after an even count; scalars stay on
+// the device: sc[3] = r.r, sc[4] = F.F)
 template <typename Real>
 void launch_galerkin_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st);
 

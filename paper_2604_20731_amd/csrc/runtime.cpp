@@ -591,15 +591,14 @@ struct Solver : SolverBase {
     if (gw_mem) return CRV_OK;
     const size_t npts = size_t(ipow(int64_t(g.ne) * (g.r + 1), 2)), ncf = size_t(g.nb) * g.nb;
     auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
-    const size_t bytes = 5 * up(npts * sizeof(Real)) + 6 * up(ncf * sizeof(Real)) +
-                         up(8 * sizeof(double)) + up(2 * 256 * sizeof(double));
+    const size_t nparts = size_t(galerkin_partials(g));
+    const size_t bytes = 3 * up(npts * sizeof(Real)) + 6 * up(ncf * sizeof(Real)) +
+                         up(8 * sizeof(double)) + up(2 * nparts * sizeof(double));
     CRV_HIP(hipMalloc(&gw_mem, bytes));
     Carve cv(gw_mem);
     gw.c = cv.take<Real>(npts);
     gw.f0 = cv.take<Real>(npts);
     gw.fy = cv.take<Real>(npts);
-    gw.vx = cv.take<Real>(npts);
-    gw.vy = cv.take<Real>(npts);
     gw.f = cv.take<Real>(ncf);
     gw.dg = cv.take<Real>(ncf);
     gw.r = cv.take<Real>(ncf);
@@ -607,7 +606,7 @@ struct Solver : SolverBase {
     gw.p = cv.take<Real>(ncf);
     gw.ap = cv.take<Real>(ncf);
     gw.sc = cv.take<double>(8);
-    gw.part = cv.take<double>(2 * 256);
+    gw.part = cv.take<double>(2 * nparts);
     return CRV_OK;
   }
   GalerkinArgs<Real> galerkin_args() {
@@ -616,8 +615,9 @@ struct Solver : SolverBase {
                               cfg.gravity, b.p, gw};
   }
   // S P = F for the current saturation into b.p by diagonally preconditioned
-  // CG from P = 0, until |r| <= rtol |F| (checked every 25 iterations) or
-  // max_iters
+  // CG from P = 0, until |r| <= rtol |F| (checked every 24 iterations) or
+  // max_iters.  Iterations alternate the slot of r.z, so every chunk but the
+  // last (which may be shorter) has an even length
   crv_status pressure_galerkin(int max_iters, double rtol, double* p_out, int* iters_out,
                                double* relres_out) override {
     if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
@@ -637,7 +637,7 @@ struct Solver : SolverBase {
     const double ff = sc[4];
     double rel = ff > 0 ? 1.0 : 0.0;
     int done = 0;
-    const int chunk = 25;
+    const int chunk = 24;  // even: each chunk starts with rz in slot 0
     if (use_graphs() && !g_gal && ff > 0 && max_iters >= chunk) {
       s = capture(&g_gal, [&] { launch_galerkin_iters<Real>(g, a, chunk, st); });
       if (s) return s;
