@@ -190,27 +190,34 @@ def run_single(prob, precision, steps, warmup, pretrain, profile, **cfg):
 
 def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
     """The paper's direct-solver path on the same workload: the Galerkin
-    pressure system (matrix-free, preconditioned CG) timed per solve, and
-    coupled steps of that algorithm (substeps + pressure re-solve) per second."""
+    pressure system (matrix-free CG, preconditioned by the scaled Kronecker
+    inverse, and for comparison by the diagonal) timed per solve, and coupled
+    steps of that algorithm (substeps + pressure re-solve) per second."""
     import torch
     from paper_2604_20731_amd import crv
-    sc = crv.scenario_from_problem(prob, precision)
-    sc.pressure_galerkin(rtol=rtol)                      # allocates, warms up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p, iters, rr = sc.pressure_galerkin(rtol=rtol)
-    t_solve = time.perf_counter() - t0
     nb = prob.n_elem + prob.degree
-    sc.step_galerkin(dt, rtol=rtol)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sc.step_galerkin(dt, rtol=rtol)
-    t_step = (time.perf_counter() - t0) / steps
-    sc.close()
-    return {"precision": precision, "rtol": rtol, "cg_iters": iters, "rel_residual": rr,
-            "ms_per_solve": 1e3 * t_solve, "coupled_steps_per_s": 1.0 / t_step,
-            "note": f"{nb}^2 pressure coefficients; direct-solver algorithm (substeps + "
-                    "Galerkin pressure re-solve, no network)"}
+
+    def one(precond):
+        sc = crv.scenario_from_problem(prob, precision)
+        sc.pressure_galerkin(rtol=rtol, precond=precond)      # allocates, warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, iters, rr = sc.pressure_galerkin(rtol=rtol, precond=precond)
+        t_solve = time.perf_counter() - t0
+        sc.step_galerkin(dt, rtol=rtol, precond=precond)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sc.step_galerkin(dt, rtol=rtol, precond=precond)
+        t_step = (time.perf_counter() - t0) / steps
+        sc.close()
+        return {"precond": precond, "cg_iters": iters, "rel_residual": rr,
+                "ms_per_solve": 1e3 * t_solve, "coupled_steps_per_s": 1.0 / t_step}
+
+    out = {"precision": precision, "rtol": rtol, **one("kron")}
+    out["jacobi"] = one("jacobi")
+    out["note"] = (f"{nb}^2 pressure coefficients; direct-solver algorithm (substeps + Galerkin "
+                   "pressure re-solve from P = 0, no network)")
+    return out
 
 
 def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):

@@ -146,27 +146,36 @@ crv_status crv_train_async(crv_ctx* ctx, int iters);
  * non-finite saturation was flagged. */
 crv_status crv_sync(crv_ctx* ctx);
 
+/* Preconditioners of the Galerkin conjugate-gradient solve. */
+#define CRV_PRECOND_JACOBI 0 /* the diagonal of S */
+#define CRV_PRECOND_KRON 1   /* D (V x V) L^-1 (V x V) D: V the DST-I basis of the
+                              * interior coefficients, L the symbol of the
+                              * constant-coefficient operator K x M + M x K of
+                              * uniform B-splines, D = sqrt(diag of that operator /
+                              * diag S) (a scaled fast-diagonalisation inverse) */
+
 /* The paper's direct-solver pressure path (eq. 15-20; 2D only): the IGA
  * Galerkin system S P = F on the B-spline space, S = int alpha grad B .
  * grad B, F = int q B + int (g F_b) . grad B with alpha and the buoyancy
  * flux F_b from the current saturation, P = 0 on the boundary coefficients.
- * Solved matrix-free by conjugate gradients with the diagonal of S as
- * preconditioner, from P = 0, until |F - S P| <= rtol |F| (tested every 24
+ * Solved matrix-free by conjugate gradients with preconditioner precond
+ * (CRV_PRECOND_*), from P = 0, until |F - S P| <= rtol |F| (tested every 24
  * iterations) or max_iters.  The solution replaces the pressure
  * coefficients the saturation substeps use.  p_coefs (nullable, host,
  * nb^2) receives them; iters and rel_residual (nullable) the iteration count
  * and |r|/|F|.  The first call allocates the solver's device arrays (owned
- * by the context, about 3 (Ne (r+1))^2 + 6 nb^2 values); CRV_EINVAL in 3D or
- * for max_iters < 0 or a negative rtol; blocks until done. */
-crv_status crv_pressure_galerkin(crv_ctx* ctx, int max_iters, double rtol, double* p_coefs,
-                                 int* iters, double* rel_residual);
+ * by the context, about 3 (Ne (r+1))^2 + 7 nb^2 + 4 mp^2 values, mp = nb - 2
+ * rounded up to 64); CRV_EINVAL in 3D, for max_iters < 0, a negative rtol or
+ * an unknown precond; blocks until done. */
+crv_status crv_pressure_galerkin(crv_ctx* ctx, int max_iters, double rtol, int precond,
+                                 double* p_coefs, int* iters, double* rel_residual);
 
 /* One pass of that algorithm: cfg.substeps saturation substeps of
  * tau = dt/substeps with the current pressure coefficients, refresh, and the
  * Galerkin pressure of the new saturation (crv_pressure_galerkin).  No
  * network training.  Blocks until done. */
-crv_status crv_step_galerkin(crv_ctx* ctx, double dt, int max_iters, double rtol, int* iters,
-                             double* rel_residual);
+crv_status crv_step_galerkin(crv_ctx* ctx, double dt, int max_iters, double rtol, int precond,
+                             int* iters, double* rel_residual);
 
 /* Algorithm steps 4-7, one coupled step of length dt > 0: project the
  * network pressure, cfg.substeps substeps of tau = dt/substeps, refresh

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcrv.so")
 
 CRV_OK, CRV_EINVAL, CRV_ENOMEM, CRV_EHIP, CRV_ENUMERIC, CRV_ESTATE = 0, -1, -2, -3, -4, -5
 PREC = {"fp32": 0, "bf16": 1, "fp64": 2, "bf16x3": 3, "bf16x3f": 4}
+PRECOND = {"jacobi": 0, "kron": 1}  # CRV_PRECOND_* of the Galerkin CG
 STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
                 -4: "CRV_ENUMERIC", -5: "CRV_ESTATE"}
 
@@ -85,8 +86,9 @@ def _load() -> C.CDLL:
         "crv_mass_solve": [vp, dp, dp],
         "crv_project_pressure": [vp, dp],
         "crv_saturation_substeps": [vp, C.c_double, C.c_int],
-        "crv_pressure_galerkin": [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int), dp],
-        "crv_step_galerkin": [vp, C.c_double, C.c_int, C.c_double, C.POINTER(C.c_int), dp],
+        "crv_pressure_galerkin": [vp, C.c_int, C.c_double, C.c_int, dp, C.POINTER(C.c_int), dp],
+        "crv_step_galerkin": [vp, C.c_double, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_int),
+                              dp],
         "crv_profile_enable": [vp, C.c_int],
         "crv_profile_read": [vp, C.c_int, dp, C.POINTER(C.c_int64)],
         "crv_destroy": [vp],
@@ -278,22 +280,25 @@ class Scenario:
     def saturation_substeps(self, tau: float, n: int):
         _check(LIB.crv_saturation_substeps(self.ctx, float(tau), int(n)))
 
-    def pressure_galerkin(self, max_iters: int = 20000, rtol: float = 1e-6):
-        """Galerkin pressure of the current saturation (2D): (coefficients
-        nb^2, CG iterations, |r|/|F|)."""
+    def pressure_galerkin(self, max_iters: int = 20000, rtol: float = 1e-6,
+                          precond: str = "kron"):
+        """Galerkin pressure of the current saturation (2D) by CG with the
+        preconditioner "kron" (scaled Kronecker inverse) or "jacobi":
+        (coefficients nb^2, CG iterations, |r|/|F|)."""
         nb = self.cfg.n_elem + self.cfg.degree
         out = np.zeros(nb ** self.cfg.dim)
         it, rr = C.c_int(), C.c_double()
-        _check(LIB.crv_pressure_galerkin(self.ctx, int(max_iters), float(rtol), _dp(out),
-                                         C.byref(it), C.byref(rr)))
+        _check(LIB.crv_pressure_galerkin(self.ctx, int(max_iters), float(rtol),
+                                         PRECOND[precond], _dp(out), C.byref(it), C.byref(rr)))
         return out, it.value, rr.value
 
-    def step_galerkin(self, dt: float, max_iters: int = 20000, rtol: float = 1e-6):
+    def step_galerkin(self, dt: float, max_iters: int = 20000, rtol: float = 1e-6,
+                      precond: str = "kron"):
         """Substeps with the current pressure coefficients, then the Galerkin
         pressure of the new saturation: (CG iterations, |r|/|F|)."""
         it, rr = C.c_int(), C.c_double()
         _check(LIB.crv_step_galerkin(self.ctx, float(dt), int(max_iters), float(rtol),
-                                     C.byref(it), C.byref(rr)))
+                                     PRECOND[precond], C.byref(it), C.byref(rr)))
         return it.value, rr.value
 
     def profile_enable(self, on: bool = True):

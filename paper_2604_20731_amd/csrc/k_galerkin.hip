@@ -1,8 +1,8 @@
 // IGA Galerkin pressure system (the paper's direct-solver path, eq. 15-20),
 // 2D: S P = F with S = int alpha grad B . grad B and
 // F = int q B + int (g F_b) . grad B (g = -gravity e_y), P = 0 on the boundary
-// coefficients, solved by conjugate gradients with the diagonal of S as the
-// preconditioner.
+// coefficients, solved by conjugate gradients, preconditioned by the diagonal
+// of S or by a scaled Kronecker (fast-diagonalisation) inverse.
 //
 // S is never assembled.  Its product with a coefficient vector runs on tiles
 // of TC x TC coefficients per block: the block stages the coefficients its
@@ -236,7 +236,8 @@ __global__ __launch_bounds__(256) void k_dot2_fin(const double* __restrict__ par
   }
 }
 
-// x = 0, r = F, z = r / d, p = z
+// x = 0, r = F and z = r / d, p = z (dg given) or p = 0 (dg null: z comes
+// from the Kronecker preconditioner and p = z + b p then sets p = z)
 template <typename Real>
 __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const Real* __restrict__ f,
                                                   const Real* __restrict__ dg, Real* __restrict__ x,
@@ -246,13 +247,18 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const Real* __restr
   if (i >= n) return;
   x[i] = 0;
   r[i] = f[i];
-  z[i] = f[i] / dg[i];
-  p[i] = z[i];
+  if (dg) {
+    z[i] = f[i] / dg[i];
+    p[i] = z[i];
+  } else {
+    p[i] = 0;
+  }
 }
 
-// a = rz / pAp (rz in slot s_rz): x += a p, r -= a Ap, z = r / d, with the
-// block's parts of the new r.z and r.r (grid-stride, kDotBlocks blocks)
-template <typename Real>
+// a = rz / pAp (rz in slot s_rz): x += a p, r -= a Ap and, with JAC,
+// z = r / d and the block's parts of the new r.z and r.r (grid-stride,
+// kDotBlocks blocks); without JAC z and the parts are left alone
+template <typename Real, bool JAC>
 __global__ __launch_bounds__(256) void k_pcg_step1(int64_t n, const double* __restrict__ sc,
                                                    int s_rz, Real* __restrict__ x,
                                                    Real* __restrict__ r, Real* __restrict__ z,
@@ -266,12 +272,15 @@ __global__ __launch_bounds__(256) void k_pcg_step1(int64_t n, const double* __re
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     x[i] += a * p[i];
     const Real ri = r[i] - a * ap[i];
-    const Real zi = ri / dg[i];
     r[i] = ri;
-    z[i] = zi;
-    s1 += double(ri) * double(zi);
-    s2 += double(ri) * double(ri);
+    if constexpr (JAC) {
+      const Real zi = ri / dg[i];
+      z[i] = zi;
+      s1 += double(ri) * double(zi);
+      s2 += double(ri) * double(ri);
+    }
   }
+  if constexpr (!JAC) return;
   const double t1 = block_sum_n<256>(s1, red);
   const double t2 = block_sum_n<256>(s2, red);
   if (threadIdx.x == 0) {
@@ -289,6 +298,117 @@ __global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, const double* __re
   if (i >= n) return;
   const Real b = sc[s_old] != 0.0 ? Real(sc[s_new] / sc[s_old]) : Real(0);
   p[i] = z[i] + b * p[i];
+}
+
+// ---- scaled Kronecker (fast-diagonalisation) preconditioner:
+//   z = D (V x V) L^-1 (V x V) D r   on the m = nb - 2 interior coefficients
+// per axis, with V the orthonormal DST-I basis of size m (padded to mp, a
+// multiple of 64), L_ij = k_i m_j + m_i k_j where m_i, k_i are the symbols
+// of the uniform B-spline mass and stiffness at the DST-I frequencies (the
+// symbol of the constant-coefficient operator K x M + M x K), and
+// D = sqrt(d0 / diag S) with d0 the diagonal of that operator, so that
+// D S D has the constant-coefficient diagonal.  D, V, L are symmetric and
+// positive (semi-)definite, so z = P r is a valid CG preconditioner.  The
+// four DST-I products run on the matrix cores; between them the interior
+// array is transposed once per axis change.
+
+// w at every Gauss point (the c of the constant-coefficient operator)
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_gal_weights2(Geom g, const Real* __restrict__ gw,
+                                                      Real* __restrict__ c) {
+  constexpr int NG = R + 1;
+  const int ng = g.ne * NG;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(ng) * ng) return;
+  c[t] = gw[int(t % ng) % NG] * gw[int(t / ng) % NG];
+}
+
+// ksc = sqrt(d0 / diag S) on the interior (d0 held in ksc on entry), 0 on the
+// boundary coefficients
+template <typename Real>
+__global__ __launch_bounds__(256) void k_kron_scalevec(int nb, const Real* __restrict__ dg,
+                                                       Real* __restrict__ ksc) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nb) * nb) return;
+  const int k = int(t % nb), l = int(t / nb);
+  const bool edge = k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
+  ksc[t] = edge ? Real(0) : Real(sqrt(ksc[t] / dg[t]));
+}
+
+// t[i][j] = (ksc r) at coefficient (i + 1, j + 1) (row i along y), 0 in the
+// padding (i or j >= m)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_kron_in(int nb, int m, int mp, const Real* __restrict__ r,
+                                                 const Real* __restrict__ ksc,
+                                                 Real* __restrict__ t) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(mp) * mp) return;
+  const int i = int(e / mp), j = int(e % mp);
+  Real v = 0;
+  if (i < m && j < m) {
+    const int64_t c = int64_t(i + 1) * nb + j + 1;
+    v = ksc[c] * r[c];
+  }
+  t[e] = v;
+}
+
+// z = ksc t on the interior (the inverse of k_kron_in's layout), 0 on the
+// boundary coefficients
+template <typename Real>
+__global__ __launch_bounds__(256) void k_kron_out(int nb, int mp, const Real* __restrict__ t,
+                                                  const Real* __restrict__ ksc,
+                                                  Real* __restrict__ z) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= int64_t(nb) * nb) return;
+  const int k = int(c % nb), l = int(c / nb);
+  const bool edge = k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
+  z[c] = edge ? Real(0) : ksc[c] * t[int64_t(l - 1) * mp + k - 1];
+}
+
+// t[i][j] /= k_i m_j + m_i k_j with sym = (m_0 .. m_mp-1, k_0 .. k_mp-1)
+// (padded modes carry m = k = 1 and zero values)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_kron_scale(int mp, const Real* __restrict__ sym,
+                                                    Real* __restrict__ t) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(mp) * mp) return;
+  const int i = int(e / mp), j = int(e % mp);
+  t[e] /= sym[mp + i] * sym[j] + sym[i] * sym[mp + j];
+}
+
+// out = in^T for an mp x mp array (mp a multiple of 32): 32 x 32 tiles
+// through LDS, 32 x 8 threads, coalesced on both sides
+template <typename Real>
+__global__ __launch_bounds__(256) void k_transpose(int mp, const Real* __restrict__ in,
+                                                   Real* __restrict__ out) {
+  __shared__ Real tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) tile[ty + k][tx] = in[int64_t(r0 + ty + k) * mp + c0 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) out[int64_t(c0 + ty + k) * mp + r0 + tx] = tile[tx][ty + k];
+}
+
+// z = P r (r and z nb^2 coefficient arrays, boundary 0); the DST-I basis is
+// symmetric, so every product is V times an mp x mp array: along y, then
+// (transposed) along x, scale, along x, (transposed back) along y
+template <typename Real>
+static void kron_apply(const GalerkinWork<Real>& w, int nb, const Real* r, Real* z,
+                       hipStream_t st) {
+  const int m = w.mg, mp = w.mgp;
+  const int64_t mp2 = int64_t(mp) * mp;
+  const dim3 tgrid(mp / 32, mp / 32);
+  k_kron_in<Real><<<cdiv(mp2, 256), 256, 0, st>>>(nb, m, mp, r, w.ksc, w.kt0);
+  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt0, mp, w.kt1, mp, st, w.kdst_pk);
+  k_transpose<Real><<<tgrid, 256, 0, st>>>(mp, w.kt1, w.kt0);
+  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt0, mp, w.kt1, mp, st, w.kdst_pk);
+  k_kron_scale<Real><<<cdiv(mp2, 256), 256, 0, st>>>(mp, w.ksym, w.kt1);
+  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt1, mp, w.kt0, mp, st, w.kdst_pk);
+  k_transpose<Real><<<tgrid, 256, 0, st>>>(mp, w.kt0, w.kt1);
+  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt1, mp, w.kt0, mp, st, w.kdst_pk);
+  k_kron_out<Real><<<cdiv(int64_t(nb) * nb, 256), 256, 0, st>>>(nb, mp, w.kt0, w.ksc, z);
 }
 
 // tile edge of the operator kernel: 16 (float, r <= 2), else 8 (LDS)
@@ -312,9 +432,21 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
       g, a.ws.f0, nullptr, a.gravity != 0.0 ? a.ws.fy : nullptr, a.gb, a.gdb, a.ws.f);
   k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
                                                              a.gdb, a.ws.dg);
-  k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.f, a.ws.dg, a.x, a.ws.r, a.ws.z, a.ws.p);
+  const bool kron = a.precond == 1;
+  if (kron) {
+    // d0 from the diagonal gather with alpha = 1 (f0 is free again)
+    k_gal_weights2<Real, R><<<cdiv(npts, 256), 256, 0, st>>>(g, a.gw, a.ws.f0);
+    k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.f0, nullptr, nullptr, a.gb,
+                                                               a.gdb, a.ws.ksc);
+    k_kron_scalevec<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, a.ws.dg, a.ws.ksc);
+  }
+  k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.f, kron ? nullptr : a.ws.dg, a.x, a.ws.r,
+                                                 a.ws.z, a.ws.p);
+  if (kron) kron_apply<Real>(a.ws, g.nb, a.ws.r, a.ws.z, st);
   k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.r, a.ws.z, a.ws.f, a.ws.f, a.ws.part);
   k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, 0, 4);
+  // p = z + b 0 = z
+  if (kron) k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, 0, 0, a.ws.z, a.ws.p);
 }
 
 // iters CG iterations; iteration it starts with rz in slot it & 1
@@ -329,8 +461,15 @@ static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hip
     k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, a.ws.p, a.ws.c, a.gb, a.gdb, a.ws.ap,
                                                          a.ws.part);
     k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, ntiles, a.ws.sc, 2, -1);
-    k_pcg_step1<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z, a.ws.p,
-                                                  a.ws.ap, a.ws.dg, a.ws.part);
+    if (a.precond == 1) {
+      k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z,
+                                                           a.ws.p, a.ws.ap, a.ws.dg, a.ws.part);
+      kron_apply<Real>(a.ws, g.nb, a.ws.r, a.ws.z, st);
+      k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.r, a.ws.z, a.ws.r, a.ws.r, a.ws.part);
+    } else {
+      k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z,
+                                                          a.ws.p, a.ws.ap, a.ws.dg, a.ws.part);
+    }
     k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, s_new, 3);
     k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, s_new, s_old, a.ws.z, a.ws.p);
   }

@@ -66,6 +66,12 @@ struct GalerkinWork {
   Real *c, *f0, *fy;              // w alpha, w q, -gravity w F_b at the Gauss points
   Real *f, *dg, *r, *z, *p, *ap;  // load, diagonal, CG vectors
   double *sc, *part;
+  // Kronecker preconditioner: mg = nb - 2 interior coefficients per axis,
+  // padded to mgp (a multiple of 64); ksc (nb^2) the diagonal scaling,
+  // kt0/kt1 (mgp^2) work arrays, ksym (2 mgp) the 1D mass and stiffness
+  // symbols, kdst (mgp^2, and packed) the orthonormal DST-I basis of size mg
+  int mg, mgp;
+  Real *ksc, *kt0, *kt1, *ksym, *kdst, *kdst_pk;
 };
 // partial sums a solve writes at most (operator tiles or dot-product blocks)
 int64_t galerkin_partials(const Geom& g);
@@ -75,6 +81,7 @@ struct GalerkinArgs {
   double mu_w, mu_g, nexp, rho_w, rho_g, gravity;
   Real* x;  // the solution (pressure coefficients; boundary coefficients 0)
   GalerkinWork<Real> ws;
+  int precond;  // 0 diagonal of S, 1 scaled Kronecker inverse
 };
 // fields at the Gauss points, load, diagonal; x = 0 and the first CG vectors
 template <typename Real>

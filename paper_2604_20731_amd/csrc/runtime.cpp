@@ -272,10 +272,10 @@ struct SolverBase {
   virtual crv_status project_host(double*) = 0;
   virtual crv_status substeps(double tau, int n) = 0;
   virtual crv_status sync() = 0;
-  virtual crv_status pressure_galerkin(int max_iters, double rtol, double* p, int* iters,
-                                       double* relres) = 0;
-  virtual crv_status step_galerkin(double dt, int max_iters, double rtol, int* iters,
-                                   double* relres) = 0;
+  virtual crv_status pressure_galerkin(int max_iters, double rtol, int precond, double* p,
+                                       int* iters, double* relres) = 0;
+  virtual crv_status step_galerkin(double dt, int max_iters, double rtol, int precond,
+                                   int* iters, double* relres) = 0;
 };
 
 template <typename Real>
@@ -586,14 +586,18 @@ struct Solver : SolverBase {
   // ---- IGA Galerkin pressure (the paper's direct-solver path, 2D) ----
   GalerkinWork<Real> gw{};
   void* gw_mem = nullptr;
-  hipGraphExec_t g_gal = nullptr;  // one captured chunk of CG iterations
+  hipGraphExec_t g_gal[2] = {nullptr, nullptr};  // a captured chunk of CG iterations per preconditioner
   crv_status galerkin_alloc() {
     if (gw_mem) return CRV_OK;
     const size_t npts = size_t(ipow(int64_t(g.ne) * (g.r + 1), 2)), ncf = size_t(g.nb) * g.nb;
     auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
     const size_t nparts = size_t(galerkin_partials(g));
-    const size_t bytes = 3 * up(npts * sizeof(Real)) + 6 * up(ncf * sizeof(Real)) +
-                         up(8 * sizeof(double)) + up(2 * nparts * sizeof(double));
+    gw.mg = g.nb - 2;
+    gw.mgp = (gw.mg + 63) / 64 * 64;
+    const size_t mp2 = size_t(gw.mgp) * gw.mgp;
+    const size_t bytes = 3 * up(npts * sizeof(Real)) + 7 * up(ncf * sizeof(Real)) +
+                         up(8 * sizeof(double)) + up(2 * nparts * sizeof(double)) +
+                         4 * up(mp2 * sizeof(Real)) + up(2 * size_t(gw.mgp) * sizeof(Real));
     CRV_HIP(hipMalloc(&gw_mem, bytes));
     Carve cv(gw_mem);
     gw.c = cv.take<Real>(npts);
@@ -607,24 +611,43 @@ struct Solver : SolverBase {
     gw.ap = cv.take<Real>(ncf);
     gw.sc = cv.take<double>(8);
     gw.part = cv.take<double>(2 * nparts);
+    gw.ksc = cv.take<Real>(ncf);
+    gw.kt0 = cv.take<Real>(mp2);
+    gw.kt1 = cv.take<Real>(mp2);
+    gw.kdst = cv.take<Real>(mp2);
+    gw.kdst_pk = cv.take<Real>(mp2);
+    gw.ksym = cv.take<Real>(2 * size_t(gw.mgp));
+    std::vector<double> dst, lam, sym;
+    dst_table(gw.mg, gw.mgp, dst, lam);
+    bspline_symbols(g.r, gw.mg, gw.mgp, sym);
+    crv_status s;
+    if ((s = upload(gw.kdst, dst.data(), dst.size()))) return s;
+    {
+      const std::vector<double> pk = pack_gemm_a(dst, gw.mgp, gw.mgp);
+      if ((s = upload(gw.kdst_pk, pk.data(), pk.size()))) return s;
+    }
+    if ((s = upload(gw.ksym, sym.data(), sym.size()))) return s;
+    CRV_HIP(hipStreamSynchronize(st));
     return CRV_OK;
   }
-  GalerkinArgs<Real> galerkin_args() {
+  GalerkinArgs<Real> galerkin_args(int precond) {
     return GalerkinArgs<Real>{b.s, b.perm, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
                               cfg.mu_w, cfg.mu_g, cfg.relperm_exp, cfg.rho_w, cfg.rho_g,
-                              cfg.gravity, b.p, gw};
+                              cfg.gravity, b.p, gw, precond};
   }
-  // S P = F for the current saturation into b.p by diagonally preconditioned
-  // CG from P = 0, until |r| <= rtol |F| (checked every 24 iterations) or
-  // max_iters.  Iterations alternate the slot of r.z, so every chunk but the
-  // last (which may be shorter) has an even length
-  crv_status pressure_galerkin(int max_iters, double rtol, double* p_out, int* iters_out,
-                               double* relres_out) override {
+  // S P = F for the current saturation into b.p by preconditioned CG from
+  // P = 0, until |r| <= rtol |F| (checked every 24 iterations) or max_iters.
+  // Iterations alternate the slot of r.z, so every chunk but the last (which
+  // may be shorter) has an even length
+  crv_status pressure_galerkin(int max_iters, double rtol, int precond, double* p_out,
+                               int* iters_out, double* relres_out) override {
     if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
     if (max_iters < 0 || !(rtol >= 0) || !std::isfinite(rtol)) return fail(CRV_EINVAL, "bad max_iters or rtol");
+    if (precond != CRV_PRECOND_JACOBI && precond != CRV_PRECOND_KRON)
+      return fail(CRV_EINVAL, "precond must be CRV_PRECOND_JACOBI or CRV_PRECOND_KRON");
     crv_status s = galerkin_alloc();
     if (s) return s;
-    const GalerkinArgs<Real> a = galerkin_args();
+    const GalerkinArgs<Real> a = galerkin_args(precond);
     launch_galerkin_setup<Real>(g, a, st);
     if ((s = check_launch())) return s;
     double sc[5] = {0, 0, 0, 0, 0};
@@ -638,13 +661,14 @@ struct Solver : SolverBase {
     double rel = ff > 0 ? 1.0 : 0.0;
     int done = 0;
     const int chunk = 24;  // even: each chunk starts with rz in slot 0
-    if (use_graphs() && !g_gal && ff > 0 && max_iters >= chunk) {
-      s = capture(&g_gal, [&] { launch_galerkin_iters<Real>(g, a, chunk, st); });
+    hipGraphExec_t& graph = g_gal[precond];
+    if (use_graphs() && !graph && ff > 0 && max_iters >= chunk) {
+      s = capture(&graph, [&] { launch_galerkin_iters<Real>(g, a, chunk, st); });
       if (s) return s;
     }
     while (ff > 0 && done < max_iters && rel > rtol) {
       const int k = std::min(chunk, max_iters - done);
-      if (g_gal && use_graphs() && k == chunk) CRV_HIP(hipGraphLaunch(g_gal, st));
+      if (graph && use_graphs() && k == chunk) CRV_HIP(hipGraphLaunch(graph, st));
       else launch_galerkin_iters<Real>(g, a, k, st);
       if ((s = check_launch())) return s;
       if ((s = read_sc())) return s;
@@ -659,7 +683,7 @@ struct Solver : SolverBase {
   }
   // the direct-solver algorithm's pass: substeps with the current pressure
   // coefficients, refresh, and the Galerkin pressure of the new saturation
-  crv_status step_galerkin(double dt, int max_iters, double rtol, int* iters,
+  crv_status step_galerkin(double dt, int max_iters, double rtol, int precond, int* iters,
                            double* relres) override {
     if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(CRV_EINVAL, "dt must be > 0");
@@ -670,11 +694,12 @@ struct Solver : SolverBase {
     refresh();
     if ((s = check_launch())) return s;
     if ((s = sync_and_check())) return s;
-    return pressure_galerkin(max_iters, rtol, nullptr, iters, relres);
+    return pressure_galerkin(max_iters, rtol, precond, nullptr, iters, relres);
   }
 
   ~Solver() override {
-    if (g_gal) (void)hipGraphExecDestroy(g_gal);
+    for (hipGraphExec_t& e : g_gal)
+      if (e) (void)hipGraphExecDestroy(e);
     if (gw_mem) (void)hipFree(gw_mem);
     if (g_train) (void)hipGraphExecDestroy(g_train);
     if (g_step) (void)hipGraphExecDestroy(g_step);
@@ -1041,16 +1066,16 @@ crv_status crv_pretrain_pressure(crv_ctx* c, int iters, double* final_loss) {
   return CRV_OK;
 }
 
-crv_status crv_pressure_galerkin(crv_ctx* c, int max_iters, double rtol, double* p_coefs,
-                                 int* iters, double* rel_residual) {
+crv_status crv_pressure_galerkin(crv_ctx* c, int max_iters, double rtol, int precond,
+                                 double* p_coefs, int* iters, double* rel_residual) {
   CRV_CTX(c);
-  return sv.pressure_galerkin(max_iters, rtol, p_coefs, iters, rel_residual);
+  return sv.pressure_galerkin(max_iters, rtol, precond, p_coefs, iters, rel_residual);
 }
 
-crv_status crv_step_galerkin(crv_ctx* c, double dt, int max_iters, double rtol, int* iters,
-                             double* rel_residual) {
+crv_status crv_step_galerkin(crv_ctx* c, double dt, int max_iters, double rtol, int precond,
+                             int* iters, double* rel_residual) {
   CRV_CTX(c);
-  return sv.step_galerkin(dt, max_iters, rtol, iters, rel_residual);
+  return sv.step_galerkin(dt, max_iters, rtol, precond, iters, rel_residual);
 }
 
 crv_status crv_train_async(crv_ctx* c, int iters) {

@@ -203,6 +203,39 @@ void dst_table(int m, int mp, std::vector<double>& s, std::vector<double>& lam) 
   }
 }
 
+// d-th derivative of the cardinal B-spline of degree p at x (truncated-power
+// form: sum_k (-1)^k C(p+1, k) (x-k)_+^(p-d) / (p-d)!)
+static double cardinal_bspline(int p, double x, int d) {
+  double s = 0.0, binom = 1.0;
+  for (int k = 0; k <= p + 1; ++k) {
+    if (x > k) s += ((k & 1) ? -binom : binom) * std::pow(x - k, p - d);
+    binom = binom * (p + 1 - k) / (k + 1);
+  }
+  double fact = 1.0;
+  for (int i = 2; i <= p - d; ++i) fact *= i;
+  return s / fact;
+}
+
+void bspline_symbols(int r, int m, int mp, std::vector<double>& sym) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> mt(r + 1), kt(r + 1);
+  for (int t = 0; t <= r; ++t) {
+    mt[t] = cardinal_bspline(2 * r + 1, r + 1 + t, 0);
+    kt[t] = -cardinal_bspline(2 * r + 1, r + 1 + t, 2);
+  }
+  sym.assign(size_t(2) * mp, 1.0);
+  for (int k = 0; k < m; ++k) {
+    const double th = double(k + 1) * pi / double(m + 1);
+    double ms = mt[0], ks = kt[0];
+    for (int t = 1; t <= r; ++t) {
+      ms += 2.0 * mt[t] * std::cos(t * th);
+      ks += 2.0 * kt[t] * std::cos(t * th);
+    }
+    sym[k] = ms;
+    sym[mp + k] = ks;
+  }
+}
+
 bool well_sources(const double* wells, int n_wells, int ne, int dim, double radius,
                   std::vector<double>& q_inj, std::vector<double>& q_prod, std::string& err) {
   const int n = ne + 1;

@@ -37,6 +37,13 @@ void gauss_tables(int ne, int r, std::vector<double>& gb, std::vector<double>& g
 // Orthonormal DST-I basis of size m, padded to mp x mp with zeros:
 // S(k, j) = sqrt(2/(m+1)) sin((k+1)(j+1) pi/(m+1)); lam[k] = 4 sin^2((k+1) pi/(2(m+1))).
 void dst_table(int m, int mp, std::vector<double>& s, std::vector<double>& lam);
+// Symbols of the uniform degree-r B-spline mass and stiffness (unit spacing)
+// at the DST-I frequencies theta_k = (k+1) pi/(m+1), k < m:
+//   m(theta) = M_0 + 2 sum_t M_t cos(t theta),  k(theta) likewise,
+// with M_t = N_{2r+1}(r+1+t), K_t = -N''_{2r+1}(r+1+t) the autocorrelations of
+// the cardinal B-spline N_r (support [0, r+1]) and of its derivative.
+// sym = (m_0 .. m_{mp-1}, k_0 .. k_{mp-1}), padded modes 1.
+void bspline_symbols(int r, int m, int mp, std::vector<double>& sym);
 // A (M x K row-major, M multiple of 32, K of 16) rearranged into the packed
 // operand order of the float32 32x32x2 matrix-core product: index
 // ((mb * K/16 + kc) * 64 + lane) * 8 + u holds A[32 mb + lane%32][16 kc + 2u + lane/32].

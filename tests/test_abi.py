@@ -105,6 +105,17 @@ def test_gravity_config_and_galerkin_argument_errors():
         c = crv.config(**bad)
         assert crv.LIB.crv_workspace_size(C.byref(c), C.byref(n)) == crv.CRV_EINVAL, bad
     it, rr = C.c_int(), C.c_double()
-    assert crv.LIB.crv_pressure_galerkin(None, 10, 1e-6, None, C.byref(it), C.byref(rr)) == crv.CRV_EINVAL
-    assert crv.LIB.crv_step_galerkin(None, 1e-3, 10, 1e-6, None, None) == crv.CRV_EINVAL
+    assert crv.LIB.crv_pressure_galerkin(None, 10, 1e-6, 1, None, C.byref(it),
+                                         C.byref(rr)) == crv.CRV_EINVAL
+    assert crv.LIB.crv_step_galerkin(None, 1e-3, 10, 1e-6, 1, None, None) == crv.CRV_EINVAL
     assert "context" in crv.LIB.crv_last_error().decode()
+
+
+def test_precond_constants_match_the_header():
+    """The binding's preconditioner codes are the header's CRV_PRECOND_*."""
+    import re
+    from pathlib import Path
+    text = (Path(__file__).resolve().parents[1] / "include" / "crv.h").read_text()
+    found = {m.group(1).lower(): int(m.group(2))
+             for m in re.finditer(r"#define CRV_PRECOND_(\w+) (\d+)", text)}
+    assert found == crv.PRECOND

@@ -1,5 +1,6 @@
 """The paper's direct-solver pressure path on the HIP side (matrix-free
-Galerkin operator, diagonally preconditioned CG; 2D) against the oracle's
+Galerkin operator, CG preconditioned by the diagonal of S or by the scaled
+Kronecker inverse; 2D) against the oracle's
 sparse direct solve of the same system (eq. 15-20; pinned on the CPU by an
 exactly reproduced polynomial pressure and the gravity load identity)."""
 import numpy as np
@@ -31,11 +32,12 @@ def _pair(prob, prec, grav, seed=3):
 @pytest.mark.parametrize("prec,rtol,tol", [("fp64", 1e-12, 1e-8), ("fp32", 1e-6, 1e-5)])
 @pytest.mark.parametrize("ne,r", [(32, 2), (24, 3), (40, 1), (64, 2)])
 @pytest.mark.parametrize("grav", [False, True])
-def test_galerkin_pressure_matches_direct_solve(prec, rtol, tol, ne, r, grav):
-    say("galerkin", prec, ne, r, grav)
+@pytest.mark.parametrize("precond", ["jacobi", "kron"])
+def test_galerkin_pressure_matches_direct_solve(prec, rtol, tol, ne, r, grav, precond):
+    say("galerkin", prec, ne, r, grav, precond)
     prob = problem("c1", n_elem=ne, degree=r)
     sc, orc = _pair(prob, prec, grav)
-    p, iters, rr = sc.pressure_galerkin(max_iters=20000, rtol=rtol)
+    p, iters, rr = sc.pressure_galerkin(max_iters=20000, rtol=rtol, precond=precond)
     pref = orc.galerkin_pressure()
     e = rel(p, pref.ravel())
     say(f"  iters {iters} |r|/|F| {rr:.2e} rel err {e:.2e}")
@@ -75,8 +77,9 @@ def test_galerkin_path_rejects_3d():
         sc.pressure_galerkin()
 
 
-def test_captured_cg_chunks_equal_eager_launches():
-    """The CG iterations replayed from a captured graph (chunks of 25, the
+@pytest.mark.parametrize("precond,min_iters", [("jacobi", 48), ("kron", 24)])
+def test_captured_cg_chunks_equal_eager_launches(precond, min_iters):
+    """The CG iterations replayed from a captured graph (chunks of 24, the
     host reading the residual between replays) give bitwise the result of
     the same iterations launched one by one."""
     import os
@@ -88,23 +91,29 @@ def test_captured_cg_chunks_equal_eager_launches():
     finally:
         del os.environ["CRV_NO_GRAPH"]
     for _ in range(2):  # the second solve replays the graph captured by the first
-        pg, ig, rg = sc_graph.pressure_galerkin(rtol=1e-7)
-        pe, ie, re = sc_eager.pressure_galerkin(rtol=1e-7)
+        pg, ig, rg = sc_graph.pressure_galerkin(rtol=1e-7, precond=precond)
+        pe, ie, re = sc_eager.pressure_galerkin(rtol=1e-7, precond=precond)
         assert ig == ie and rg == re and np.array_equal(pg, pe)
-        assert ig >= 50
+        assert ig >= min_iters
 
 
 @pytest.mark.timeout(600)
 def test_galerkin_at_the_benchmark_size():
     """The 512^2 workload the benchmark times (514^2 coefficients, FP32, rtol
-    1e-6) against the oracle's sparse LU of the same system: the same bound as
-    at the small sizes, 1e-5 (measured 8.4e-7)."""
+    1e-6) against the oracle's sparse LU of the same system, with both
+    preconditioners: the same bound as at the small sizes, 1e-5 (measured
+    8.4e-7 with the diagonal).  The Kronecker inverse's iteration count does
+    not grow with the mesh as the diagonal's does: well under half of it
+    here."""
     say("galerkin 512^2")
     prob = problem("b512")
     sc = scenario_for(prob, "fp32")
     orc = oracle_for(prob)
-    p, iters, rr = sc.pressure_galerkin(rtol=1e-6)
-    pref = orc.galerkin_pressure()
-    e = rel(p, pref.ravel())
-    say(f"  iters {iters} |r|/|F| {rr:.2e} rel err {e:.2e}")
-    assert rr <= 1e-6 and e < 1e-5
+    pref = orc.galerkin_pressure().ravel()
+    its = {}
+    for precond in ("jacobi", "kron"):
+        p, its[precond], rr = sc.pressure_galerkin(rtol=1e-6, precond=precond)
+        e = rel(p, pref)
+        say(f"  {precond}: iters {its[precond]} |r|/|F| {rr:.2e} rel err {e:.2e}")
+        assert rr <= 1e-6 and e < 1e-5
+    assert its["kron"] < 0.5 * its["jacobi"]
