@@ -195,9 +195,21 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   }
 }
 
-// ---- conjugate-gradient pieces; scalars live on the device (sc[]):
-//      0 and 1 rz of consecutive iterations (alternating), 2 pAp, 3 rr, 4 ff
+// ---- conjugate-gradient pieces.  Scalars on the device (sc[]): 0 and 1 the
+// r.z of consecutive iterations (alternating slots), 3 r.r, 4 F.F.  The
+// operator leaves one partial of p.Ap per tile in part, the update kernels
+// one (r.z, r.r) pair per block in part2; a kernel that needs such a sum adds
+// the partials itself, every block in the same fixed order, so all blocks
+// hold the same value and no reduction launch sits between the steps.
 constexpr int kDotBlocks = 256;
+
+// sum over i < np of part[2 i + j] (blocks of 256 threads; every block alike)
+__device__ inline double sum_pairs(const double* __restrict__ part, int np, int j,
+                                   double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[2 * i + j];
+  return block_sum_n<256>(s, red);
+}
 
 // fixed-order partial sums of a.b and (if c) c.d, double accumulation
 template <typename Real>
@@ -220,31 +232,40 @@ __global__ __launch_bounds__(256) void k_dot2_part(int64_t n, const Real* __rest
   }
 }
 
+// sc[slot1], sc[slot2] = the two sums of nparts pairs (set-up only)
 __global__ __launch_bounds__(256) void k_dot2_fin(const double* __restrict__ part, int nparts,
                                                   double* __restrict__ sc, int slot1, int slot2) {
   __shared__ double red[256];
-  double s1 = 0, s2 = 0;
-  for (int i = threadIdx.x; i < nparts; i += 256) {
-    s1 += part[2 * i];
-    s2 += part[2 * i + 1];
-  }
-  const double t1 = block_sum_n<256>(s1, red);
-  const double t2 = block_sum_n<256>(s2, red);
+  const double t1 = sum_pairs(part, nparts, 0, red);
+  const double t2 = sum_pairs(part, nparts, 1, red);
   if (threadIdx.x == 0) {
     sc[slot1] = t1;
-    if (slot2 >= 0) sc[slot2] = t2;
+    sc[slot2] = t2;
   }
 }
 
-// x = 0, r = F and z = r / d, p = z (dg given) or p = 0 (dg null: z comes
-// from the Kronecker preconditioner and p = z + b p then sets p = z)
 template <typename Real>
-__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const Real* __restrict__ f,
-                                                  const Real* __restrict__ dg, Real* __restrict__ x,
-                                                  Real* __restrict__ r, Real* __restrict__ z,
-                                                  Real* __restrict__ p) {
+__global__ __launch_bounds__(256) void k_zero(int64_t n, Real* __restrict__ a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i < n) a[i] = 0;
+}
+
+__device__ inline bool on_edge(int k, int l, int nb) {
+  return k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
+}
+
+// x = 0, r = F and either z = r / d, p = z (dg given) or p = 0 and the
+// Kronecker preconditioner's input t = ksc F on the interior (dg null; p = z
+// follows once z is known)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_pcg_init(int nb, int mp, const Real* __restrict__ f,
+                                                  const Real* __restrict__ dg,
+                                                  const Real* __restrict__ ksc,
+                                                  Real* __restrict__ x, Real* __restrict__ r,
+                                                  Real* __restrict__ z, Real* __restrict__ p,
+                                                  Real* __restrict__ t) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(nb) * nb) return;
   x[i] = 0;
   r[i] = f[i];
   if (dg) {
@@ -252,22 +273,26 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const Real* __restr
     p[i] = z[i];
   } else {
     p[i] = 0;
+    const int k = int(i % nb), l = int(i / nb);
+    if (!on_edge(k, l, nb)) t[int64_t(l - 1) * mp + k - 1] = ksc[i] * f[i];
   }
 }
 
-// a = rz / pAp (rz in slot s_rz): x += a p, r -= a Ap and, with JAC,
-// z = r / d and the block's parts of the new r.z and r.r (grid-stride,
-// kDotBlocks blocks); without JAC z and the parts are left alone
+// p.Ap from the operator's ntiles partials, a = rz / pAp (rz in slot s_rz):
+// x += a p, r -= a Ap, then
+//   JAC:  z = r / d and this block's (r.z, r.r) pair in part2;
+//   else: the Kronecker preconditioner's input t = ksc r on the interior
+// (grid-stride, kDotBlocks blocks of 256)
 template <typename Real, bool JAC>
-__global__ __launch_bounds__(256) void k_pcg_step1(int64_t n, const double* __restrict__ sc,
-                                                   int s_rz, Real* __restrict__ x,
-                                                   Real* __restrict__ r, Real* __restrict__ z,
-                                                   const Real* __restrict__ p,
-                                                   const Real* __restrict__ ap,
-                                                   const Real* __restrict__ dg,
-                                                   double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_pcg_step1(
+    int nb, int mp, const double* __restrict__ sc, int s_rz, const double* __restrict__ part,
+    int ntiles, Real* __restrict__ x, Real* __restrict__ r, Real* __restrict__ z,
+    const Real* __restrict__ p, const Real* __restrict__ ap, const Real* __restrict__ dg,
+    const Real* __restrict__ ksc, Real* __restrict__ t, double* __restrict__ part2) {
   __shared__ double red[256];
-  const Real a = sc[2] != 0.0 ? Real(sc[s_rz] / sc[2]) : Real(0);  // converged exactly: stay
+  const double pap = sum_pairs(part, ntiles, 0, red);
+  const Real a = pap != 0.0 ? Real(sc[s_rz] / pap) : Real(0);  // converged exactly: stay
+  const int64_t n = int64_t(nb) * nb;
   double s1 = 0, s2 = 0;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     x[i] += a * p[i];
@@ -278,25 +303,39 @@ __global__ __launch_bounds__(256) void k_pcg_step1(int64_t n, const double* __re
       z[i] = zi;
       s1 += double(ri) * double(zi);
       s2 += double(ri) * double(ri);
+    } else {
+      const int k = int(i % nb), l = int(i / nb);
+      if (!on_edge(k, l, nb)) t[int64_t(l - 1) * mp + k - 1] = ksc[i] * ri;
     }
   }
   if constexpr (!JAC) return;
   const double t1 = block_sum_n<256>(s1, red);
   const double t2 = block_sum_n<256>(s2, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = t1;
-    part[2 * blockIdx.x + 1] = t2;
+    part2[2 * blockIdx.x] = t1;
+    part2[2 * blockIdx.x + 1] = t2;
   }
 }
 
-// b = rz_new / rz_old: p = z + b p
+// rz_new and rr from the kDotBlocks pairs in part2; b = rz_new / sc[s_old]:
+// p = z + b p.  Block 0 stores rz_new in slot s_new (never s_old) and rr in
+// slot 3
 template <typename Real>
-__global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, const double* __restrict__ sc,
-                                                   int s_new, int s_old, const Real* __restrict__ z,
+__global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, double* __restrict__ sc, int s_new,
+                                                   int s_old, const double* __restrict__ part2,
+                                                   const Real* __restrict__ z,
                                                    Real* __restrict__ p) {
+  __shared__ double red[256];
+  const double rz = sum_pairs(part2, kDotBlocks, 0, red);
+  const double rr = sum_pairs(part2, kDotBlocks, 1, red);
+  const double old = sc[s_old];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[s_new] = rz;
+    sc[3] = rr;
+  }
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Real b = sc[s_old] != 0.0 ? Real(sc[s_new] / sc[s_old]) : Real(0);
+  const Real b = old != 0.0 ? Real(rz / old) : Real(0);
   p[i] = z[i] + b * p[i];
 }
 
@@ -308,9 +347,13 @@ __global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, const double* __re
 // symbol of the constant-coefficient operator K x M + M x K), and
 // D = sqrt(d0 / diag S) with d0 the diagonal of that operator, so that
 // D S D has the constant-coefficient diagonal.  D, V, L are symmetric and
-// positive (semi-)definite, so z = P r is a valid CG preconditioner.  The
-// four DST-I products run on the matrix cores; between them the interior
-// array is transposed once per axis change.
+// positive definite on the interior, so z = P r is a valid CG
+// preconditioner.  The input t0 = D r (row i along y; padding 0, written once)
+// comes from the update kernel; four DST-I products on the matrix cores,
+// whose epilogues transpose or divide by L:
+//   t1 = (V t0)^T,  t2 = (V t1) / L,  t1 = (V t2)^T,  t2 = V t1,
+// and the last kernel scatters z = D t2 with the (r.z, r.r) pairs.  The
+// padded rows and columns of every product are exactly 0 (V's are).
 
 // w at every Gauss point (the c of the constant-coefficient operator)
 template <typename Real, int R>
@@ -330,85 +373,44 @@ __global__ __launch_bounds__(256) void k_kron_scalevec(int nb, const Real* __res
                                                        Real* __restrict__ ksc) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(nb) * nb) return;
-  const int k = int(t % nb), l = int(t / nb);
-  const bool edge = k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
-  ksc[t] = edge ? Real(0) : Real(sqrt(ksc[t] / dg[t]));
+  ksc[t] = on_edge(int(t % nb), int(t / nb), nb) ? Real(0) : Real(sqrt(ksc[t] / dg[t]));
 }
 
-// t[i][j] = (ksc r) at coefficient (i + 1, j + 1) (row i along y), 0 in the
-// padding (i or j >= m)
+// z = ksc t on the interior, 0 on the boundary, and this block's (r.z, r.r)
+// pair in part2 (grid-stride, kDotBlocks blocks of 256)
 template <typename Real>
-__global__ __launch_bounds__(256) void k_kron_in(int nb, int m, int mp, const Real* __restrict__ r,
-                                                 const Real* __restrict__ ksc,
-                                                 Real* __restrict__ t) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= int64_t(mp) * mp) return;
-  const int i = int(e / mp), j = int(e % mp);
-  Real v = 0;
-  if (i < m && j < m) {
-    const int64_t c = int64_t(i + 1) * nb + j + 1;
-    v = ksc[c] * r[c];
+__global__ __launch_bounds__(256) void k_kron_out_dot(int nb, int mp, const Real* __restrict__ t,
+                                                      const Real* __restrict__ ksc,
+                                                      const Real* __restrict__ r,
+                                                      Real* __restrict__ z,
+                                                      double* __restrict__ part2) {
+  __shared__ double red[256];
+  const int64_t n = int64_t(nb) * nb;
+  double s1 = 0, s2 = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int k = int(i % nb), l = int(i / nb);
+    const Real zi = on_edge(k, l, nb) ? Real(0) : ksc[i] * t[int64_t(l - 1) * mp + k - 1];
+    const Real ri = r[i];
+    z[i] = zi;
+    s1 += double(ri) * double(zi);
+    s2 += double(ri) * double(ri);
   }
-  t[e] = v;
+  const double t1 = block_sum_n<256>(s1, red);
+  const double t2 = block_sum_n<256>(s2, red);
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = t1;
+    part2[2 * blockIdx.x + 1] = t2;
+  }
 }
 
-// z = ksc t on the interior (the inverse of k_kron_in's layout), 0 on the
-// boundary coefficients
+// t0 -> t2 = (V x V) L^-1 (V x V) t0 (the four products)
 template <typename Real>
-__global__ __launch_bounds__(256) void k_kron_out(int nb, int mp, const Real* __restrict__ t,
-                                                  const Real* __restrict__ ksc,
-                                                  Real* __restrict__ z) {
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= int64_t(nb) * nb) return;
-  const int k = int(c % nb), l = int(c / nb);
-  const bool edge = k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
-  z[c] = edge ? Real(0) : ksc[c] * t[int64_t(l - 1) * mp + k - 1];
-}
-
-// t[i][j] /= k_i m_j + m_i k_j with sym = (m_0 .. m_mp-1, k_0 .. k_mp-1)
-// (padded modes carry m = k = 1 and zero values)
-template <typename Real>
-__global__ __launch_bounds__(256) void k_kron_scale(int mp, const Real* __restrict__ sym,
-                                                    Real* __restrict__ t) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= int64_t(mp) * mp) return;
-  const int i = int(e / mp), j = int(e % mp);
-  t[e] /= sym[mp + i] * sym[j] + sym[i] * sym[mp + j];
-}
-
-// out = in^T for an mp x mp array (mp a multiple of 32): 32 x 32 tiles
-// through LDS, 32 x 8 threads, coalesced on both sides
-template <typename Real>
-__global__ __launch_bounds__(256) void k_transpose(int mp, const Real* __restrict__ in,
-                                                   Real* __restrict__ out) {
-  __shared__ Real tile[32][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-#pragma unroll
-  for (int k = 0; k < 32; k += 8) tile[ty + k][tx] = in[int64_t(r0 + ty + k) * mp + c0 + tx];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 32; k += 8) out[int64_t(c0 + ty + k) * mp + r0 + tx] = tile[tx][ty + k];
-}
-
-// z = P r (r and z nb^2 coefficient arrays, boundary 0); the DST-I basis is
-// symmetric, so every product is V times an mp x mp array: along y, then
-// (transposed) along x, scale, along x, (transposed back) along y
-template <typename Real>
-static void kron_apply(const GalerkinWork<Real>& w, int nb, const Real* r, Real* z,
-                       hipStream_t st) {
-  const int m = w.mg, mp = w.mgp;
-  const int64_t mp2 = int64_t(mp) * mp;
-  const dim3 tgrid(mp / 32, mp / 32);
-  k_kron_in<Real><<<cdiv(mp2, 256), 256, 0, st>>>(nb, m, mp, r, w.ksc, w.kt0);
-  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt0, mp, w.kt1, mp, st, w.kdst_pk);
-  k_transpose<Real><<<tgrid, 256, 0, st>>>(mp, w.kt1, w.kt0);
-  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt0, mp, w.kt1, mp, st, w.kdst_pk);
-  k_kron_scale<Real><<<cdiv(mp2, 256), 256, 0, st>>>(mp, w.ksym, w.kt1);
-  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt1, mp, w.kt0, mp, st, w.kdst_pk);
-  k_transpose<Real><<<tgrid, 256, 0, st>>>(mp, w.kt0, w.kt1);
-  launch_gemm<Real>(mp, mp, mp, w.kdst, mp, w.kt1, mp, w.kt0, mp, st, w.kdst_pk);
-  k_kron_out<Real><<<cdiv(int64_t(nb) * nb, 256), 256, 0, st>>>(nb, mp, w.kt0, w.ksc, z);
+static void kron_products(const GalerkinWork<Real>& w, hipStream_t st) {
+  const int mp = w.mgp;
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt0, w.kt1, 1, w.ksym, st, w.kdst_pk);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 2, w.ksym, st, w.kdst_pk);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt2, w.kt1, 1, w.ksym, st, w.kdst_pk);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 0, w.ksym, st, w.kdst_pk);
 }
 
 // tile edge of the operator kernel: 16 (float, r <= 2), else 8 (LDS)
@@ -432,46 +434,55 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
       g, a.ws.f0, nullptr, a.gravity != 0.0 ? a.ws.fy : nullptr, a.gb, a.gdb, a.ws.f);
   k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
                                                              a.gdb, a.ws.dg);
-  const bool kron = a.precond == 1;
-  if (kron) {
+  const GalerkinWork<Real>& w = a.ws;
+  if (a.precond == 1) {
+    const int64_t mp2 = int64_t(w.mgp) * w.mgp;
     // d0 from the diagonal gather with alpha = 1 (f0 is free again)
-    k_gal_weights2<Real, R><<<cdiv(npts, 256), 256, 0, st>>>(g, a.gw, a.ws.f0);
-    k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.f0, nullptr, nullptr, a.gb,
-                                                               a.gdb, a.ws.ksc);
-    k_kron_scalevec<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, a.ws.dg, a.ws.ksc);
+    k_gal_weights2<Real, R><<<cdiv(npts, 256), 256, 0, st>>>(g, a.gw, w.f0);
+    k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, w.f0, nullptr, nullptr, a.gb,
+                                                               a.gdb, w.ksc);
+    k_kron_scalevec<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, w.dg, w.ksc);
+    k_zero<Real><<<cdiv(mp2, 256), 256, 0, st>>>(mp2, w.kt0);
+    k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, w.mgp, w.f, nullptr, w.ksc, a.x, w.r,
+                                                   w.z, w.p, w.kt0);
+    kron_products<Real>(w, st);
+    k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z, w.part2);
+    k_dot2_fin<<<1, 256, 0, st>>>(w.part2, kDotBlocks, w.sc, 0, 4);  // r.z, F.F (r = F)
+    // p = z + b 0 = z (slot 4 as the old value: read only, never written here)
+    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, 0, 4, w.part2, w.z, w.p);
+  } else {
+    k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, 0, w.f, w.dg, nullptr, a.x, w.r, w.z,
+                                                   w.p, nullptr);
+    k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, w.r, w.z, w.f, w.f, w.part2);
+    k_dot2_fin<<<1, 256, 0, st>>>(w.part2, kDotBlocks, w.sc, 0, 4);
   }
-  k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.f, kron ? nullptr : a.ws.dg, a.x, a.ws.r,
-                                                 a.ws.z, a.ws.p);
-  if (kron) kron_apply<Real>(a.ws, g.nb, a.ws.r, a.ws.z, st);
-  k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.r, a.ws.z, a.ws.f, a.ws.f, a.ws.part);
-  k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, 0, 4);
-  // p = z + b 0 = z
-  if (kron) k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, 0, 0, a.ws.z, a.ws.p);
 }
 
-// iters CG iterations; iteration it starts with rz in slot it & 1
+// iters CG iterations; iteration it starts with rz in slot it & 1.  Launches
+// per iteration: operator, update, [4 products, scatter + dots], p update
 template <typename Real, int R>
 static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st) {
   constexpr int TC = gal_tc<Real, R>();
+  const GalerkinWork<Real>& w = a.ws;
   const int64_t n = int64_t(g.nb) * g.nb;
   const dim3 tiles(cdiv(g.nb, TC), cdiv(g.nb, TC));
   const int ntiles = int(tiles.x * tiles.y);
   for (int it = 0; it < iters; ++it) {
     const int s_old = it & 1, s_new = s_old ^ 1;
-    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, a.ws.p, a.ws.c, a.gb, a.gdb, a.ws.ap,
-                                                         a.ws.part);
-    k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, ntiles, a.ws.sc, 2, -1);
+    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.p, w.c, a.gb, a.gdb, w.ap, w.part);
     if (a.precond == 1) {
-      k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z,
-                                                           a.ws.p, a.ws.ap, a.ws.dg, a.ws.part);
-      kron_apply<Real>(a.ws, g.nb, a.ws.r, a.ws.z, st);
-      k_dot2_part<Real><<<kDotBlocks, 256, 0, st>>>(n, a.ws.r, a.ws.z, a.ws.r, a.ws.r, a.ws.part);
+      k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.sc, s_old, w.part,
+                                                           ntiles, a.x, w.r, w.z, w.p, w.ap,
+                                                           w.dg, w.ksc, w.kt0, w.part2);
+      kron_products<Real>(w, st);
+      k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z,
+                                                       w.part2);
     } else {
-      k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(n, a.ws.sc, s_old, a.x, a.ws.r, a.ws.z,
-                                                          a.ws.p, a.ws.ap, a.ws.dg, a.ws.part);
+      k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(g.nb, 0, w.sc, s_old, w.part, ntiles,
+                                                          a.x, w.r, w.z, w.p, w.ap, w.dg,
+                                                          nullptr, nullptr, w.part2);
     }
-    k_dot2_fin<<<1, 256, 0, st>>>(a.ws.part, kDotBlocks, a.ws.sc, s_new, 3);
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, a.ws.sc, s_new, s_old, a.ws.z, a.ws.p);
+    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, s_new, s_old, w.part2, w.z, w.p);
   }
 }
 

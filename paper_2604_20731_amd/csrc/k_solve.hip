@@ -507,11 +507,14 @@ void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_str
 // LDS, 4x4 outputs per thread.  blockIdx.z selects one product of a batch
 // that shares A (B and C advance by sb and sc).
 // ---------------------------------------------------------------------------
-template <typename Real>
+// EPI (this kernel and k_gemm_pa_f32): 0 stores C; 1 stores C^T (square C);
+// 2 stores C_ij / (sym[M+i] sym[j] + sym[i] sym[M+j]) (square C; the
+// Kronecker symbol of the Galerkin preconditioner)
+template <typename Real, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* __restrict__ A,
                                               int lda, const Real* __restrict__ B, int ldb,
                                               int64_t sb, Real* __restrict__ C, int ldc,
-                                              int64_t sc) {
+                                              int64_t sc, const Real* __restrict__ sym) {
   B += int64_t(blockIdx.z) * sb;
   C += int64_t(blockIdx.z) * sc;
   __shared__ Real As[16][64 + 4];
@@ -548,7 +551,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* _
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) C[int64_t(m0 + ty * 4 + i) * ldc + n0 + tx * 4 + j] = acc[i][j];
+    for (int j = 0; j < 4; ++j) {
+      const int gi = m0 + ty * 4 + i, gj = n0 + tx * 4 + j;
+      if constexpr (EPI == 1) {
+        C[int64_t(gj) * ldc + gi] = acc[i][j];
+      } else if constexpr (EPI == 2) {
+        C[int64_t(gi) * ldc + gj] = acc[i][j] / (sym[M + gi] * sym[gj] + sym[gi] * sym[M + gj]);
+      } else {
+        C[int64_t(gi) * ldc + gj] = acc[i][j];
+      }
+    }
 }
 
 // float32 C = A B on the matrix cores (v_mfma_f32_32x32x2f32): one 32x32
@@ -601,11 +613,12 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
 // consecutive floats, so every A load of a wave is one contiguous 2 KB read.
 // One 32x32 output tile per block; its NW waves split K into NW contiguous
 // ranges and the partial tiles are summed in a fixed order through LDS.
+template <int EPI>
 __global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
                                                      const float* __restrict__ Af,
                                                      const float* __restrict__ B, int ldb,
                                                      int64_t sb, float* __restrict__ C, int ldc,
-                                                     int64_t sc) {
+                                                     int64_t sc, const float* __restrict__ sym) {
   B += int64_t(blockIdx.z) * sb;
   C += int64_t(blockIdx.z) * sc;
   __shared__ float part[8][32 * 33];
@@ -632,20 +645,29 @@ __global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
   for (int i = 0; i < 16; ++i) part[w][(8 * (i >> 2) + 4 * g + (i & 3)) * 33 + r] = acc[i];
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
-    const int row = e >> 5, col = e & 31;
+    // the transposed store walks the tile by columns, so both stores are
+    // contiguous along the lanes
+    const int row = EPI == 1 ? (e & 31) : (e >> 5), col = EPI == 1 ? (e >> 5) : (e & 31);
     float v = part[0][row * 33 + col];
     for (int k = 1; k < nw; ++k) v += part[k][row * 33 + col];
-    C[int64_t(mb * 32 + row) * ldc + n0 + col] = v;
+    const int gi = mb * 32 + row, gj = n0 + col;
+    if constexpr (EPI == 1) {
+      C[int64_t(gj) * ldc + gi] = v;
+    } else if constexpr (EPI == 2) {
+      C[int64_t(gi) * ldc + gj] = v / (sym[M + gi] * sym[gj] + sym[gi] * sym[M + gj]);
+    } else {
+      C[int64_t(gi) * ldc + gj] = v;
+    }
   }
 }
 
-template <typename Real>
-void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
-                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
-                         const Real* a_packed) {
+template <typename Real, int EPI>
+static void gemm_dispatch(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
+                          int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
+                          const Real* a_packed, const Real* sym) {
   if (batch <= 0) return;
   if constexpr (sizeof(Real) == 4) {
-    if (a_packed) {
+    if (EPI != 0 || a_packed) {  // epilogues: callers always pass the packed operand
       // K split over nw waves (the largest divisor of K/64 up to 8), so that
       // every wave's range is a multiple of 16
       const int units = K / 64;
@@ -656,7 +678,7 @@ void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real
           break;
         }
       dim3 grid(N / 32, M / 32, batch);
-      k_gemm_pa_f32<<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc);
+      k_gemm_pa_f32<EPI><<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc, sym);
       return;
     }
     // dims are multiples of 64, so K/4 is a multiple of 16
@@ -664,8 +686,24 @@ void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real
     k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
   } else {
     dim3 grid(N / 64, M / 64, batch);
-    k_gemm<Real><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
+    k_gemm<Real, EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, sym);
   }
+}
+
+template <typename Real>
+void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
+                         int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
+                         const Real* a_packed) {
+  gemm_dispatch<Real, 0>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, batch, st, a_packed, nullptr);
+}
+
+template <typename Real>
+void launch_gemm_sq_epi(int M, const Real* A, const Real* B, Real* C, int epi, const Real* sym,
+                        hipStream_t st, const Real* a_packed) {
+  if (sizeof(Real) == 4 && !a_packed) return;  // float epilogues run on the packed kernel only
+  if (epi == 1) gemm_dispatch<Real, 1>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
+  else if (epi == 2) gemm_dispatch<Real, 2>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
+  else gemm_dispatch<Real, 0>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
 }
 
 template <typename Real>
@@ -682,7 +720,9 @@ void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int
   template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t, \
                                const R*);                                                     \
   template void launch_gemm_batched<R>(int, int, int, const R*, int, const R*, int, int64_t, R*, \
-                                       int, int64_t, int, hipStream_t, const R*);
+                                       int, int64_t, int, hipStream_t, const R*);                \
+  template void launch_gemm_sq_epi<R>(int, const R*, const R*, R*, int, const R*, hipStream_t,  \
+                                      const R*);
 CRV_INST(float)
 CRV_INST(double)
 

@@ -65,13 +65,13 @@ template <typename Real>
 struct GalerkinWork {
   Real *c, *f0, *fy;              // w alpha, w q, -gravity w F_b at the Gauss points
   Real *f, *dg, *r, *z, *p, *ap;  // load, diagonal, CG vectors
-  double *sc, *part;
+  double *sc, *part, *part2;       // scalars, operator tile partials, update-block pairs
   // Kronecker preconditioner: mg = nb - 2 interior coefficients per axis,
   // padded to mgp (a multiple of 64); ksc (nb^2) the diagonal scaling,
-  // kt0/kt1 (mgp^2) work arrays, ksym (2 mgp) the 1D mass and stiffness
+  // kt0..kt2 (mgp^2) work arrays, ksym (2 mgp) the 1D mass and stiffness
   // symbols, kdst (mgp^2, and packed) the orthonormal DST-I basis of size mg
   int mg, mgp;
-  Real *ksc, *kt0, *kt1, *ksym, *kdst, *kdst_pk;
+  Real *ksc, *kt0, *kt1, *kt2, *ksym, *kdst, *kdst_pk;
 };
 // partial sums a solve writes at most (operator tiles or dot-product blocks)
 int64_t galerkin_partials(const Geom& g);
@@ -140,6 +140,14 @@ template <typename Real>
 void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
                          int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
                          const Real* a_packed = nullptr);
+
+// C = A B for square M x M operands (M a multiple of 64, leading dimensions M)
+// with an epilogue: epi 0 stores C, 1 stores C^T, 2 stores
+// C_ij / (sym[M+i] sym[j] + sym[i] sym[M+j]).  float needs a_packed (the
+// call does nothing without it); double ignores it.
+template <typename Real>
+void launch_gemm_sq_epi(int M, const Real* A, const Real* B, Real* C, int epi, const Real* sym,
+                        hipStream_t st, const Real* a_packed);
 
 // ---- network (k_mlp.hip) ---------------------------------------------------
 struct MlpShape {

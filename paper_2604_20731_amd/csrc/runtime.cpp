@@ -596,8 +596,8 @@ struct Solver : SolverBase {
     gw.mgp = (gw.mg + 63) / 64 * 64;
     const size_t mp2 = size_t(gw.mgp) * gw.mgp;
     const size_t bytes = 3 * up(npts * sizeof(Real)) + 7 * up(ncf * sizeof(Real)) +
-                         up(8 * sizeof(double)) + up(2 * nparts * sizeof(double)) +
-                         4 * up(mp2 * sizeof(Real)) + up(2 * size_t(gw.mgp) * sizeof(Real));
+                         up(8 * sizeof(double)) + 2 * up(2 * nparts * sizeof(double)) +
+                         5 * up(mp2 * sizeof(Real)) + up(2 * size_t(gw.mgp) * sizeof(Real));
     CRV_HIP(hipMalloc(&gw_mem, bytes));
     Carve cv(gw_mem);
     gw.c = cv.take<Real>(npts);
@@ -611,9 +611,11 @@ struct Solver : SolverBase {
     gw.ap = cv.take<Real>(ncf);
     gw.sc = cv.take<double>(8);
     gw.part = cv.take<double>(2 * nparts);
+    gw.part2 = cv.take<double>(2 * nparts);
     gw.ksc = cv.take<Real>(ncf);
     gw.kt0 = cv.take<Real>(mp2);
     gw.kt1 = cv.take<Real>(mp2);
+    gw.kt2 = cv.take<Real>(mp2);
     gw.kdst = cv.take<Real>(mp2);
     gw.kdst_pk = cv.take<Real>(mp2);
     gw.ksym = cv.take<Real>(2 * size_t(gw.mgp));
