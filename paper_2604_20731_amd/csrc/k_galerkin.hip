@@ -105,7 +105,16 @@ __global__ __launch_bounds__(256) void k_gal_gather2(Geom g, const Real* __restr
 }
 
 // y = S x on a TC x TC tile of coefficients per block (boundary coefficients
-// 0); part[2 b] = the tile's share of x . y, part[2 b + 1] = 0
+// 0); part[2 b] = the tile's share of x . y, part[2 b + 1] = 0.  The block
+// stages the coefficients its TE x TE elements touch and the 1D basis tables
+// of those elements in LDS, then works by sum factorisation (one axis at a
+// time, no atomics, fixed summation order):
+//   Tx = (d_x B) X, Tv = B X along x            [coefficient rows x Gauss x]
+//   Fx = c (B Tx), Fy = c ((d_y B) Tv) along y  [Gauss y x Gauss x]
+//   Ux = B Fx, Uy = (d_y B) Fy along y          [tile rows x Gauss x]
+//   y = (d_x B) Ux + B Uy along x               [tile rows x tile columns]
+// with c = w alpha at the Gauss points.  Tables and fluxes of elements
+// outside the mesh are 0, so every sum runs over its full local range.
 template <typename Real, int R, int TC>
 __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __restrict__ x,
                                                       const Real* __restrict__ c,
@@ -114,49 +123,93 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
                                                       Real* __restrict__ y,
                                                       double* __restrict__ part) {
   constexpr int NG = R + 1;
-  constexpr int TE = TC + R;       // elements per tile and axis
-  constexpr int TCO = TC + 2 * R;  // coefficients those elements touch
-  constexpr int GP = TE * NG;      // Gauss points per axis
+  constexpr int NT = NG * (R + 1);  // table entries per element
+  constexpr int TE = TC + R;        // elements per tile and axis
+  constexpr int TCO = TC + 2 * R;   // coefficients those elements touch
+  constexpr int GP = TE * NG;       // Gauss points per axis
+  constexpr int NTH = TC * TC;
+  constexpr int NW1 = 2 * TCO * GP, NW2 = 2 * TC * GP;  // Tx/Tv, then Ux/Uy
   __shared__ Real sX[TCO * TCO], sFx[GP * GP], sFy[GP * GP];
-  __shared__ double red[TC * TC];
+  __shared__ Real sW[NW1 > NW2 ? NW1 : NW2];
+  __shared__ Real sB[4][TE * NT];  // B and d B along x, then along y
+  __shared__ double red[NTH];
   const int tid = threadIdx.x;
   const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC;
   const int c0x = k0 - R, c0y = l0 - R;
   const int nb = g.nb, ne = g.ne, ng = ne * NG;
-  for (int t = tid; t < TCO * TCO; t += TC * TC) {
+  for (int t = tid; t < TCO * TCO; t += NTH) {
     const int a = c0x + t % TCO, bb = c0y + t / TCO;
     sX[t] = (a >= 0 && a < nb && bb >= 0 && bb < nb) ? x[int64_t(bb) * nb + a] : Real(0);
   }
+  for (int t = tid; t < TE * NT; t += NTH) {
+    const int el = t / NT, r = t % NT;
+    const int ex = c0x + el, ey = c0y + el;
+    const bool okx = ex >= 0 && ex < ne, oky = ey >= 0 && ey < ne;
+    sB[0][t] = okx ? gb[int64_t(ex) * NT + r] : Real(0);
+    sB[1][t] = okx ? gdb[int64_t(ex) * NT + r] : Real(0);
+    sB[2][t] = oky ? gb[int64_t(ey) * NT + r] : Real(0);
+    sB[3][t] = oky ? gdb[int64_t(ey) * NT + r] : Real(0);
+  }
   __syncthreads();
-  for (int t = tid; t < GP * GP; t += TC * TC) {
+  Real* sTx = sW;
+  Real* sTv = sW + TCO * GP;
+  for (int t = tid; t < TCO * GP; t += NTH) {
+    const int row = t / GP, gxl = t % GP, exl = gxl / NG, gx = gxl % NG;
+    const Real* xr = sX + row * TCO + exl;
+    const Real* bx = sB[0] + exl * NT + gx * (R + 1);
+    const Real* dbx = sB[1] + exl * NT + gx * (R + 1);
+    Real tx = 0, tv = 0;
+#pragma unroll
+    for (int a = 0; a <= R; ++a) {
+      tx += dbx[a] * xr[a];
+      tv += bx[a] * xr[a];
+    }
+    sTx[t] = tx;
+    sTv[t] = tv;
+  }
+  __syncthreads();
+  for (int t = tid; t < GP * GP; t += NTH) {
     const int gxl = t % GP, gyl = t / GP;
-    const int exl = gxl / NG, gx = gxl % NG, eyl = gyl / NG, gy = gyl % NG;
+    const int exl = gxl / NG, eyl = gyl / NG, gy = gyl % NG;
     const int ex = c0x + exl, ey = c0y + eyl;
     Real fx = 0, fy = 0;
     if (ex >= 0 && ex < ne && ey >= 0 && ey < ne) {
-      const Real* bx = gb + (int64_t(ex) * NG + gx) * (R + 1);
-      const Real* dbx = gdb + (int64_t(ex) * NG + gx) * (R + 1);
-      const Real* by = gb + (int64_t(ey) * NG + gy) * (R + 1);
-      const Real* dby = gdb + (int64_t(ey) * NG + gy) * (R + 1);
+      const Real* by = sB[2] + eyl * NT + gy * (R + 1);
+      const Real* dby = sB[3] + eyl * NT + gy * (R + 1);
       Real px = 0, py = 0;
 #pragma unroll
       for (int b = 0; b <= R; ++b) {
-        Real rx = 0, rv = 0;
-#pragma unroll
-        for (int a = 0; a <= R; ++a) {
-          const Real v = sX[(eyl + b) * TCO + exl + a];
-          rx += dbx[a] * v;
-          rv += bx[a] * v;
-        }
-        px += by[b] * rx;
-        py += dby[b] * rv;
+        px += by[b] * sTx[(eyl + b) * GP + gxl];
+        py += dby[b] * sTv[(eyl + b) * GP + gxl];
       }
-      const Real cc = c[int64_t(ey * NG + gy) * ng + ex * NG + gx];
+      const Real cc = c[int64_t(ey * NG + gy) * ng + ex * NG + gxl % NG];
       fx = cc * px;
       fy = cc * py;
     }
     sFx[t] = fx;
     sFy[t] = fy;
+  }
+  __syncthreads();
+  // tile row ly (coefficient l0 + ly) meets local elements ly .. ly + R, as
+  // basis function R - j of element ly + j
+  Real* sUx = sW;
+  Real* sUy = sW + TC * GP;
+  for (int t = tid; t < TC * GP; t += NTH) {
+    const int ly = t / GP, gxl = t % GP;
+    Real ux = 0, uy = 0;
+#pragma unroll
+    for (int j = 0; j <= R; ++j) {
+      const int eyl = ly + j;
+#pragma unroll
+      for (int gy = 0; gy < NG; ++gy) {
+        const int tb = eyl * NT + gy * (R + 1) + R - j;
+        const int f = (eyl * NG + gy) * GP + gxl;
+        ux += sB[2][tb] * sFx[f];
+        uy += sB[3][tb] * sFy[f];
+      }
+    }
+    sUx[t] = ux;
+    sUy[t] = uy;
   }
   __syncthreads();
   const int tx = tid % TC, ty = tid / TC;
@@ -165,22 +218,14 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   if (k < nb && l < nb) {
     Real acc = 0;
     if (k > 0 && l > 0 && k < nb - 1 && l < nb - 1) {
-      for (int ey = max(l - R, 0); ey <= min(l, ne - 1); ++ey) {
-        const int bb = l - ey, eyl = ey - c0y;
-        for (int ex = max(k - R, 0); ex <= min(k, ne - 1); ++ex) {
-          const int a = k - ex, exl = ex - c0x;
 #pragma unroll
-          for (int gy = 0; gy < NG; ++gy) {
-            const Real by = gb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
-            const Real dby = gdb[(int64_t(ey) * NG + gy) * (R + 1) + bb];
+      for (int j = 0; j <= R; ++j) {
+        const int exl = tx + j;
 #pragma unroll
-            for (int gx = 0; gx < NG; ++gx) {
-              const Real bx = gb[(int64_t(ex) * NG + gx) * (R + 1) + a];
-              const Real dbx = gdb[(int64_t(ex) * NG + gx) * (R + 1) + a];
-              const int t = (eyl * NG + gy) * GP + exl * NG + gx;
-              acc += dbx * by * sFx[t] + bx * dby * sFy[t];
-            }
-          }
+        for (int gx = 0; gx < NG; ++gx) {
+          const int tb = exl * NT + gx * (R + 1) + R - j;
+          const int u = ty * GP + exl * NG + gx;
+          acc += sB[1][tb] * sUx[u] + sB[0][tb] * sUy[u];
         }
       }
     }
