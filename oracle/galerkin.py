@@ -90,6 +90,28 @@ def solve(space: Space, alpha_g: np.ndarray, f: np.ndarray) -> np.ndarray:
     return out.reshape((space.nb,) * space.dim)
 
 
+def apply_stiffness(space: Space, alpha_g: np.ndarray, coefs: np.ndarray,
+                    absolute: bool = False) -> np.ndarray:
+    """S P in 2D without assembling S, one axis at a time (eq. 18):
+        S P = B^T (c * (B P D^T)) D + D^T (c * (D P B^T)) B,
+    B, D the 1D basis and derivative tables at the Gauss points, c = w alpha
+    (arrays y-major, x fastest).  absolute: the same with |B|, |D| and |P|,
+    an entrywise upper bound of |S| |P| (c > 0), for backward errors at sizes
+    where the assembled S does not fit."""
+    assert space.dim == 2
+    b, d, p = space.bg, space.dbg, np.asarray(coefs).reshape(space.nb, space.nb)
+    if absolute:
+        b, d, p = np.abs(b), np.abs(d), np.abs(p)
+    b, d = sp.csr_matrix(b), sp.csr_matrix(d)  # r+1 entries per row
+    c = np.multiply.outer(space.wg, space.wg) * alpha_g.reshape(len(space.wg), len(space.wg))
+
+    def term(ty, tx):  # ty^T (c * (ty P tx^T)) tx
+        g = np.asarray(tx @ np.asarray(ty @ p).T).T
+        return np.asarray(tx.T @ np.asarray(ty.T @ (c * g)).T).T
+
+    return term(b, d) + term(d, b)
+
+
 def fields_at_gauss(space: Space, s_coefs, perm, mu_w, mu_g, n_exp, rho_w=0.0, rho_g=0.0):
     """alpha and the buoyancy flux at the Gauss points from the saturation
     spline and the Q1-interpolated nodal permeability."""

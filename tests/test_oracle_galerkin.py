@@ -11,7 +11,9 @@ against what the mathematics fixes:
   by parts, v = 0 on the boundary), so both give the same pressure; a
   constant F_b gives no load on the interior coefficients;
 * the whole path (fields from S and nodal K, sources from the nodes) leaves
-  a residual of round-off size in the assembled interior system.
+  a residual of round-off size in the assembled interior system;
+* the axis-by-axis product S P equals the assembled S times P, and its
+  absolute form bounds |S| |P| entrywise.
 """
 import numpy as np
 
@@ -99,3 +101,18 @@ def test_direct_solver_algorithm_step():
     assert np.max(np.abs(o.s - s0)) > 1e-8
     assert np.max(np.abs(p1 - p0)) > 0
     assert np.all(p1[~galerkin.interior_mask(o.space)] == 0.0)
+
+
+def test_separable_product_equals_assembled_stiffness():
+    rng = np.random.default_rng(7)
+    for ne, r in ((6, 1), (7, 2), (5, 3)):
+        sp = Space(ne, r, 2)
+        ng = len(sp.wg)
+        alpha = rng.uniform(0.1, 3.0, ng * ng)
+        p = rng.standard_normal((sp.nb, sp.nb))
+        s = galerkin.stiffness(sp, alpha)
+        sp_p = galerkin.apply_stiffness(sp, alpha, p)
+        assert np.abs(sp_p.ravel() - s @ p.ravel()).max() <= 1e-13 * np.abs(s @ p.ravel()).max()
+        bound = galerkin.apply_stiffness(sp, alpha, p, absolute=True).ravel()
+        exact = abs(s) @ np.abs(p.ravel())
+        assert np.all(bound >= exact * (1 - 1e-13))
