@@ -159,8 +159,9 @@ crv_status crv_sync(crv_ctx* ctx);
  * grad B, F = int q B + int (g F_b) . grad B with alpha and the buoyancy
  * flux F_b from the current saturation, P = 0 on the boundary coefficients.
  * Solved matrix-free by conjugate gradients with preconditioner precond
- * (CRV_PRECOND_*), from P = 0, until |F - S P| <= rtol |F| (tested every 24
- * iterations) or max_iters.  The solution replaces the pressure
+ * (CRV_PRECOND_*), from P = 0, until |F - S P| <= rtol |F| (the recursively
+ * updated residual, tested on the device after every iteration) or
+ * max_iters.  The solution replaces the pressure
  * coefficients the saturation substeps use.  p_coefs (nullable, host,
  * nb^2) receives them; iters and rel_residual (nullable) the iteration count
  * and |r|/|F|.  The first call allocates the solver's device arrays (owned

@@ -16,6 +16,11 @@
 
 namespace crv {
 
+// CG scalars on the device (layout below): converged when r.r (slot 3) is at
+// or under the threshold (slot 6); slot 5 the running iteration's stop flag
+__device__ inline bool cg_converged(const double* sc) { return sc[3] <= sc[6]; }
+__device__ inline void sc5_store(double* sc, bool stop) { sc[5] = stop ? 1.0 : 0.0; }
+
 // w alpha, w q and -gravity w F_b at every Gauss point (S from the spline, K
 // and q Q1-interpolated from the nodes, as in the saturation update)
 template <typename Real, int R>
@@ -121,7 +126,9 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
                                                       const Real* __restrict__ gb,
                                                       const Real* __restrict__ gdb,
                                                       Real* __restrict__ y,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part,
+                                                      const double* __restrict__ sc) {
+  if (cg_converged(sc)) return;
   constexpr int NG = R + 1;
   constexpr int NT = NG * (R + 1);  // table entries per element
   constexpr int TE = TC + R;        // elements per tile and axis
@@ -241,12 +248,19 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
 }
 
 // ---- conjugate-gradient pieces.  Scalars on the device (sc[]): 0 and 1 the
-// r.z of consecutive iterations (alternating slots), 3 r.r, 4 F.F.  The
+// r.z of consecutive iterations (alternating slots), 3 r.r, 4 F.F, 5 the
+// stop flag of the running iteration, 6 the threshold rtol^2 F.F, 7 the
+// iterations done.  Every kernel of an iteration returns at once when r.r
+// (left by the previous iteration) is at or under the threshold, so that
+// iterations after convergence cost only their launches and the count in
+// slot 7 is exact; the direction update, which rewrites r.r, tests the flag
+// that the x/r update of its own iteration set instead.  The
 // operator leaves one partial of p.Ap per tile in part, the update kernels
 // one (r.z, r.r) pair per block in part2; a kernel that needs such a sum adds
 // the partials itself, every block in the same fixed order, so all blocks
 // hold the same value and no reduction launch sits between the steps.
 constexpr int kDotBlocks = 256;
+
 
 // sum over i < np of part[2 i + j] (blocks of 256 threads; every block alike)
 __device__ inline double sum_pairs(const double* __restrict__ part, int np, int j,
@@ -330,11 +344,14 @@ __global__ __launch_bounds__(256) void k_pcg_init(int nb, int mp, const Real* __
 // (grid-stride, kDotBlocks blocks of 256)
 template <typename Real, bool JAC>
 __global__ __launch_bounds__(256) void k_pcg_step1(
-    int nb, int mp, const double* __restrict__ sc, int s_rz, const double* __restrict__ part,
+    int nb, int mp, double* __restrict__ sc, int s_rz, const double* __restrict__ part,
     int ntiles, Real* __restrict__ x, Real* __restrict__ r, Real* __restrict__ z,
     const Real* __restrict__ p, const Real* __restrict__ ap, const Real* __restrict__ dg,
     const Real* __restrict__ ksc, Real* __restrict__ t, double* __restrict__ part2) {
   __shared__ double red[256];
+  const bool stop = cg_converged(sc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc5_store(sc, stop);
+  if (stop) return;
   const double pap = sum_pairs(part, ntiles, 0, red);
   const Real a = pap != 0.0 ? Real(sc[s_rz] / pap) : Real(0);  // converged exactly: stay
   const int64_t n = int64_t(nb) * nb;
@@ -364,19 +381,22 @@ __global__ __launch_bounds__(256) void k_pcg_step1(
 
 // rz_new and rr from the kDotBlocks pairs in part2; b = rz_new / sc[s_old]:
 // p = z + b p.  Block 0 stores rz_new in slot s_new (never s_old) and rr in
-// slot 3
+// slot 3 and counts the iteration.  Skipped when the flag of this iteration
+// is set (count_it false: the set-up's call, which is no iteration)
 template <typename Real>
 __global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, double* __restrict__ sc, int s_new,
                                                    int s_old, const double* __restrict__ part2,
                                                    const Real* __restrict__ z,
-                                                   Real* __restrict__ p) {
+                                                   Real* __restrict__ p, bool count_it) {
   __shared__ double red[256];
+  if (count_it && sc[5] != 0.0) return;
   const double rz = sum_pairs(part2, kDotBlocks, 0, red);
   const double rr = sum_pairs(part2, kDotBlocks, 1, red);
   const double old = sc[s_old];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[s_new] = rz;
     sc[3] = rr;
+    if (count_it) sc[7] += 1.0;
   }
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -428,7 +448,9 @@ __global__ __launch_bounds__(256) void k_kron_out_dot(int nb, int mp, const Real
                                                       const Real* __restrict__ ksc,
                                                       const Real* __restrict__ r,
                                                       Real* __restrict__ z,
-                                                      double* __restrict__ part2) {
+                                                      double* __restrict__ part2,
+                                                      const double* __restrict__ sc) {
+  if (sc && cg_converged(sc)) return;
   __shared__ double red[256];
   const int64_t n = int64_t(nb) * nb;
   double s1 = 0, s2 = 0;
@@ -448,14 +470,16 @@ __global__ __launch_bounds__(256) void k_kron_out_dot(int nb, int mp, const Real
   }
 }
 
-// t0 -> t2 = (V x V) L^-1 (V x V) t0 (the four products)
+// t0 -> t2 = (V x V) L^-1 (V x V) t0 (the four products); skipped once the
+// CG scalars sc (nullable: never skipped) show convergence
 template <typename Real>
-static void kron_products(const GalerkinWork<Real>& w, hipStream_t st) {
+static void kron_products(const GalerkinWork<Real>& w, const double* sc, hipStream_t st) {
   const int mp = w.mgp;
-  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt0, w.kt1, 1, w.ksym, st, w.kdst_pk);
-  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 2, w.ksym, st, w.kdst_pk);
-  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt2, w.kt1, 1, w.ksym, st, w.kdst_pk);
-  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 0, w.ksym, st, w.kdst_pk);
+  const double* skip = sc ? sc + 3 : nullptr;  // skip[0] = r.r, skip[3] = the threshold
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt0, w.kt1, 1, w.ksym, st, w.kdst_pk, skip);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 2, w.ksym, st, w.kdst_pk, skip);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt2, w.kt1, 1, w.ksym, st, w.kdst_pk, skip);
+  launch_gemm_sq_epi<Real>(mp, w.kdst, w.kt1, w.kt2, 0, w.ksym, st, w.kdst_pk, skip);
 }
 
 // tile edge of the operator kernel: 16 (float, r <= 2), else 8 (LDS)
@@ -490,11 +514,12 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
     k_zero<Real><<<cdiv(mp2, 256), 256, 0, st>>>(mp2, w.kt0);
     k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, w.mgp, w.f, nullptr, w.ksc, a.x, w.r,
                                                    w.z, w.p, w.kt0);
-    kron_products<Real>(w, st);
-    k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z, w.part2);
+    kron_products<Real>(w, nullptr, st);
+    k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z, w.part2,
+                                                     nullptr);
     k_dot2_fin<<<1, 256, 0, st>>>(w.part2, kDotBlocks, w.sc, 0, 4);  // r.z, F.F (r = F)
     // p = z + b 0 = z (slot 4 as the old value: read only, never written here)
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, 0, 4, w.part2, w.z, w.p);
+    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, 0, 4, w.part2, w.z, w.p, false);
   } else {
     k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, 0, w.f, w.dg, nullptr, a.x, w.r, w.z,
                                                    w.p, nullptr);
@@ -514,20 +539,22 @@ static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hip
   const int ntiles = int(tiles.x * tiles.y);
   for (int it = 0; it < iters; ++it) {
     const int s_old = it & 1, s_new = s_old ^ 1;
-    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.p, w.c, a.gb, a.gdb, w.ap, w.part);
+    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.p, w.c, a.gb, a.gdb, w.ap, w.part,
+                                                         w.sc);
     if (a.precond == 1) {
       k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.sc, s_old, w.part,
                                                            ntiles, a.x, w.r, w.z, w.p, w.ap,
                                                            w.dg, w.ksc, w.kt0, w.part2);
-      kron_products<Real>(w, st);
+      kron_products<Real>(w, w.sc, st);
       k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z,
-                                                       w.part2);
+                                                       w.part2, w.sc);
     } else {
       k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(g.nb, 0, w.sc, s_old, w.part, ntiles,
                                                           a.x, w.r, w.z, w.p, w.ap, w.dg,
                                                           nullptr, nullptr, w.part2);
     }
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, s_new, s_old, w.part2, w.z, w.p);
+    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, s_new, s_old, w.part2, w.z, w.p,
+                                                    true);
   }
 }
 

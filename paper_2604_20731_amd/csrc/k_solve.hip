@@ -509,12 +509,16 @@ void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_str
 // ---------------------------------------------------------------------------
 // EPI (this kernel and k_gemm_pa_f32): 0 stores C; 1 stores C^T (square C);
 // 2 stores C_ij / (sym[M+i] sym[j] + sym[i] sym[M+j]) (square C; the
-// Kronecker symbol of the Galerkin preconditioner)
+// Kronecker symbol of the Galerkin preconditioner).  skip (nullable): the
+// whole product is left out when skip[0] <= skip[3] (an iterative solve's
+// residual against its threshold, read from device memory)
 template <typename Real, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Real* __restrict__ A,
                                               int lda, const Real* __restrict__ B, int ldb,
                                               int64_t sb, Real* __restrict__ C, int ldc,
-                                              int64_t sc, const Real* __restrict__ sym) {
+                                              int64_t sc, const Real* __restrict__ sym,
+                                              const double* __restrict__ skip) {
+  if (skip && skip[0] <= skip[3]) return;
   B += int64_t(blockIdx.z) * sb;
   C += int64_t(blockIdx.z) * sc;
   __shared__ Real As[16][64 + 4];
@@ -618,7 +622,9 @@ __global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
                                                      const float* __restrict__ Af,
                                                      const float* __restrict__ B, int ldb,
                                                      int64_t sb, float* __restrict__ C, int ldc,
-                                                     int64_t sc, const float* __restrict__ sym) {
+                                                     int64_t sc, const float* __restrict__ sym,
+                                                     const double* __restrict__ skip) {
+  if (skip && skip[0] <= skip[3]) return;
   B += int64_t(blockIdx.z) * sb;
   C += int64_t(blockIdx.z) * sc;
   __shared__ float part[8][32 * 33];
@@ -664,7 +670,7 @@ __global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
 template <typename Real, int EPI>
 static void gemm_dispatch(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
                           int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
-                          const Real* a_packed, const Real* sym) {
+                          const Real* a_packed, const Real* sym, const double* skip) {
   if (batch <= 0) return;
   if constexpr (sizeof(Real) == 4) {
     if (EPI != 0 || a_packed) {  // epilogues: callers always pass the packed operand
@@ -678,7 +684,8 @@ static void gemm_dispatch(int M, int N, int K, const Real* A, int lda, const Rea
           break;
         }
       dim3 grid(N / 32, M / 32, batch);
-      k_gemm_pa_f32<EPI><<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc, sym);
+      k_gemm_pa_f32<EPI><<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc, sym,
+                                                   skip);
       return;
     }
     // dims are multiples of 64, so K/4 is a multiple of 16
@@ -686,7 +693,7 @@ static void gemm_dispatch(int M, int N, int K, const Real* A, int lda, const Rea
     k_gemm_mfma_f32<<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc);
   } else {
     dim3 grid(N / 64, M / 64, batch);
-    k_gemm<Real, EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, sym);
+    k_gemm<Real, EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, sym, skip);
   }
 }
 
@@ -694,16 +701,20 @@ template <typename Real>
 void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb,
                          int64_t sb, Real* C, int ldc, int64_t sc, int batch, hipStream_t st,
                          const Real* a_packed) {
-  gemm_dispatch<Real, 0>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, batch, st, a_packed, nullptr);
+  gemm_dispatch<Real, 0>(M, N, K, A, lda, B, ldb, sb, C, ldc, sc, batch, st, a_packed, nullptr,
+                         nullptr);
 }
 
 template <typename Real>
 void launch_gemm_sq_epi(int M, const Real* A, const Real* B, Real* C, int epi, const Real* sym,
-                        hipStream_t st, const Real* a_packed) {
+                        hipStream_t st, const Real* a_packed, const double* skip) {
   if (sizeof(Real) == 4 && !a_packed) return;  // float epilogues run on the packed kernel only
-  if (epi == 1) gemm_dispatch<Real, 1>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
-  else if (epi == 2) gemm_dispatch<Real, 2>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
-  else gemm_dispatch<Real, 0>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym);
+  if (epi == 1)
+    gemm_dispatch<Real, 1>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym, skip);
+  else if (epi == 2)
+    gemm_dispatch<Real, 2>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym, skip);
+  else
+    gemm_dispatch<Real, 0>(M, M, M, A, M, B, M, 0, C, M, 0, 1, st, a_packed, sym, skip);
 }
 
 template <typename Real>
@@ -722,7 +733,7 @@ void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int
   template void launch_gemm_batched<R>(int, int, int, const R*, int, const R*, int, int64_t, R*, \
                                        int, int64_t, int, hipStream_t, const R*);                \
   template void launch_gemm_sq_epi<R>(int, const R*, const R*, R*, int, const R*, hipStream_t,  \
-                                      const R*);
+                                      const R*, const double*);
 CRV_INST(float)
 CRV_INST(double)
 

@@ -144,10 +144,11 @@ void launch_gemm_batched(int M, int N, int K, const Real* A, int lda, const Real
 // C = A B for square M x M operands (M a multiple of 64, leading dimensions M)
 // with an epilogue: epi 0 stores C, 1 stores C^T, 2 stores
 // C_ij / (sym[M+i] sym[j] + sym[i] sym[M+j]).  float needs a_packed (the
-// call does nothing without it); double ignores it.
+// call does nothing without it); double ignores it.  skip (nullable, device):
+// the product is left out when skip[0] <= skip[3] at the time it runs.
 template <typename Real>
 void launch_gemm_sq_epi(int M, const Real* A, const Real* B, Real* C, int epi, const Real* sym,
-                        hipStream_t st, const Real* a_packed);
+                        hipStream_t st, const Real* a_packed, const double* skip);
 
 // ---- network (k_mlp.hip) ---------------------------------------------------
 struct MlpShape {

@@ -638,9 +638,10 @@ struct Solver : SolverBase {
                               cfg.gravity, b.p, gw, precond};
   }
   // S P = F for the current saturation into b.p by preconditioned CG from
-  // P = 0, until |r| <= rtol |F| (checked every 24 iterations) or max_iters.
-  // Iterations alternate the slot of r.z, so every chunk but the last (which
-  // may be shorter) has an even length
+  // P = 0, until |r| <= rtol |F| (tested after every iteration on the device)
+  // or max_iters.  Iterations run in chunks of 24 (a captured graph) and
+  // alternate the slot of r.z, so every chunk but the last (which may be
+  // shorter) has an even length
   crv_status pressure_galerkin(int max_iters, double rtol, int precond, double* p_out,
                                int* iters_out, double* relres_out) override {
     if (g.dim != 2) return fail(CRV_EINVAL, "the Galerkin pressure path is built for 2D");
@@ -650,9 +651,18 @@ struct Solver : SolverBase {
     crv_status s = galerkin_alloc();
     if (s) return s;
     const GalerkinArgs<Real> a = galerkin_args(precond);
+    // slots 5-7 (stop flag, threshold, iteration count): no stop before the
+    // threshold is known
+    double tail[3] = {0.0, -1.0, 0.0};
+    auto write_tail = [&]() -> crv_status {
+      CRV_HIP(hipMemcpyAsync(gw.sc + 5, tail, sizeof(tail), hipMemcpyHostToDevice, st));
+      CRV_HIP(hipStreamSynchronize(st));
+      return CRV_OK;
+    };
+    if ((s = write_tail())) return s;
     launch_galerkin_setup<Real>(g, a, st);
     if ((s = check_launch())) return s;
-    double sc[5] = {0, 0, 0, 0, 0};
+    double sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto read_sc = [&]() -> crv_status {
       CRV_HIP(hipMemcpyAsync(sc, gw.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
       CRV_HIP(hipStreamSynchronize(st));
@@ -661,6 +671,16 @@ struct Solver : SolverBase {
     if ((s = read_sc())) return s;
     const double ff = sc[4];
     double rel = ff > 0 ? 1.0 : 0.0;
+    // the iterations stop themselves on the device once r.r <= rtol^2 F.F, so
+    // a chunk may end early and the count comes from the device.  Slots 3-7:
+    // r.r = F.F (r = F before the first iteration; the Kronecker set-up has
+    // already stored this very sum), F.F, flag, threshold, count
+    {
+      const double head[5] = {ff, ff, 0.0, rtol * rtol * ff, 0.0};
+      CRV_HIP(hipMemcpyAsync(gw.sc + 3, head, sizeof(head), hipMemcpyHostToDevice, st));
+      CRV_HIP(hipStreamSynchronize(st));
+      tail[1] = head[3];
+    }
     int done = 0;
     const int chunk = 24;  // even: each chunk starts with rz in slot 0
     hipGraphExec_t& graph = g_gal[precond];
@@ -668,7 +688,8 @@ struct Solver : SolverBase {
       s = capture(&graph, [&] { launch_galerkin_iters<Real>(g, a, chunk, st); });
       if (s) return s;
     }
-    while (ff > 0 && done < max_iters && rel > rtol) {
+    bool stopped = false;
+    while (ff > 0 && done < max_iters && rel > rtol && !stopped) {
       const int k = std::min(chunk, max_iters - done);
       if (graph && use_graphs() && k == chunk) CRV_HIP(hipGraphLaunch(graph, st));
       else launch_galerkin_iters<Real>(g, a, k, st);
@@ -676,8 +697,10 @@ struct Solver : SolverBase {
       if ((s = read_sc())) return s;
       done += k;
       rel = std::sqrt(std::max(sc[3], 0.0) / ff);
+      stopped = sc[3] <= tail[1];
       if (!std::isfinite(rel)) return fail(CRV_ENUMERIC, "Galerkin solve produced a non-finite residual");
     }
+    done = int(sc[7]);
     if (iters_out) *iters_out = done;
     if (relres_out) *relres_out = rel;
     if (p_out && (s = download(p_out, b.p, nc))) return s;

@@ -77,11 +77,13 @@ def test_galerkin_path_rejects_3d():
         sc.pressure_galerkin()
 
 
-@pytest.mark.parametrize("precond,min_iters", [("jacobi", 48), ("kron", 24)])
+@pytest.mark.parametrize("precond,min_iters", [("jacobi", 48), ("kron", 25)])
 def test_captured_cg_chunks_equal_eager_launches(precond, min_iters):
     """The CG iterations replayed from a captured graph (chunks of 24, the
-    host reading the residual between replays) give bitwise the result of
-    the same iterations launched one by one."""
+    host reading the residual between replays, the iterations stopping
+    themselves on the device inside a chunk) give bitwise the result and the
+    iteration count of the same iterations launched one by one; rtol 1e-9
+    takes both preconditioners past the first chunk."""
     import os
     prob = problem("c1", n_elem=48)
     sc_graph, _ = _pair(prob, "fp32", grav=True)
@@ -91,8 +93,8 @@ def test_captured_cg_chunks_equal_eager_launches(precond, min_iters):
     finally:
         del os.environ["CRV_NO_GRAPH"]
     for _ in range(2):  # the second solve replays the graph captured by the first
-        pg, ig, rg = sc_graph.pressure_galerkin(rtol=1e-7, precond=precond)
-        pe, ie, re = sc_eager.pressure_galerkin(rtol=1e-7, precond=precond)
+        pg, ig, rg = sc_graph.pressure_galerkin(rtol=1e-9, precond=precond)
+        pe, ie, re = sc_eager.pressure_galerkin(rtol=1e-9, precond=precond)
         assert ig == ie and rg == re and np.array_equal(pg, pe)
         assert ig >= min_iters
 
@@ -155,3 +157,39 @@ def test_galerkin_at_the_largest_mesh(precond):
         f"|r| / (u || |S||P| ||) {rn / (u * sn):.1f}")
     assert rr <= rtol
     assert rn <= 2 * rtol * fn + 64 * u * sn
+
+
+def test_galerkin_rejects_an_unknown_preconditioner():
+    """precond outside CRV_PRECOND_* is CRV_EINVAL before any device work;
+    the context stays usable."""
+    import ctypes as C
+    from paper_2604_20731_amd import crv
+    prob = problem("c1")
+    sc = scenario_for(prob, "fp32")
+    it, rr = C.c_int(), C.c_double()
+    for bad in (-1, 2, 7):
+        assert crv.LIB.crv_pressure_galerkin(sc.ctx, 10, 1e-6, bad, None, C.byref(it),
+                                             C.byref(rr)) == crv.CRV_EINVAL
+        assert "precond" in crv.LIB.crv_last_error().decode()
+        assert crv.LIB.crv_step_galerkin(sc.ctx, 1e-4, 10, 1e-6, bad, None, None) == crv.CRV_EINVAL
+    with pytest.raises(KeyError):
+        sc.pressure_galerkin(precond="multigrid")
+    _, iters, rr = sc.pressure_galerkin(rtol=1e-6)
+    assert rr <= 1e-6 and iters > 0
+
+
+def test_iteration_count_is_exact():
+    """The solve stops after the first iteration whose residual meets rtol
+    (tested on the device after every iteration, not per chunk of 24): with
+    max_iters one less than that count the residual is still above rtol, and
+    a solve limited to max_iters iterations does exactly max_iters."""
+    prob = problem("c1", n_elem=48)
+    for precond in ("jacobi", "kron"):
+        sc, _ = _pair(prob, "fp32", grav=True)
+        _, n, rr = sc.pressure_galerkin(rtol=1e-6, precond=precond)
+        assert rr <= 1e-6 and n > 5
+        _, n1, rr1 = sc.pressure_galerkin(max_iters=n - 1, rtol=1e-6, precond=precond)
+        assert n1 == n - 1 and rr1 > 1e-6
+        _, n2, _ = sc.pressure_galerkin(max_iters=5, rtol=1e-6, precond=precond)
+        assert n2 == 5
+        say(f"  {precond}: {n} iterations")
