@@ -133,8 +133,8 @@ def test_galerkin_at_the_largest_mesh(precond):
     a size-independent criterion), plus the gap between the recursively
     updated and the true residual: |F - S P| <= 2 rtol |F| + 64 u || |S| |P| ||
     (the normwise backward-error bound of the other maximum-size solves;
-    measured 1.1 u with the Kronecker preconditioner in 264 iterations,
-    2.5 u with the diagonal in 1344)."""
+    measured 1.1 u with the Kronecker preconditioner in 255 iterations,
+    2.5 u with the diagonal in 1334)."""
     from oracle import galerkin
     say("galerkin 1024^2 cubic", precond)
     prob = problem("c3", width=64)
