@@ -109,8 +109,10 @@ __global__ __launch_bounds__(256) void k_gal_gather2(Geom g, const Real* __restr
   out[t] = acc;
 }
 
-// y = S x on a TC x TC tile of coefficients per block (boundary coefficients
-// 0); part[2 b] = the tile's share of x . y, part[2 b + 1] = 0.  The block
+// y = S x on a TC x TC tile of interior coefficients per block (the tiles
+// cover coefficients 1 .. nb-2 per axis; y on the boundary coefficients is 0
+// and never written here: the set-up zeroes it once); part[2 b] = the tile's
+// share of x . y, part[2 b + 1] = 0.  The block
 // stages the coefficients its TE x TE elements touch and the 1D basis tables
 // of those elements in LDS, then works by sum factorisation (one axis at a
 // time, no atomics, fixed summation order):
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   __shared__ Real sB[4][TE * NT];  // B and d B along x, then along y
   __shared__ double red[NTH];
   const int tid = threadIdx.x;
-  const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC;
+  const int k0 = 1 + blockIdx.x * TC, l0 = 1 + blockIdx.y * TC;
   const int c0x = k0 - R, c0y = l0 - R;
   const int nb = g.nb, ne = g.ne, ng = ne * NG;
   for (int t = tid; t < TCO * TCO; t += NTH) {
@@ -222,18 +224,16 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   const int tx = tid % TC, ty = tid / TC;
   const int k = k0 + tx, l = l0 + ty;
   double xy = 0;
-  if (k < nb && l < nb) {
+  if (k < nb - 1 && l < nb - 1) {
     Real acc = 0;
-    if (k > 0 && l > 0 && k < nb - 1 && l < nb - 1) {
 #pragma unroll
-      for (int j = 0; j <= R; ++j) {
-        const int exl = tx + j;
+    for (int j = 0; j <= R; ++j) {
+      const int exl = tx + j;
 #pragma unroll
-        for (int gx = 0; gx < NG; ++gx) {
-          const int tb = exl * NT + gx * (R + 1) + R - j;
-          const int u = ty * GP + exl * NG + gx;
-          acc += sB[1][tb] * sUx[u] + sB[0][tb] * sUy[u];
-        }
+      for (int gx = 0; gx < NG; ++gx) {
+        const int tb = exl * NT + gx * (R + 1) + R - j;
+        const int u = ty * GP + exl * NG + gx;
+        acc += sB[1][tb] * sUx[u] + sB[0][tb] * sUy[u];
       }
     }
     y[int64_t(l) * nb + k] = acc;
@@ -504,6 +504,7 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
   k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
                                                              a.gdb, a.ws.dg);
   const GalerkinWork<Real>& w = a.ws;
+  k_zero<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.ap);  // boundary entries stay 0
   if (a.precond == 1) {
     const int64_t mp2 = int64_t(w.mgp) * w.mgp;
     // d0 from the diagonal gather with alpha = 1 (f0 is free again)
@@ -535,7 +536,7 @@ static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hip
   constexpr int TC = gal_tc<Real, R>();
   const GalerkinWork<Real>& w = a.ws;
   const int64_t n = int64_t(g.nb) * g.nb;
-  const dim3 tiles(cdiv(g.nb, TC), cdiv(g.nb, TC));
+  const dim3 tiles(cdiv(g.nb - 2, TC), cdiv(g.nb - 2, TC));  // interior coefficients
   const int ntiles = int(tiles.x * tiles.y);
   for (int it = 0; it < iters; ++it) {
     const int s_old = it & 1, s_new = s_old ^ 1;
