@@ -165,7 +165,7 @@ crv_status crv_sync(crv_ctx* ctx);
  * coefficients the saturation substeps use.  p_coefs (nullable, host,
  * nb^2) receives them; iters and rel_residual (nullable) the iteration count
  * and |r|/|F|.  The first call allocates the solver's device arrays (owned
- * by the context, about 3 (Ne (r+1))^2 + 7 nb^2 + 5 mp^2 values, mp = nb - 2
+ * by the context, about 3 (Ne (r+1))^2 + 8 nb^2 + 5 mp^2 values, mp = nb - 2
  * rounded up to 64); CRV_EINVAL in 3D, for max_iters < 0, a negative rtol or
  * an unknown precond; blocks until done. */
 crv_status crv_pressure_galerkin(crv_ctx* ctx, int max_iters, double rtol, int precond,

@@ -19,7 +19,19 @@ namespace crv {
 // CG scalars on the device (layout below): converged when r.r (slot 3) is at
 // or under the threshold (slot 6); slot 5 the running iteration's stop flag
 __device__ inline bool cg_converged(const double* sc) { return sc[3] <= sc[6]; }
-__device__ inline void sc5_store(double* sc, bool stop) { sc[5] = stop ? 1.0 : 0.0; }
+
+// blocks of the update kernels (each leaves one (r.z, r.r) pair)
+constexpr int kDotBlocks = 256;
+
+// sum over i < np of part[2 i + j] by a block of NTH threads (flat index),
+// in a fixed order (every block alike)
+template <int NTH>
+__device__ inline double sum_pairs_n(const double* __restrict__ part, int np, int j,
+                                     double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < np; i += NTH) s += part[2 * i + j];
+  return block_sum_n<NTH>(s, red);
+}
 
 // w alpha, w q and -gravity w F_b at every Gauss point (S from the spline, K
 // and q Q1-interpolated from the nodes, as in the saturation update)
@@ -109,10 +121,16 @@ __global__ __launch_bounds__(256) void k_gal_gather2(Geom g, const Real* __restr
   out[t] = acc;
 }
 
-// y = S x on a TC x TC tile of interior coefficients per block (the tiles
-// cover coefficients 1 .. nb-2 per axis; y on the boundary coefficients is 0
-// and never written here: the set-up zeroes it once); part[2 b] = the tile's
-// share of x . y, part[2 b + 1] = 0.  The block
+// The conjugate-gradient iteration's first step: from the previous update's
+// (r.z, r.r) pairs in part2 (summed by every block alike) the convergence
+// test (r.r <= sc[6]: the block returns; block 0 records r.r in sc[3], r.z in
+// sc[s_new] and the stop flag in sc[5]), then the direction
+// x = z + b p_old with b = r.z / sc[s_old] (0 when that is 0), written to
+// p_new for the tile's own coefficients, and y = S x on a TC x TC tile of
+// interior coefficients per block (the tiles cover coefficients 1 .. nb-2
+// per axis; y and p_new on the boundary coefficients are 0 and never
+// written here: the set-up zeroes them); part[2 b] = the tile's share of
+// x . y, part[2 b + 1] = 0.  The block
 // stages the coefficients its TE x TE elements touch and the 1D basis tables
 // of those elements in LDS, then works by sum factorisation (one axis at a
 // time, no atomics, fixed summation order):
@@ -123,14 +141,11 @@ __global__ __launch_bounds__(256) void k_gal_gather2(Geom g, const Real* __restr
 // with c = w alpha at the Gauss points.  Tables and fluxes of elements
 // outside the mesh are 0, so every sum runs over its full local range.
 template <typename Real, int R, int TC>
-__global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __restrict__ x,
-                                                      const Real* __restrict__ c,
-                                                      const Real* __restrict__ gb,
-                                                      const Real* __restrict__ gdb,
-                                                      Real* __restrict__ y,
-                                                      double* __restrict__ part,
-                                                      const double* __restrict__ sc) {
-  if (cg_converged(sc)) return;
+__global__ __launch_bounds__(TC* TC) void k_gal_apply2(
+    Geom g, const Real* __restrict__ z, const Real* __restrict__ p_old, Real* __restrict__ p_new,
+    const Real* __restrict__ c, const Real* __restrict__ gb, const Real* __restrict__ gdb,
+    Real* __restrict__ y, double* __restrict__ part, const double* __restrict__ part2,
+    double* __restrict__ sc, int s_new, int s_old) {
   constexpr int NG = R + 1;
   constexpr int NT = NG * (R + 1);  // table entries per element
   constexpr int TE = TC + R;        // elements per tile and axis
@@ -143,12 +158,28 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   __shared__ Real sB[4][TE * NT];  // B and d B along x, then along y
   __shared__ double red[NTH];
   const int tid = threadIdx.x;
+  const double rz = sum_pairs_n<NTH>(part2, kDotBlocks, 0, red);
+  const double rr = sum_pairs_n<NTH>(part2, kDotBlocks, 1, red);
+  const bool stop = rr <= sc[6];
+  const double old = sc[s_old];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+    sc[3] = rr;
+    sc[s_new] = rz;
+    sc[5] = stop ? 1.0 : 0.0;
+  }
+  if (stop) return;
+  const Real bdir = old != 0.0 ? Real(rz / old) : Real(0);
   const int k0 = 1 + blockIdx.x * TC, l0 = 1 + blockIdx.y * TC;
   const int c0x = k0 - R, c0y = l0 - R;
   const int nb = g.nb, ne = g.ne, ng = ne * NG;
   for (int t = tid; t < TCO * TCO; t += NTH) {
     const int a = c0x + t % TCO, bb = c0y + t / TCO;
-    sX[t] = (a >= 0 && a < nb && bb >= 0 && bb < nb) ? x[int64_t(bb) * nb + a] : Real(0);
+    Real v = 0;
+    if (a >= 0 && a < nb && bb >= 0 && bb < nb) {
+      const int64_t ci = int64_t(bb) * nb + a;
+      v = z[ci] + bdir * p_old[ci];
+    }
+    sX[t] = v;
   }
   for (int t = tid; t < TE * NT; t += NTH) {
     const int el = t / NT, r = t % NT;
@@ -225,6 +256,7 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
   const int k = k0 + tx, l = l0 + ty;
   double xy = 0;
   if (k < nb - 1 && l < nb - 1) {
+    p_new[int64_t(l) * nb + k] = sX[(ty + R) * TCO + tx + R];
     Real acc = 0;
 #pragma unroll
     for (int j = 0; j <= R; ++j) {
@@ -250,24 +282,22 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(Geom g, const Real* __res
 // ---- conjugate-gradient pieces.  Scalars on the device (sc[]): 0 and 1 the
 // r.z of consecutive iterations (alternating slots), 3 r.r, 4 F.F, 5 the
 // stop flag of the running iteration, 6 the threshold rtol^2 F.F, 7 the
-// iterations done.  Every kernel of an iteration returns at once when r.r
-// (left by the previous iteration) is at or under the threshold, so that
+// iterations done.  An iteration is: operator (convergence test, direction
+// p = z + b p_old into the other of two direction arrays, p.Ap partials),
+// update (x, r; with the diagonal also z and the (r.z, r.r) pairs), and with
+// the Kronecker preconditioner its four products and the scatter with the
+// pairs.  Once r.r is at or under the threshold the operator sets the flag
+// and every kernel of that and later iterations returns at once, so
 // iterations after convergence cost only their launches and the count in
-// slot 7 is exact; the direction update, which rewrites r.r, tests the flag
-// that the x/r update of its own iteration set instead.  The
-// operator leaves one partial of p.Ap per tile in part, the update kernels
-// one (r.z, r.r) pair per block in part2; a kernel that needs such a sum adds
-// the partials itself, every block in the same fixed order, so all blocks
-// hold the same value and no reduction launch sits between the steps.
-constexpr int kDotBlocks = 256;
-
-
+// slot 7 is exact.  The operator leaves one partial of p.Ap per tile in
+// part, the update kernels one (r.z, r.r) pair per block in part2; a kernel
+// that needs such a sum adds the partials itself, every block in the same
+// fixed order, so all blocks hold the same value and no reduction launch
+// sits between the steps.
 // sum over i < np of part[2 i + j] (blocks of 256 threads; every block alike)
 __device__ inline double sum_pairs(const double* __restrict__ part, int np, int j,
                                    double* red) {
-  double s = 0;
-  for (int i = threadIdx.x; i < np; i += 256) s += part[2 * i + j];
-  return block_sum_n<256>(s, red);
+  return sum_pairs_n<256>(part, np, j, red);
 }
 
 // fixed-order partial sums of a.b and (if c) c.d, double accumulation
@@ -313,9 +343,8 @@ __device__ inline bool on_edge(int k, int l, int nb) {
   return k == 0 || l == 0 || k == nb - 1 || l == nb - 1;
 }
 
-// x = 0, r = F and either z = r / d, p = z (dg given) or p = 0 and the
-// Kronecker preconditioner's input t = ksc F on the interior (dg null; p = z
-// follows once z is known)
+// x = 0, r = F, p = 0 and either z = r / d (dg given) or the Kronecker
+// preconditioner's input t = ksc F on the interior (dg null)
 template <typename Real>
 __global__ __launch_bounds__(256) void k_pcg_init(int nb, int mp, const Real* __restrict__ f,
                                                   const Real* __restrict__ dg,
@@ -327,16 +356,16 @@ __global__ __launch_bounds__(256) void k_pcg_init(int nb, int mp, const Real* __
   if (i >= int64_t(nb) * nb) return;
   x[i] = 0;
   r[i] = f[i];
+  p[i] = 0;
   if (dg) {
     z[i] = f[i] / dg[i];
-    p[i] = z[i];
   } else {
-    p[i] = 0;
     const int k = int(i % nb), l = int(i / nb);
     if (!on_edge(k, l, nb)) t[int64_t(l - 1) * mp + k - 1] = ksc[i] * f[i];
   }
 }
 
+// Unless this iteration's operator set the stop flag: count the iteration,
 // p.Ap from the operator's ntiles partials, a = rz / pAp (rz in slot s_rz):
 // x += a p, r -= a Ap, then
 //   JAC:  z = r / d and this block's (r.z, r.r) pair in part2;
@@ -349,9 +378,8 @@ __global__ __launch_bounds__(256) void k_pcg_step1(
     const Real* __restrict__ p, const Real* __restrict__ ap, const Real* __restrict__ dg,
     const Real* __restrict__ ksc, Real* __restrict__ t, double* __restrict__ part2) {
   __shared__ double red[256];
-  const bool stop = cg_converged(sc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc5_store(sc, stop);
-  if (stop) return;
+  if (sc[5] != 0.0) return;  // set by this iteration's operator
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[7] += 1.0;
   const double pap = sum_pairs(part, ntiles, 0, red);
   const Real a = pap != 0.0 ? Real(sc[s_rz] / pap) : Real(0);  // converged exactly: stay
   const int64_t n = int64_t(nb) * nb;
@@ -377,31 +405,6 @@ __global__ __launch_bounds__(256) void k_pcg_step1(
     part2[2 * blockIdx.x] = t1;
     part2[2 * blockIdx.x + 1] = t2;
   }
-}
-
-// rz_new and rr from the kDotBlocks pairs in part2; b = rz_new / sc[s_old]:
-// p = z + b p.  Block 0 stores rz_new in slot s_new (never s_old) and rr in
-// slot 3 and counts the iteration.  Skipped when the flag of this iteration
-// is set (count_it false: the set-up's call, which is no iteration)
-template <typename Real>
-__global__ __launch_bounds__(256) void k_pcg_step2(int64_t n, double* __restrict__ sc, int s_new,
-                                                   int s_old, const double* __restrict__ part2,
-                                                   const Real* __restrict__ z,
-                                                   Real* __restrict__ p, bool count_it) {
-  __shared__ double red[256];
-  if (count_it && sc[5] != 0.0) return;
-  const double rz = sum_pairs(part2, kDotBlocks, 0, red);
-  const double rr = sum_pairs(part2, kDotBlocks, 1, red);
-  const double old = sc[s_old];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc[s_new] = rz;
-    sc[3] = rr;
-    if (count_it) sc[7] += 1.0;
-  }
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Real b = old != 0.0 ? Real(rz / old) : Real(0);
-  p[i] = z[i] + b * p[i];
 }
 
 // ---- scaled Kronecker (fast-diagonalisation) preconditioner:
@@ -504,7 +507,10 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
   k_gal_gather2<Real, R, true><<<cdiv(n, 256), 256, 0, st>>>(g, a.ws.c, nullptr, nullptr, a.gb,
                                                              a.gdb, a.ws.dg);
   const GalerkinWork<Real>& w = a.ws;
-  k_zero<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.ap);  // boundary entries stay 0
+  // the operator writes only interior entries: the boundary ones of Ap and of
+  // both direction arrays stay 0 (p_old of the first iteration is all 0)
+  k_zero<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.ap);
+  k_zero<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.p2);
   if (a.precond == 1) {
     const int64_t mp2 = int64_t(w.mgp) * w.mgp;
     // d0 from the diagonal gather with alpha = 1 (f0 is free again)
@@ -519,8 +525,6 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
     k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z, w.part2,
                                                      nullptr);
     k_dot2_fin<<<1, 256, 0, st>>>(w.part2, kDotBlocks, w.sc, 0, 4);  // r.z, F.F (r = F)
-    // p = z + b 0 = z (slot 4 as the old value: read only, never written here)
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, 0, 4, w.part2, w.z, w.p, false);
   } else {
     k_pcg_init<Real><<<cdiv(n, 256), 256, 0, st>>>(g.nb, 0, w.f, w.dg, nullptr, a.x, w.r, w.z,
                                                    w.p, nullptr);
@@ -529,34 +533,41 @@ static void gal_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream_t st
   }
 }
 
-// iters CG iterations; iteration it starts with rz in slot it & 1.  Launches
-// per iteration: operator, update, [4 products, scatter + dots], p update
+// iters CG iterations; iteration it stores its r.z in slot it & 1 and its
+// direction in p (it even) or p2 (it odd), reading the previous ones from the
+// other slot and array.  Launches per iteration: operator, update, and with
+// the Kronecker preconditioner 4 products and the scatter with the pairs
 template <typename Real, int R>
 static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st) {
   constexpr int TC = gal_tc<Real, R>();
   const GalerkinWork<Real>& w = a.ws;
-  const int64_t n = int64_t(g.nb) * g.nb;
   const dim3 tiles(cdiv(g.nb - 2, TC), cdiv(g.nb - 2, TC));  // interior coefficients
   const int ntiles = int(tiles.x * tiles.y);
   for (int it = 0; it < iters; ++it) {
-    const int s_old = it & 1, s_new = s_old ^ 1;
-    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.p, w.c, a.gb, a.gdb, w.ap, w.part,
-                                                         w.sc);
+    const int s_cur = it & 1, s_prev = s_cur ^ 1;
+    Real* p_cur = s_cur ? w.p2 : w.p;
+    const Real* p_prev = s_cur ? w.p : w.p2;
+    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.z, p_prev, p_cur, w.c, a.gb, a.gdb,
+                                                         w.ap, w.part, w.part2, w.sc, s_cur,
+                                                         s_prev);
     if (a.precond == 1) {
-      k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.sc, s_old, w.part,
-                                                           ntiles, a.x, w.r, w.z, w.p, w.ap,
+      k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.sc, s_cur, w.part,
+                                                           ntiles, a.x, w.r, w.z, p_cur, w.ap,
                                                            w.dg, w.ksc, w.kt0, w.part2);
       kron_products<Real>(w, w.sc, st);
       k_kron_out_dot<Real><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.kt2, w.ksc, w.r, w.z,
                                                        w.part2, w.sc);
     } else {
-      k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(g.nb, 0, w.sc, s_old, w.part, ntiles,
-                                                          a.x, w.r, w.z, w.p, w.ap, w.dg,
+      k_pcg_step1<Real, true><<<kDotBlocks, 256, 0, st>>>(g.nb, 0, w.sc, s_cur, w.part, ntiles,
+                                                          a.x, w.r, w.z, p_cur, w.ap, w.dg,
                                                           nullptr, nullptr, w.part2);
     }
-    k_pcg_step2<Real><<<cdiv(n, 256), 256, 0, st>>>(n, w.sc, s_new, s_old, w.part2, w.z, w.p,
-                                                    true);
   }
+}
+
+template <typename Real>
+void launch_galerkin_finish(const GalerkinWork<Real>& w, hipStream_t st) {
+  k_dot2_fin<<<1, 256, 0, st>>>(w.part2, kDotBlocks, w.sc, 2, 3);
 }
 
 template <typename Real>
@@ -577,5 +588,7 @@ template void launch_galerkin_setup<float>(const Geom&, const GalerkinArgs<float
 template void launch_galerkin_setup<double>(const Geom&, const GalerkinArgs<double>&, hipStream_t);
 template void launch_galerkin_iters<float>(const Geom&, const GalerkinArgs<float>&, int, hipStream_t);
 template void launch_galerkin_iters<double>(const Geom&, const GalerkinArgs<double>&, int, hipStream_t);
+template void launch_galerkin_finish<float>(const GalerkinWork<float>&, hipStream_t);
+template void launch_galerkin_finish<double>(const GalerkinWork<double>&, hipStream_t);
 
 }  // namespace crv

@@ -64,7 +64,7 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
 template <typename Real>
 struct GalerkinWork {
   Real *c, *f0, *fy;              // w alpha, w q, -gravity w F_b at the Gauss points
-  Real *f, *dg, *r, *z, *p, *ap;  // load, diagonal, CG vectors
+  Real *f, *dg, *r, *z, *p, *p2, *ap;  // load, diagonal, CG vectors (two direction arrays)
   double *sc, *part, *part2;       // scalars, operator tile partials, update-block pairs
   // Kronecker preconditioner: mg = nb - 2 interior coefficients per axis,
   // padded to mgp (a multiple of 64); ksc (nb^2) the diagonal scaling,
@@ -91,6 +91,10 @@ void launch_galerkin_setup(const Geom& g, const GalerkinArgs<Real>& a, hipStream
 // the device: sc[3] = r.r, sc[4] = F.F)
 template <typename Real>
 void launch_galerkin_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st);
+// r.r of the last update into sc[3] (the operator records it only at the
+// start of the next iteration), after the last chunk
+template <typename Real>
+void launch_galerkin_finish(const GalerkinWork<Real>& w, hipStream_t st);
 
 // K7f: float64 factorisations on the device.
 // Banded LDL^T of the 1D mass matrix (band (nb, r+1)) -> lt (nb*r), inv_d (nb).

@@ -595,7 +595,7 @@ struct Solver : SolverBase {
     gw.mg = g.nb - 2;
     gw.mgp = (gw.mg + 63) / 64 * 64;
     const size_t mp2 = size_t(gw.mgp) * gw.mgp;
-    const size_t bytes = 3 * up(npts * sizeof(Real)) + 7 * up(ncf * sizeof(Real)) +
+    const size_t bytes = 3 * up(npts * sizeof(Real)) + 8 * up(ncf * sizeof(Real)) +
                          up(8 * sizeof(double)) + 2 * up(2 * nparts * sizeof(double)) +
                          5 * up(mp2 * sizeof(Real)) + up(2 * size_t(gw.mgp) * sizeof(Real));
     CRV_HIP(hipMalloc(&gw_mem, bytes));
@@ -608,6 +608,7 @@ struct Solver : SolverBase {
     gw.r = cv.take<Real>(ncf);
     gw.z = cv.take<Real>(ncf);
     gw.p = cv.take<Real>(ncf);
+    gw.p2 = cv.take<Real>(ncf);
     gw.ap = cv.take<Real>(ncf);
     gw.sc = cv.take<double>(8);
     gw.part = cv.take<double>(2 * nparts);
@@ -672,14 +673,13 @@ struct Solver : SolverBase {
     const double ff = sc[4];
     double rel = ff > 0 ? 1.0 : 0.0;
     // the iterations stop themselves on the device once r.r <= rtol^2 F.F, so
-    // a chunk may end early and the count comes from the device.  Slots 3-7:
-    // r.r = F.F (r = F before the first iteration; the Kronecker set-up has
-    // already stored this very sum), F.F, flag, threshold, count
+    // a chunk may end early and the count comes from the device.  Slots 1-7:
+    // the r.z before the first iteration (0: no previous direction), unused,
+    // r.r = F.F (r = F), F.F, flag, threshold, count
     {
-      const double head[5] = {ff, ff, 0.0, rtol * rtol * ff, 0.0};
-      CRV_HIP(hipMemcpyAsync(gw.sc + 3, head, sizeof(head), hipMemcpyHostToDevice, st));
+      const double head[7] = {0.0, 0.0, ff, ff, 0.0, rtol * rtol * ff, 0.0};
+      CRV_HIP(hipMemcpyAsync(gw.sc + 1, head, sizeof(head), hipMemcpyHostToDevice, st));
       CRV_HIP(hipStreamSynchronize(st));
-      tail[1] = head[3];
     }
     int done = 0;
     const int chunk = 24;  // even: each chunk starts with rz in slot 0
@@ -696,8 +696,14 @@ struct Solver : SolverBase {
       if ((s = check_launch())) return s;
       if ((s = read_sc())) return s;
       done += k;
+      stopped = sc[5] != 0.0;
+      if (!std::isfinite(sc[3])) return fail(CRV_ENUMERIC, "Galerkin solve produced a non-finite residual");
+    }
+    if (ff > 0) {
+      launch_galerkin_finish<Real>(gw, st);
+      if ((s = check_launch())) return s;
+      if ((s = read_sc())) return s;
       rel = std::sqrt(std::max(sc[3], 0.0) / ff);
-      stopped = sc[3] <= tail[1];
       if (!std::isfinite(rel)) return fail(CRV_ENUMERIC, "Galerkin solve produced a non-finite residual");
     }
     done = int(sc[7]);
