@@ -145,7 +145,14 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(
     Geom g, const Real* __restrict__ z, const Real* __restrict__ p_old, Real* __restrict__ p_new,
     const Real* __restrict__ c, const Real* __restrict__ gb, const Real* __restrict__ gdb,
     Real* __restrict__ y, double* __restrict__ part, const double* __restrict__ part2,
-    double* __restrict__ sc, int s_new, int s_old) {
+    double* __restrict__ sc, int s_new, int s_old, int ntx, int ntiles) {
+  // Workgroups are dealt round-robin over the 8 XCDs: block b takes tile
+  // (b % 8) * per + b / 8, so each XCD (one L2) works through a contiguous
+  // band of tile rows and neighbouring tiles share their halo in its L2;
+  // the grid is 8 per blocks, those past the last tile leave at once
+  const int per = int(gridDim.x) / 8;
+  const int tile = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
+  if (tile >= ntiles) return;
   constexpr int NG = R + 1;
   constexpr int NT = NG * (R + 1);  // table entries per element
   constexpr int TE = TC + R;        // elements per tile and axis
@@ -162,14 +169,14 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(
   const double rr = sum_pairs_n<NTH>(part2, kDotBlocks, 1, red);
   const bool stop = rr <= sc[6];
   const double old = sc[s_old];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+  if (tile == 0 && tid == 0) {
     sc[3] = rr;
     sc[s_new] = rz;
     sc[5] = stop ? 1.0 : 0.0;
   }
   if (stop) return;
   const Real bdir = old != 0.0 ? Real(rz / old) : Real(0);
-  const int k0 = 1 + blockIdx.x * TC, l0 = 1 + blockIdx.y * TC;
+  const int k0 = 1 + (tile % ntx) * TC, l0 = 1 + (tile / ntx) * TC;
   const int c0x = k0 - R, c0y = l0 - R;
   const int nb = g.nb, ne = g.ne, ng = ne * NG;
   for (int t = tid; t < TCO * TCO; t += NTH) {
@@ -273,9 +280,8 @@ __global__ __launch_bounds__(TC* TC) void k_gal_apply2(
   }
   const double t = block_sum_n<TC * TC>(xy, red);
   if (tid == 0) {
-    const int64_t bid = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
-    part[2 * bid] = t;
-    part[2 * bid + 1] = 0;
+    part[2 * tile] = t;
+    part[2 * tile + 1] = 0;
   }
 }
 
@@ -541,15 +547,16 @@ template <typename Real, int R>
 static void gal_iters(const Geom& g, const GalerkinArgs<Real>& a, int iters, hipStream_t st) {
   constexpr int TC = gal_tc<Real, R>();
   const GalerkinWork<Real>& w = a.ws;
-  const dim3 tiles(cdiv(g.nb - 2, TC), cdiv(g.nb - 2, TC));  // interior coefficients
-  const int ntiles = int(tiles.x * tiles.y);
+  const int ntx = cdiv(g.nb - 2, TC);  // tiles of interior coefficients per axis
+  const int ntiles = ntx * ntx;
+  const int nblk = 8 * cdiv(ntiles, 8);
   for (int it = 0; it < iters; ++it) {
     const int s_cur = it & 1, s_prev = s_cur ^ 1;
     Real* p_cur = s_cur ? w.p2 : w.p;
     const Real* p_prev = s_cur ? w.p : w.p2;
-    k_gal_apply2<Real, R, TC><<<tiles, TC * TC, 0, st>>>(g, w.z, p_prev, p_cur, w.c, a.gb, a.gdb,
-                                                         w.ap, w.part, w.part2, w.sc, s_cur,
-                                                         s_prev);
+    k_gal_apply2<Real, R, TC><<<nblk, TC * TC, 0, st>>>(g, w.z, p_prev, p_cur, w.c, a.gb, a.gdb,
+                                                        w.ap, w.part, w.part2, w.sc, s_cur,
+                                                        s_prev, ntx, ntiles);
     if (a.precond == 1) {
       k_pcg_step1<Real, false><<<kDotBlocks, 256, 0, st>>>(g.nb, w.mgp, w.sc, s_cur, w.part,
                                                            ntiles, a.x, w.r, w.z, p_cur, w.ap,
