@@ -6,10 +6,34 @@ from paper_2604_20731_amd import inputs
 
 
 def rel(a, b):
+    """Relative L2 error |a - b| / |b|."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def maxrel(a, b):
+    """Elementwise error normalised by the field's scale, max|a - b| / max|b|.
+    Beside the relative L2 error it catches errors confined to a few entries
+    (one wrong boundary row, a padded tile), which an L2 norm over the whole
+    field dilutes."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
+    mb = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0))
+
+
+def check(label, a, b, tol, max_tol=None):
+    """Print both errors and require rel-L2 < tol and max-rel < max_tol (tol
+    unless given).  Returns (rel-L2, max-rel)."""
+    e2, em = rel(a, b), maxrel(a, b)
+    mt = tol if max_tol is None else max_tol
+    say(f"  {label}: relL2 {e2:.2e} max {em:.2e} (tol {tol:.0e}/{mt:.0e})")
+    assert e2 < tol and em < mt, (label, e2, em, tol, mt)
+    return e2, em
 
 
 def problem(name, seed=0, **over):

@@ -5,7 +5,7 @@ sum-factorised saturation assembly, three-direction Kronecker mass solve,
 import numpy as np
 import pytest
 
-from helpers import oracle_for, problem, rel, say, scenario_for
+from helpers import check, oracle_for, problem, rel, say, scenario_for
 from oracle import ads, bspline, cfl_dt, pressure
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +34,7 @@ def test_mass_solve_3d(prec, ne, r):
     sc = scenario_for(prob3(ne, r, width=16, hidden=2), prec)
     sp_ = ads.Space(ne, r, 3)
     b = np.random.default_rng(ne + r).standard_normal((sp_.nb,) * 3)
-    assert rel(sc.mass_solve(b), sp_.mass_solve(b)) < TOL[prec]
+    check("x", sc.mass_solve(b), sp_.mass_solve(b), TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -46,7 +46,7 @@ def test_gram_solve_3d(prec, ne):
     sc = scenario_for(prob3(ne, width=16, hidden=2), prec)
     res = np.random.default_rng(ne).standard_normal((ne - 1,) * 3)
     q = sc.gram_solve(res)
-    assert rel(q, pressure.gram_solve(res)) < TOL[prec] * 10
+    check("q", q, pressure.gram_solve(res), TOL[prec] * 10)
 
 
 @pytest.mark.parametrize("prec,ne,width,hidden", [
@@ -63,11 +63,13 @@ def test_loss_and_gradients_3d(prec, ne, width, hidden):
     loss, g, gl = sc.loss_grad(with_logperm=True)
     lref, gref = orc.loss_and_grad()
     glref = orc.loss_grad_logperm()
-    el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
-    say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
+    el = abs(loss - lref) / abs(lref)
+    say(f"  loss {el:.2e}")
     tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4, "bf16x3f": 1e-4}[prec]
     # mixed form: bf16 activations and deltas in the backward (dtheta 3e-3)
-    assert el <= tol and egl < tol and eg < (3e-3 if prec == "bf16x3f" else tol)
+    assert el <= tol
+    check("dlogK", gl, glref, tol)
+    check("dtheta", g, gref, 3e-3 if prec == "bf16x3f" else tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -78,7 +80,7 @@ def test_projection_3d(prec, ne, r):
     sc = scenario_for(prob, prec)
     orc = oracle_for(prob)
     pref = ads.project_nodal(orc.space, orc.u_nodal())
-    assert rel(sc.project_pressure(), pref) < (1e-11 if prec == "fp64" else fp32_tol(ne, r))
+    check("p", sc.project_pressure(), pref, 1e-11 if prec == "fp64" else fp32_tol(ne, r))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -103,9 +105,9 @@ def test_saturation_substeps_3d(prec, nsub, ne, r):
     orc.refresh()
     _, s_gpu, sn_gpu = sc.fields()
     tol = 1e-12 if prec == "fp64" else fp32_tol(ne, r) * nsub
-    assert rel(s_gpu, orc.s) < tol
-    assert rel(sn_gpu, orc.s_nodal) < tol
-    assert rel(s_gpu - s0, orc.s - s0) < (1e-10 if prec == "fp64" else 1e-3)
+    check("S", s_gpu, orc.s, tol)
+    check("S nodal", sn_gpu, orc.s_nodal, tol)
+    check("dS", s_gpu - s0, orc.s - s0, 1e-10 if prec == "fp64" else 1e-3)
 
 
 @pytest.mark.parametrize("prec,width,tol", [("fp64", 16, 1e-8), ("fp32", 32, 1e-3),
@@ -127,4 +129,33 @@ def test_coupled_trajectory_3d(prec, width, tol):
         p, s, sn = sc.fields()
         pr, sr, snr = orc.fields()
         say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
-        assert rel(p, pr) < tol and rel(s, sr) < tol and rel(sn, snr) < tol
+        check("p", p, pr, tol)
+        check("S", s, sr, tol)
+        check("S nodal", sn, snr, tol)
+
+
+@pytest.mark.timeout(600)
+def test_coupled_trajectory_3d_c5_network():
+    """The C5 network (3 -> 4x128 -> 1) in the mixed form, the serving and
+    precision default, on a 25^3-node grid with two vertical wells: 200
+    pretraining iterations and two coupled steps against the FP64 oracle at
+    the BF16-network tolerance 5e-3."""
+    say("coupled_3d c5 network, bf16x3f")
+    tol = 5e-3
+    prob = prob3(24, width=128, hidden=4)
+    sc = scenario_for(prob, "bf16x3f")
+    orc = oracle_for(prob, lr=1e-4)
+    n_pre = 200
+    l_gpu = sc.pretrain_pressure(n_pre)
+    orc.pretrain(n_pre)
+    assert abs(l_gpu - orc.loss_history[-1]) <= tol * abs(orc.loss_history[-1])
+    dt = cfl_dt(orc)
+    for k in range(2):
+        sc.step(dt)
+        orc.step(dt)
+        p, s, sn = sc.fields()
+        pr, sr, snr = orc.fields()
+        say(f"  step {k}")
+        check("p", p, pr, tol)
+        check("S", s, sr, tol)
+        check("S nodal", sn, snr, tol)

@@ -7,14 +7,14 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import oracle_for, problem, rel, say, scenario_for
+from helpers import maxrel, oracle_for, problem, rel, say, scenario_for
 
 pytestmark = pytest.mark.gpu
 
 WELLS3 = np.array([[0.25, 0.25, 1.0], [0.75, 0.75, -1.0]])
 
 
-def _check(prob, prec, tol, n_coords=32):
+def _check(prob, prec, tol, n_coords=32, tol_dtheta=None):
     from paper_2604_20731_amd.autograd import crv_loss
     sc = scenario_for(prob, prec)
     orc = oracle_for(prob)
@@ -36,9 +36,10 @@ def _check(prob, prec, tol, n_coords=32):
     ik = rng.choice(lk.size, size=n_coords, replace=False)
     e = dict(loss=abs(float(loss.detach()) - lref) / abs(lref), dtheta32=rel(g[it], gref[it]),
              dlogK32=rel(gl.ravel()[ik], glref.ravel()[ik]), dtheta=rel(g, gref),
-             dlogK=rel(gl, glref))
+             dlogK=rel(gl, glref), dtheta_max=maxrel(g, gref), dlogK_max=maxrel(gl, glref))
     say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
-    assert all(v < tol for v in e.values()), e
+    tt = tol if tol_dtheta is None else tol_dtheta
+    assert all(v < (tt if k.startswith("dtheta") else tol) for k, v in e.items()), e
     assert sc.get_state()[3] == t_before      # training state untouched
 
 
@@ -63,3 +64,15 @@ def test_autograd_c5_full():
     injectors, FP32 network."""
     say("autograd c5 129^3 fp32")
     _check(problem("c5"), "fp32", 1e-4)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol,tol_dtheta", [("bf16x3f", 1e-4, 3e-3), ("bf16", 1e-1, 1e-1)])
+def test_autograd_c5_full_bf16(prec, tol, tol_dtheta):
+    """The same full-size 3D workload with the network on bf16 matrix cores:
+    the mixed form (split-bf16 forward, so loss and dlogK keep 1e-4; bf16
+    activations and deltas in the backward, dtheta 3e-3) and plain bf16
+    (products of bf16-rounded operands, error about 2^-9 per product through
+    four layers: the documented 1e-1 bound of that form)."""
+    say("autograd c5 129^3", prec)
+    _check(problem("c5"), prec, tol, tol_dtheta=tol_dtheta)

@@ -8,7 +8,7 @@ are non-uniform so every gravity term is active."""
 import numpy as np
 import pytest
 
-from helpers import oracle_for, problem, rel, say, scenario_for
+from helpers import check, oracle_for, problem, rel, say, scenario_for
 from oracle import ads, bspline, cfl_dt
 
 pytestmark = pytest.mark.gpu
@@ -52,10 +52,12 @@ def test_loss_and_gradients_with_gravity(prec, name, over):
     loss, g, gl = sc.loss_grad(with_logperm=True)
     lref, gref = orc.loss_and_grad()
     glref = orc.loss_grad_logperm()
-    el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
-    say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
+    el = abs(loss - lref) / abs(lref)
+    say(f"  loss {el:.2e}")
     tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3f": 1e-4}[prec]
-    assert el <= tol and egl < tol and eg < (3e-3 if prec == "bf16x3f" else tol)
+    assert el <= tol
+    check("dlogK", gl, glref, tol)
+    check("dtheta", g, gref, 3e-3 if prec == "bf16x3f" else tol)
     # the gravity terms matter at this size: without them the loss differs
     orc.gravity = 0.0
     orc.refresh()
@@ -81,17 +83,18 @@ def test_saturation_substeps_with_gravity(prec, nsub, name, over):
     _, s_gpu, sn_gpu = sc.fields()
     tol = 1e-12 if prec == "fp64" else _fp32_tol(prob.n_elem, prob.degree, prob.dim) * nsub
     say(f"  S {rel(s_gpu, orc.s):.2e}  dS {rel(s_gpu - s0, orc.s - s0):.2e}")
-    assert rel(s_gpu, orc.s) < tol
-    assert rel(sn_gpu, orc.s_nodal) < tol
-    assert rel(s_gpu - s0, orc.s - s0) < (1e-10 if prec == "fp64" else 1e-3)
+    check("S", s_gpu, orc.s, tol)
+    check("S nodal", sn_gpu, orc.s_nodal, tol)
+    check("dS", s_gpu - s0, orc.s - s0, 1e-10 if prec == "fp64" else 1e-3)
 
 
-# Mixed form: its backward rounds activations and deltas to bf16 (dtheta within
-# 3e-3 of the oracle per iteration, pinned above); 500 Adam iterations of
-# such gradients let the network pressure drift up to about 6e-3 from the
-# FP64 trajectory here (gravity adds a large smooth source), hence 1e-2 for
-# the trajectory while the one-iteration parity keeps 1e-4 / 3e-3.
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3f", 1e-2)])
+# The mixed form (bf16 activations and deltas in the backward) drifts to
+# about 6e-3 from the FP64 trajectory over these 500 iterations at C1 size
+# with gravity, above the 5e-3 bound of a BF16 network; gravity scenarios
+# therefore take the split-bf16 form (three products per weight product in
+# the backward too), which is held to 5e-3 here.  The mixed form's
+# one-iteration parity with gravity is checked above.
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 5e-3)])
 def test_coupled_trajectory_with_gravity(prec, tol):
     say("gravity coupled c1", prec)
     prob = problem("c1")
@@ -107,4 +110,6 @@ def test_coupled_trajectory_with_gravity(prec, tol):
         p, s, sn = sc.fields()
         pr, sr, snr = orc.fields()
         say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
-        assert rel(p, pr) < tol and rel(s, sr) < tol and rel(sn, snr) < tol
+        check("p", p, pr, tol)
+        check("S", s, sr, tol)
+        check("S nodal", sn, snr, tol)

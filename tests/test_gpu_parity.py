@@ -6,7 +6,7 @@ of the same kernels must agree to round-off."""
 import numpy as np
 import pytest
 
-from helpers import oracle_for, problem, rel, say, scenario_for
+from helpers import check, oracle_for, problem, rel, say, scenario_for
 from oracle import ads, cfl_dt, pressure
 
 pytestmark = pytest.mark.gpu
@@ -23,7 +23,7 @@ def test_mass_solve(prec, ne, r):
     sp_ = ads.Space(ne, r, 2)
     b = np.random.default_rng(ne + r).standard_normal((sp_.nb, sp_.nb))
     x = sc.mass_solve(b)
-    assert rel(x, sp_.mass_solve(b)) < TOL[prec]
+    check("x", x, sp_.mass_solve(b), TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -34,7 +34,7 @@ def test_gram_solve(prec, ne):
     sc = scenario_for(prob, prec)
     res = np.random.default_rng(ne).standard_normal((ne - 1, ne - 1))
     q = sc.gram_solve(res)
-    assert rel(q, pressure.gram_solve(res)) < TOL[prec] * (10 if ne >= 256 else 1)
+    check("q", q, pressure.gram_solve(res), TOL[prec] * (10 if ne >= 256 else 1))
 
 
 GRAD_CASES = [("tiny", {}), ("c1", {}), ("c1", dict(n_elem=40, width=64, hidden=4)),
@@ -59,13 +59,15 @@ def test_loss_and_gradients(prec, name, over):
     loss, g, gl = sc.loss_grad(with_logperm=True)
     lref, gref = orc.loss_and_grad()
     glref = orc.loss_grad_logperm()
-    el, eg, egl = abs(loss - lref) / abs(lref), rel(g, gref), rel(gl, glref)
-    say(f"  loss {el:.2e} dtheta {eg:.2e} dlogK {egl:.2e}")
+    el = abs(loss - lref) / abs(lref)
+    say(f"  loss {el:.2e}")
     tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1, "bf16x3": 1e-4, "bf16x3f": 1e-4}[prec]
     # mixed form: loss and dlogK come from the split-bf16 forward (1e-4); the
     # network backward rounds activations and deltas to bf16 (2^-9 each, random
     # across nodes), so dtheta gets 3e-3 (measured up to 1.0e-3)
-    assert el <= tol and egl < tol and eg < (3e-3 if prec == "bf16x3f" else tol)
+    assert el <= tol
+    check("dlogK", gl, glref, tol)
+    check("dtheta", g, gref, 3e-3 if prec == "bf16x3f" else tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -77,7 +79,7 @@ def test_projection(prec, ne, r):
     orc = oracle_for(prob)
     p = sc.project_pressure()
     pref = ads.project_nodal(orc.space, orc.u_nodal())
-    assert rel(p, pref) < (1e-11 if prec == "fp64" else 1e-5)
+    check("p", p, pref, 1e-11 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -105,9 +107,9 @@ def test_saturation_substeps(prec, nsub, ne, r, wells):
     orc.refresh()
     _, s_gpu, sn_gpu = sc.fields()
     tol = 1e-12 if prec == "fp64" else 1e-5 * nsub
-    assert rel(s_gpu, orc.s) < tol
-    assert rel(sn_gpu, orc.s_nodal) < tol
-    assert rel(s_gpu - s0, orc.s - s0) < (1e-10 if prec == "fp64" else 1e-3)
+    check("S", s_gpu, orc.s, tol)
+    check("S nodal", sn_gpu, orc.s_nodal, tol)
+    check("dS", s_gpu - s0, orc.s - s0, 1e-10 if prec == "fp64" else 1e-3)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3), ("bf16x3", 5e-3),
@@ -129,11 +131,13 @@ def test_coupled_trajectory_c1(prec, tol):
         p, s, sn = sc.fields()
         pr, sr, snr = orc.fields()
         say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
-        assert rel(p, pr) < tol and rel(s, sr) < tol and rel(sn, snr) < tol
+        check("p", p, pr, tol)
+        check("S", s, sr, tol)
+        check("S nodal", sn, snr, tol)
     hist = sc.loss_history()
     assert len(hist) == n_pre + n_steps * 100
     say(f"  loss history {rel(hist, np.array(orc.loss_history)):.3e}")
-    assert rel(hist, np.array(orc.loss_history)) < tol
+    check("hist", hist, np.array(orc.loss_history), tol)
 
 
 @pytest.mark.timeout(900)
@@ -156,7 +160,7 @@ def test_coupled_trajectory_c1_full(prec, tol):
         orc.step(dt)
         p, s, sn = sc.fields()
         pr, sr, snr = orc.fields()
-        e = max(rel(p, pr), rel(s, sr), rel(sn, snr))
-        worst = max(worst, e)
-        say(f"  step {k}: p {rel(p, pr):.3e}  S {rel(s, sr):.3e}  Snodal {rel(sn, snr):.3e}")
-    assert worst < tol
+        say(f"  step {k}")
+        for lab, a, b in (("p", p, pr), ("S", s, sr), ("S nodal", sn, snr)):
+            worst = max(worst, *check(lab, a, b, tol))
+    say(f"  worst {worst:.3e}")
