@@ -97,14 +97,16 @@ def measured_traffic(symbol, table=os.path.join(ROOT, "profiles", "b512_hbm_traf
     return None
 
 
-def kernel_rooflines(kernels, prob, precision):
+def kernel_rooflines(kernels, prob, precision, scenarios=1):
     """Add achieved rate, peak and fraction to every event-timed kernel with an
-    algorithmic work figure (matrix-core kernels in TFLOP/s, the rest in GB/s)."""
+    algorithmic work figure (matrix-core kernels in TFLOP/s, the rest in GB/s);
+    a batched launch does the work of `scenarios` scenarios."""
     for name, kv in kernels.items():
         work = algorithmic_work(name, prob, 1)
         if not work:
             continue
         amount, unit = work
+        amount *= scenarios
         sec = kv["us_per_launch"] * 1e-6
         if unit == "flop":
             if name == "gram_dst":
@@ -220,23 +222,32 @@ def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
     return out
 
 
-def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
-    """Aggregate coupled steps/s of several 512^2 scenarios, each on its own
-    stream, stepped together by crv_step_batch (their captured steps overlap
-    on the device)."""
+def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="bucket",
+                profile=False):
+    """Aggregate coupled steps/s of several 512^2 scenarios stepped together by
+    crv_step_batch.  mode "bucket": the scenarios' workspaces lie at one
+    stride in one allocation and every kernel of the step runs once for all of
+    them (the scenario index selects the workspace); "streams": each scenario
+    on its own stream, their captured steps overlapping on the device.  With
+    profile, one more batched step runs event-timed (bucket mode)."""
     import torch
     from paper_2604_20731_amd import crv, inputs
-    scs = []
-    for sd in seeds:
-        prob = inputs.make_problem("b512", seed=sd, n_elem=n_elem)
-        cfg = crv.config(dim=2, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
-                         hidden=prob.hidden, precision=precision)
-        st = torch.cuda.Stream()
-        sc = crv.Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0, stream=st)
+    probs = [inputs.make_problem("b512", seed=sd, n_elem=n_elem) for sd in seeds]
+    p0 = probs[0]
+    cfg = crv.config(dim=2, n_elem=p0.n_elem, degree=p0.degree, width=p0.width,
+                     hidden=p0.hidden, precision=precision)
+    bucket = None
+    if mode == "bucket":
+        bucket = crv.Bucket(cfg, probs)
+        ctxs = bucket.scenarios
+    else:
+        ctxs = [crv.Scenario(cfg, pr.log_perm, pr.porosity, pr.wells, pr.theta0,
+                             stream=torch.cuda.Stream()) for pr in probs]
+    dts = []
+    for sc, pr in zip(ctxs, probs):
         sc.pretrain_pressure(pretrain)
         p, _, _ = sc.fields()
-        scs.append((sc, cfl_dt_from_pressure(p, np.exp(prob.log_perm), prob.porosity, prob.n_elem)))
-    ctxs, dts = [sc for sc, _ in scs], [dt for _, dt in scs]
+        dts.append(cfl_dt_from_pressure(p, np.exp(pr.log_perm), pr.porosity, pr.n_elem))
     for _ in range(warmup):
         crv.step_batch(ctxs, dts)
     torch.cuda.synchronize()
@@ -245,12 +256,26 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512):
         crv.step_batch(ctxs, dts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    for sc, _ in scs:
+    kernels = {}
+    if profile and bucket is not None:
+        ctxs[0].profile_enable(True)
+        crv.step_batch(ctxs, dts)
+        prof = ctxs[0].profile_read()
+        ctxs[0].profile_enable(False)
+        kernels = {name: {"ms_per_step": ms, "launches_per_step": n,
+                          "us_per_launch": 1e3 * ms / n, "scenarios_per_launch": len(seeds)}
+                   for name, (ms, n) in prof.items() if n}
+    for sc in ctxs:
         pf, scf, _ = sc.fields()
         assert np.all(np.isfinite(pf)) and np.all(np.isfinite(scf))
-        sc.close()
-    return {"value": len(seeds) * steps / elapsed, "scenarios": len(seeds),
-            "ms_per_round": 1e3 * elapsed / steps}
+    if bucket is not None:
+        bucket.close()
+    else:
+        for sc in ctxs:
+            sc.close()
+    out = {"value": len(seeds) * steps / elapsed, "scenarios": len(seeds), "mode": mode,
+           "ms_per_round": 1e3 * elapsed / steps}
+    return (out, kernels) if profile else out
 
 
 def main():
@@ -303,9 +328,13 @@ def main():
     log(f"{args.precision} single scenario, {args.steps} steps (+ event-timed kernels)")
     single, kernels = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain,
                                  not args.no_profile)
-    log(f"{args.precision} batched: {args.batch} scenarios x {args.steps} steps")
-    batched = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
-                          args.pretrain)
+    log(f"{args.precision} batched, one launch per kernel: {args.batch} scenarios x {args.steps} steps")
+    batched, bkern = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
+                                 args.pretrain, profile=True)
+    kernel_rooflines(bkern, prob, args.precision, scenarios=args.batch)
+    log(f"{args.precision} {args.batch} scenarios on their own streams, {args.steps} steps")
+    streams = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
+                          args.pretrain, mode="streams")
     alt = None
     if args.alt_precision:
         log(f"{args.alt_precision}: single scenario and {args.batch} batched, {args.steps} steps")
@@ -381,6 +410,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 / batched["value"],
+        "ms_per_step_is": "1000 / value: the aggregate rate's step time; one batched round "
+                          "(a coupled step of every scenario) takes ms_per_round",
+        "ms_per_round": batched["ms_per_round"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -396,7 +428,10 @@ def main():
         "plain_fp32_single": plain,
         "single": single,
         "batched": batched,
+        "batched_kernels": bkern,
+        "streams_batched": streams,
         "vs_plain": batched["value"] / plain["value"],
+        "vs_single": batched["value"] / single["value"],
         "alt_precision": alt,
         "batch_sweep": sweep,
         "gravity_single": grav,

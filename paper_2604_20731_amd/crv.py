@@ -145,10 +145,11 @@ def workspace_size(cfg: CrvConfig) -> int:
 
 class Scenario:
     """One reservoir scenario: a libcrv context on the current torch stream
-    with a torch-allocated device workspace."""
+    with a torch-allocated device workspace (or the given uint8 device tensor
+    of at least workspace_size(cfg) bytes, 256-byte aligned)."""
 
     def __init__(self, cfg: CrvConfig, log_perm, porosity, wells, theta0, s0_coefs=None,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, workspace=None):
         import torch  # device memory and streams only
         self.cfg = cfg
         self.dim, self.ne, self.r = cfg.dim, cfg.n_elem, cfg.degree
@@ -158,7 +159,12 @@ class Scenario:
         self.m = self.ne - 1
         self.P = param_count(cfg)
         self.ws_bytes = workspace_size(cfg)
-        self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        if workspace is None:
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        else:
+            if workspace.dtype != torch.uint8 or workspace.numel() < self.ws_bytes:
+                raise ValueError(f"workspace must be a uint8 tensor of >= {self.ws_bytes} bytes")
+            self._ws = workspace
         st = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
         self._stream = st
         lp, po = _f64(log_perm).ravel(), _f64(porosity).ravel()
@@ -315,14 +321,46 @@ class Scenario:
 
 
 def step_batch(scenarios, dts):
-    """crv_step_batch: one coupled step for each scenario (each on its own
-    stream, no host wait between them)."""
+    """crv_step_batch: one coupled step for each scenario.  Scenarios of one
+    configuration whose workspaces lie at one stride (a Bucket, or a run of
+    consecutive scenarios of one) step with one launch per kernel; others
+    each on their own stream, with no host wait between them."""
     n = len(scenarios)
     if len(dts) != n:
         raise ValueError("one dt per scenario")
     ctxs = (C.c_void_p * n)(*[sc.ctx for sc in scenarios])
     d = _f64(dts)
     _check(LIB.crv_step_batch(ctxs, _dp(d), n))
+
+
+class Bucket:
+    """Scenarios of one configuration whose workspaces lie at a fixed stride
+    in one device allocation, so that crv_step_batch advances them with one
+    launch per kernel of the coupled step (the scenario index selects the
+    workspace).  All of them run on one stream."""
+
+    def __init__(self, cfg: CrvConfig, problems, device: str = "cuda:0", stream=None):
+        import torch  # device memory and streams only
+        self.cfg = cfg
+        self.stride = (workspace_size(cfg) + 255) // 256 * 256
+        n = len(problems)
+        self._mem = torch.empty(self.stride * n + 256, dtype=torch.uint8, device=device)
+        lead = (-self._mem.data_ptr()) % 256
+        st = stream if stream is not None else torch.cuda.current_stream(self._mem.device)
+        self.scenarios = [
+            Scenario(cfg, p.log_perm, p.porosity, p.wells, p.theta0, p.s0_coefs, device=device,
+                     stream=st, workspace=self._mem[lead + k * self.stride:
+                                                    lead + (k + 1) * self.stride])
+            for k, p in enumerate(problems)]
+
+    def step(self, dts):
+        step_batch(self.scenarios, dts)
+
+    def close(self):
+        for sc in self.scenarios:
+            sc.close()
+        self.scenarios = []
+        self._mem = None
 
 
 def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:

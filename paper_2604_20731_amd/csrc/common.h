@@ -20,6 +20,22 @@ struct Geom {
   int mp;   // padded pitch of interior arrays (multiple of 64)
 };
 
+// Scenario batching.  Scenarios of one configuration whose workspaces lie zb
+// bytes apart advance with one launch per kernel: blockIdx.z selects the
+// scenario and every pointer argument (an address in the first scenario's
+// workspace) moves by blockIdx.z * zb bytes.  n = 1, zb = 0 is a single
+// scenario.  Only kernels whose grid leaves z free take a batch.
+struct Batch {
+  int n = 1;
+  int64_t zb = 0;
+};
+
+template <typename T>
+__device__ inline T* zofs(T* p, int64_t zb) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + uint64_t(blockIdx.z) * uint64_t(zb))
+           : p;
+}
+
 __host__ __device__ inline int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
   for (int i = 0; i < e; ++i) r *= b;

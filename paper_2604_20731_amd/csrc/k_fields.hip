@@ -20,7 +20,9 @@ __global__ __launch_bounds__(256) void k_refresh2(Geom g, const Real* __restrict
                                                   Real inv_mu_g, Real nexp, Real rw_mu, Real rg_mu,
                                                   Real* __restrict__ s_nodal,
                                                   Real* __restrict__ alpha,
-                                                  Real* __restrict__ flux) {
+                                                  Real* __restrict__ flux, int64_t zb) {
+  c = zofs(c, zb); kf = zofs(kf, zb); kv = zofs(kv, zb); perm = zofs(perm, zb);
+  s_nodal = zofs(s_nodal, zb); alpha = zofs(alpha, zb); flux = zofs(flux, zb);
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int n = g.n;
   if (p >= int64_t(n) * n) return;
@@ -79,7 +81,8 @@ __global__ __launch_bounds__(256) void k_refresh3(Geom g, const Real* __restrict
 template <typename Real>
 void launch_refresh(const Geom& g, const Real* s_coefs, const int* kf, const Real* kv,
                     const Real* perm, double mu_w, double mu_g, double nexp, double rho_w,
-                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st) {
+                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st,
+                    Batch bz) {
   const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp);
   const Real rw = Real(rho_w / mu_w), rg = Real(rho_g / mu_g);
   if (g.dim == 3) {
@@ -92,11 +95,11 @@ void launch_refresh(const Geom& g, const Real* s_coefs, const int* kf, const Rea
     return;
   }
   const int64_t tot = int64_t(g.n) * g.n;
-  dim3 grid(cdiv(tot, 256));
+  dim3 grid(cdiv(tot, 256), 1, bz.n);
   switch (g.r) {
-    case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
-    case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
-    default: k_refresh2<Real, 3><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux); break;
+    case 1: k_refresh2<Real, 1><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux, bz.zb); break;
+    case 2: k_refresh2<Real, 2><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux, bz.zb); break;
+    default: k_refresh2<Real, 3><<<grid, 256, 0, st>>>(g, s_coefs, kf, kv, perm, iw, ig, ne, rw, rg, s_nodal, alpha, flux, bz.zb); break;
   }
 }
 
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(256) void k_gravity_rhs(int64_t total, int64_t sv, 
                                                      const Real* __restrict__ flux,
                                                      const Real* __restrict__ qi,
                                                      const Real* __restrict__ qp, Real hd,
-                                                     Real gh, Real* __restrict__ hq) {
+                                                     Real gh, Real* __restrict__ hq, int64_t zb) {
+  flux = zofs(flux, zb); qi = zofs(qi, zb); qp = zofs(qp, zb); hq = zofs(hq, zb);
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= total) return;
   Real v = hd * (qi[p] + qp[p]);
@@ -120,13 +124,13 @@ __global__ __launch_bounds__(256) void k_gravity_rhs(int64_t total, int64_t sv, 
 
 template <typename Real>
 void launch_gravity_rhs(const Geom& g, const Real* flux, const Real* qi, const Real* qp,
-                        double gravity, Real* hq, hipStream_t st) {
+                        double gravity, Real* hq, hipStream_t st, Batch bz) {
   const int64_t n = g.n, total = ipow(g.n, g.dim);
   const int64_t sv = g.dim == 3 ? n * n : n;  // stride of the vertical axis
   const double h = 1.0 / g.ne;
-  k_gravity_rhs<Real><<<cdiv(total, 256), 256, 0, st>>>(total, sv, total - sv, flux, qi, qp,
-                                                         Real(std::pow(h, g.dim)),
-                                                         Real(gravity * std::pow(h, g.dim - 1)), hq);
+  k_gravity_rhs<Real><<<dim3(cdiv(total, 256), 1, bz.n), 256, 0, st>>>(
+      total, sv, total - sv, flux, qi, qp, Real(std::pow(h, g.dim)),
+      Real(gravity * std::pow(h, g.dim - 1)), hq, bz.zb);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,7 +141,8 @@ template <typename Real>
 __global__ __launch_bounds__(256) void k_residual2(Geom g, const Real* __restrict__ u,
                                                    const Real* __restrict__ alpha,
                                                    const Real* __restrict__ hq,
-                                                   Real* __restrict__ res) {
+                                                   Real* __restrict__ res, int64_t zb) {
+  u = zofs(u, zb); alpha = zofs(alpha, zb); hq = zofs(hq, zb); res = zofs(res, zb);
   const int ii = blockIdx.x * 64 + (threadIdx.x & 63);  // interior column 0..m-1
   const int jj = blockIdx.y * 4 + (threadIdx.x >> 6);   // interior row
   if (ii >= g.m || jj >= g.m) return;
@@ -171,14 +176,14 @@ __global__ __launch_bounds__(256) void k_residual3(Geom g, const Real* __restric
 
 template <typename Real>
 void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real* hq, Real* res,
-                     hipStream_t st) {
+                     hipStream_t st, Batch bz) {
   if (g.dim == 3) {
     dim3 grid3(cdiv(g.m, 64), cdiv(g.m, 4), g.m);
     k_residual3<Real><<<grid3, 256, 0, st>>>(g, u, alpha, hq, Real(1.0 / g.ne), res);
     return;
   }
-  dim3 grid(cdiv(g.m, 64), cdiv(g.m, 4));
-  k_residual2<Real><<<grid, 256, 0, st>>>(g, u, alpha, hq, res);
+  dim3 grid(cdiv(g.m, 64), cdiv(g.m, 4), bz.n);
+  k_residual2<Real><<<grid, 256, 0, st>>>(g, u, alpha, hq, res, bz.zb);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,7 +314,8 @@ void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real
 template <typename Real, int R>
 __global__ __launch_bounds__(256) void k_project2(Geom g, const Real* __restrict__ u,
                                                   const Real* __restrict__ qv,
-                                                  Real* __restrict__ b) {
+                                                  Real* __restrict__ b, int64_t zb) {
+  u = zofs(u, zb); qv = zofs(qv, zb); b = zofs(b, zb);
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int nb = g.nb;
   if (idx >= int64_t(nb) * nb) return;
@@ -364,7 +370,8 @@ __global__ __launch_bounds__(256) void k_project3(Geom g, const Real* __restrict
 }
 
 template <typename Real>
-void launch_project(const Geom& g, const Real* u, const Real* qv, Real* b, hipStream_t st) {
+void launch_project(const Geom& g, const Real* u, const Real* qv, Real* b, hipStream_t st,
+                    Batch bz) {
   if (g.dim == 3) {
     dim3 grid3(cdiv(ipow(g.nb, 3), 256));
     switch (g.r) {
@@ -374,11 +381,11 @@ void launch_project(const Geom& g, const Real* u, const Real* qv, Real* b, hipSt
     }
     return;
   }
-  dim3 grid(cdiv(int64_t(g.nb) * g.nb, 256));
+  dim3 grid(cdiv(int64_t(g.nb) * g.nb, 256), 1, bz.n);
   switch (g.r) {
-    case 1: k_project2<Real, 1><<<grid, 256, 0, st>>>(g, u, qv, b); break;
-    case 2: k_project2<Real, 2><<<grid, 256, 0, st>>>(g, u, qv, b); break;
-    default: k_project2<Real, 3><<<grid, 256, 0, st>>>(g, u, qv, b); break;
+    case 1: k_project2<Real, 1><<<grid, 256, 0, st>>>(g, u, qv, b, bz.zb); break;
+    case 2: k_project2<Real, 2><<<grid, 256, 0, st>>>(g, u, qv, b, bz.zb); break;
+    default: k_project2<Real, 3><<<grid, 256, 0, st>>>(g, u, qv, b, bz.zb); break;
   }
 }
 
@@ -394,7 +401,10 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
     const Real* __restrict__ perm, const Real* __restrict__ poro, const Real* __restrict__ qi,
     const Real* __restrict__ qp, const Real* __restrict__ gb, const Real* __restrict__ gdb,
     const Real* __restrict__ gxi, const Real* __restrict__ gw, const double* __restrict__ tau_dev,
-    Real inv_mu_w, Real inv_mu_g, Real nexp, Real gshift, Real* __restrict__ b) {
+    Real inv_mu_w, Real inv_mu_g, Real nexp, Real gshift, Real* __restrict__ b, int64_t zb) {
+  sc = zofs(sc, zb); pc = zofs(pc, zb); perm = zofs(perm, zb); poro = zofs(poro, zb);
+  qi = zofs(qi, zb); qp = zofs(qp, zb); gb = zofs(gb, zb); gdb = zofs(gdb, zb);
+  gxi = zofs(gxi, zb); gw = zofs(gw, zb); tau_dev = zofs(tau_dev, zb); b = zofs(b, zb);
   const Real tau = Real(*tau_dev);
   constexpr int NG = R + 1;          // Gauss points per element and axis
   constexpr int TE = TC + R;         // elements per tile and axis
@@ -724,7 +734,7 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
                          const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
                          double mu_w, double mu_g, double nexp, double gshift, Real* b,
-                         hipStream_t st) {
+                         hipStream_t st, Batch bz) {
   const double* t = tau;
   const Real iw = Real(1.0 / mu_w), ig = Real(1.0 / mu_g), ne = Real(nexp), gs = Real(gshift);
   if (g.dim == 3) {
@@ -739,16 +749,16 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
   constexpr bool big = sizeof(Real) == 8;
   if (g.r == 1) {
     constexpr int TC = 16;
-    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 1, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC), bz.n);
+    k_ads_assemble2<Real, 1, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, bz.zb);
   } else if (g.r == 2) {
     constexpr int TC = big ? 8 : 16;
-    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 2, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC), bz.n);
+    k_ads_assemble2<Real, 2, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, bz.zb);
   } else {
     constexpr int TC = 8;
-    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC));
-    k_ads_assemble2<Real, 3, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b);
+    dim3 grid(cdiv(g.nb, TC), cdiv(g.nb, TC), bz.n);
+    k_ads_assemble2<Real, 3, TC><<<grid, TC * TC, 0, st>>>(g, s, p, perm, poro, qi, qp, gb, gdb, gxi, gw, t, iw, ig, ne, gs, b, bz.zb);
   }
 }
 
@@ -829,6 +839,25 @@ __global__ void k_set_f64(double* p, double v) {
 
 void launch_set_f64(double* p, double v, hipStream_t st) { k_set_f64<<<1, 64, 0, st>>>(p, v); }
 
+// one value per scenario of a batch: p + k zb bytes <- v[k]
+struct F64Batch {
+  double v[64];
+};
+__global__ void k_set_f64_batch(double* p, int64_t zb, int n, F64Batch vals) {
+  const int k = threadIdx.x;
+  if (blockIdx.x == 0 && k < n)
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(p) + int64_t(k) * zb) = vals.v[k];
+}
+void launch_set_f64_batch(double* p, int64_t zb, const double* v, int n, hipStream_t st) {
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    F64Batch vals{};
+    const int cnt = n - k0 < 64 ? n - k0 : 64;
+    for (int k = 0; k < cnt; ++k) vals.v[k] = v[k0 + k];
+    k_set_f64_batch<<<1, 64, 0, st>>>(
+        reinterpret_cast<double*>(reinterpret_cast<char*>(p) + int64_t(k0) * zb), zb, cnt, vals);
+  }
+}
+
 __global__ void k_bump(long long* t) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *t = *t + 1;
 }
@@ -857,36 +886,40 @@ void launch_convert(const Src* in, Dst* out, size_t n, hipStream_t st) {
 }
 
 template <typename Real>
-__global__ void k_check_finite(const Real* p, size_t n, int* flag) {
+__global__ void k_check_finite(const Real* p, size_t n, int* flag, int64_t zb) {
+  p = zofs(p, zb);
+  flag = zofs(flag, zb);
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n && !isfinite(p[i])) *flag = 1;
 }
 template <typename Real>
-void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st) {
+void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st, Batch bz) {
   if (n == 0) return;
-  k_check_finite<Real><<<cdiv(n, 256), 256, 0, st>>>(p, n, flag);
+  k_check_finite<Real><<<dim3(cdiv(n, 256), 1, bz.n), 256, 0, st>>>(p, n, flag, bz.zb);
 }
 
 #define CRV_INST(R)                                                                              \
   template void launch_refresh<R>(const Geom&, const R*, const int*, const R*, const R*, double, \
-                                  double, double, double, double, R*, R*, R*, hipStream_t);      \
+                                  double, double, double, double, R*, R*, R*, hipStream_t,       \
+                                  Batch);                                                        \
   template void launch_gravity_rhs<R>(const Geom&, const R*, const R*, const R*, double, R*,     \
-                                      hipStream_t);                                              \
-  template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t);  \
+                                      hipStream_t, Batch);                                       \
+  template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t,   \
+                                   Batch);                                                       \
   template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t); \
   template void launch_loss_finalize<R>(const R*, int, double*, int, const long long*, int,      \
                                         hipStream_t);                                            \
   template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, const R*, double, \
                                        R*, hipStream_t);                                         \
-  template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t);             \
+  template void launch_project<R>(const Geom&, const R*, const R*, R*, hipStream_t, Batch);      \
   template void launch_ads_assemble<R>(const Geom&, const R*, const R*, const R*, const R*,      \
                                        const R*, const R*, const R*, const R*, const R*,         \
                                        const R*, const double*, double, double, double, double,  \
-                                       R*, hipStream_t);                                         \
+                                       R*, hipStream_t, Batch);                                  \
   template void launch_factor_band<R>(const double*, int, int, double*, R*, R*, int*, hipStream_t); \
   template void launch_factor_shifted<R>(const double*, int, int, int, double, R*, R*, hipStream_t); \
   template void launch_fill<R>(R*, size_t, R, hipStream_t);                                      \
-  template void launch_check_finite<R>(const R*, size_t, int*, hipStream_t);
+  template void launch_check_finite<R>(const R*, size_t, int*, hipStream_t, Batch);
 
 CRV_INST(float)
 CRV_INST(double)

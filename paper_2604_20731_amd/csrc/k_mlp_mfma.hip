@@ -389,7 +389,9 @@ __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::fe
 template <int W, int L, int MODE, int DIM>
 __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __restrict__ th,
                                                       const typename MM<MODE>::felem* __restrict__ frag,
-                                                      float* __restrict__ u, long long* t_bump) {
+                                                      float* __restrict__ u, long long* t_bump,
+                                                      int64_t zb) {
+  th = zofs(th, zb); frag = zofs(frag, zb); u = zofs(u, zb); t_bump = zofs(t_bump, zb);
   constexpr int NR = W / 4;
   using SM = Small<W, L, DIM>;
   if (t_bump && blockIdx.x == 0 && threadIdx.x == 0) *t_bump = *t_bump + 1;  // new Adam iteration
@@ -457,7 +459,10 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
                                                              const float* __restrict__ alpha,
                                                              const float* __restrict__ res,
                                                              float* __restrict__ partials,
-                                                             float* __restrict__ loss_part) {
+                                                             float* __restrict__ loss_part,
+                                                             int64_t zb) {
+  th = zofs(th, zb); frag = zofs(frag, zb); qg = zofs(qg, zb); alpha = zofs(alpha, zb);
+  res = zofs(res, zb); partials = zofs(partials, zb); loss_part = zofs(loss_part, zb);
   using T = MM<MODE>;
   using BS = BwdShape<W, L, MODE, DIM, NW>;
   using E = typename BS::E;
@@ -747,7 +752,10 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
     float* __restrict__ m, float* __restrict__ v, double lr, double b1, double b2, double eps,
     const long long* __restrict__ t_dev, int dim, int W, int hidden,
     typename MM<MODE>::felem* __restrict__ frag, const float* __restrict__ loss_part, int loss_np,
-    double* __restrict__ hist, int cap) {
+    double* __restrict__ hist, int cap, int64_t zb) {
+  part = zofs(part, zb); th = zofs(th, zb); m = zofs(m, zb); v = zofs(v, zb);
+  t_dev = zofs(t_dev, zb); frag = zofs(frag, zb); loss_part = zofs(loss_part, zb);
+  hist = zofs(hist, zb);
   __shared__ f32x4_t red[4 * RW][16];
   if (blockIdx.x == gridDim.x - 1) {
     __shared__ double lb[64 * RW];
@@ -822,13 +830,13 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t
                              float* m, float* v, double lr, double b1, double b2, double eps,
                              const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
-                             int cap, hipStream_t st) {
-  const int blocks = cdiv(P, 64) + 1;
+                             int cap, hipStream_t st, Batch bz) {
+  const dim3 blocks(cdiv(P, 64) + 1, 1, bz.n);
   if (mode == NET_MIX) mode = NET_X3;  // same fragments
 #define CRV_RA(MM_, TT)                                                                           \
   k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, ldp, theta, m, v, lr, b1, b2, eps, \
                                                   t_dev, dim, width, hidden, static_cast<TT*>(frag), \
-                                                  loss_part, loss_np, loss_hist, cap)
+                                                  loss_part, loss_np, loss_hist, cap, bz.zb)
   if (mode == NET_F32) CRV_RA(NET_F32, float);
   else if (mode == NET_BF16) CRV_RA(NET_BF16, __bf16);
   else CRV_RA(NET_X3, __bf16);
@@ -837,17 +845,18 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t
 
 template <int W, int L, int MODE>
 static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u, long long* tb,
-                     hipStream_t st) {
+                     hipStream_t st, Batch bz) {
   const int64_t total = ipow(g.n, g.dim);
   const int64_t tiles = (total + 15) / 16;
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
+  const dim3 grid(cdiv(tiles, 4), 1, bz.n);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_fwd_mfma<W, L, MODE, 3><<<cdiv(tiles, 4), 256, 0, st>>>(g, th, fr, u, tb);
+      k_mlp_fwd_mfma<W, L, MODE, 3><<<grid, 256, 0, st>>>(g, th, fr, u, tb, bz.zb);
       return;
     }
   }
-  k_mlp_fwd_mfma<W, L, MODE, 2><<<cdiv(tiles, 4), 256, 0, st>>>(g, th, fr, u, tb);
+  k_mlp_fwd_mfma<W, L, MODE, 2><<<grid, 256, 0, st>>>(g, th, fr, u, tb, bz.zb);
 }
 
 // instantiated shapes: the forward of the mixed form is the split-bf16 one;
@@ -867,10 +876,11 @@ static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u,
   X(128, 4, NET_MIX)
 
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
-                             const void* frag, float* u, long long* t_bump, hipStream_t st) {
+                             const void* frag, float* u, long long* t_bump, hipStream_t st,
+                             Batch bz) {
   if (mode == NET_MIX) mode = NET_X3;  // the forward of the mixed form is split bf16
 #define CRV_FW(WW, LL, MM_) \
-  if (width == WW && hidden == LL && mode == MM_) return fwd_inst<WW, LL, MM_>(g, theta, frag, u, t_bump, st);
+  if (width == WW && hidden == LL && mode == MM_) return fwd_inst<WW, LL, MM_>(g, theta, frag, u, t_bump, st, bz);
   CRV_FWD_SHAPES(CRV_FW)
 #undef CRV_FW
 }
@@ -931,27 +941,28 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t ldp, const float* th, const void* frag, const float* q,
                      const float* alpha, const float* res, float* partials, float* loss_part,
-                     int blocks, hipStream_t st) {
+                     int blocks, hipStream_t st, Batch bz) {
   constexpr int NW = bwd_nw(W, MODE);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
+  const dim3 grid(blocks, 1, bz.n);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<blocks, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
-                                                                    partials, loss_part);
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<grid, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
+                                                                  partials, loss_part, bz.zb);
       return;
     }
   }
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<blocks, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
-                                                                partials, loss_part);
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<grid, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
+                                                              partials, loss_part, bz.zb);
 }
 
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
-                              float* loss_part, int blocks, hipStream_t st) {
+                              float* loss_part, int blocks, hipStream_t st, Batch bz) {
 #define CRV_BW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) \
-    return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, st);
+    return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, st, bz);
   CRV_BWD_SHAPES(CRV_BW)
 #undef CRV_BW
 }

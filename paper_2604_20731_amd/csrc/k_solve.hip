@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
                                                    int nlines, int64_t line_stride,
                                                    const Real* __restrict__ lt,
                                                    const Real* __restrict__ invd, int64_t cs,
-                                                   int64_t csd) {
+                                                   int64_t csd, int64_t zb) {
+  b = zofs(b, zb); x = zofs(x, zb); lt = zofs(lt, zb); invd = zofs(invd, zb);
   constexpr int S = (P % 2 == 0) ? P + 1 : P;
   __shared__ Real buf[4][64 * S];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -208,10 +209,10 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
 template <typename Real, int R>
 static void band_rows_dispatch(int P, const Real* b, Real* x, int n, int nlines, int64_t ls,
                                const Real* lt, const Real* invd, int64_t cs, int64_t csd,
-                               hipStream_t st) {
-  dim3 grid(cdiv(nlines, 4));
+                               hipStream_t st, Batch bz) {
+  dim3 grid(cdiv(nlines, 4), 1, bz.n);
 #define CRV_P(PP) \
-  case PP: k_band_rows<Real, R, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, ls, lt, invd, cs, csd); break;
+  case PP: k_band_rows<Real, R, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, ls, lt, invd, cs, csd, bz.zb); break;
   switch (P) {
     CRV_P(1) CRV_P(2) CRV_P(3) CRV_P(4) CRV_P(5) CRV_P(8) CRV_P(9) CRV_P(12) CRV_P(16) CRV_P(17)
     default: break;
@@ -258,7 +259,8 @@ __global__ __launch_bounds__(256) void k_tridiag_rows(const Real* __restrict__ b
                                                       Real* __restrict__ x, int n, int nlines,
                                                       int64_t ls, const Real* __restrict__ lt,
                                                       const Real* __restrict__ invd, int64_t cs,
-                                                      int64_t csd, bool vec) {
+                                                      int64_t csd, bool vec, int64_t zb) {
+  b = zofs(b, zb); x = zofs(x, zb); lt = zofs(lt, zb); invd = zofs(invd, zb);
   const int lane = threadIdx.x & 63;
   const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (line >= nlines) return;  // the wave leaves as a whole; no block barriers here
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(256) void k_tridiag_rows(const Real* __restrict__ b
 template <typename Real>
 void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t coef_stride,
-                      int64_t coef_stride_d, hipStream_t st) {
+                      int64_t coef_stride_d, hipStream_t st, Batch bz) {
   const int P = pick_p(n);
   if (P < 0 || nlines <= 0) return;
   if (r == 1 && coef_stride > 0 && coef_stride_d > 0) {
@@ -338,9 +340,9 @@ void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_st
                      span <= line_stride && span <= coef_stride && span <= coef_stride_d &&
                      reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(lt) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(inv_d) % 16 == 0;
-    dim3 grid(cdiv(nlines, 4));
+    dim3 grid(cdiv(nlines, 4), 1, bz.n);
 #define CRV_T(PP) \
-  case PP: k_tridiag_rows<Real, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, vec); return;
+  case PP: k_tridiag_rows<Real, PP><<<grid, 256, 0, st>>>(b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, vec, bz.zb); return;
     switch (P) {
       CRV_T(1) CRV_T(2) CRV_T(3) CRV_T(4) CRV_T(5) CRV_T(8) CRV_T(9) CRV_T(12) CRV_T(16) CRV_T(17)
       default: break;
@@ -348,9 +350,9 @@ void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_st
 #undef CRV_T
   }
   switch (r) {
-    case 1: band_rows_dispatch<Real, 1>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
-    case 2: band_rows_dispatch<Real, 2>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
-    default: band_rows_dispatch<Real, 3>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st); break;
+    case 1: band_rows_dispatch<Real, 1>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st, bz); break;
+    case 2: band_rows_dispatch<Real, 2>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st, bz); break;
+    default: band_rows_dispatch<Real, 3>(P, b, x, n, nlines, line_stride, lt, inv_d, coef_stride, coef_stride_d, st, bz); break;
   }
 }
 
@@ -493,8 +495,15 @@ static void band_cols_dispatch(const Real* b, Real* x, int n, int nlines, int64_
 template <typename Real>
 void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t batch, int64_t batch_stride,
-                      hipStream_t st) {
+                      hipStream_t st, Batch bz) {
   if (nlines <= 0) return;
+  if (bz.n > 1) {
+    // scenarios of a batch are the planes of the launch (2D passes have one
+    // plane); the factors are the same table in every scenario's workspace
+    if (batch != 1) return;
+    batch = bz.n;
+    batch_stride = bz.zb / int64_t(sizeof(Real));
+  }
   switch (r) {
     case 1: band_cols_dispatch<Real, 1>(b, x, n, nlines, row_stride, lt, inv_d, batch, batch_stride, st); break;
     case 2: band_cols_dispatch<Real, 2>(b, x, n, nlines, row_stride, lt, inv_d, batch, batch_stride, st); break;
@@ -725,9 +734,9 @@ void launch_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int
 
 #define CRV_INST(R)                                                                            \
   template void launch_band_rows<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
-                                    int64_t, int64_t, hipStream_t);                           \
+                                    int64_t, int64_t, hipStream_t, Batch);                    \
   template void launch_band_cols<R>(const R*, R*, int, int, int64_t, int, const R*, const R*, \
-                                    int64_t, int64_t, hipStream_t);                           \
+                                    int64_t, int64_t, hipStream_t, Batch);                    \
   template void launch_gemm<R>(int, int, int, const R*, int, const R*, int, R*, int, hipStream_t, \
                                const R*);                                                     \
   template void launch_gemm_batched<R>(int, int, int, const R*, int, const R*, int, int64_t, R*, \

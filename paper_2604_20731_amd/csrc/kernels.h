@@ -11,17 +11,18 @@ namespace crv {
 template <typename Real>
 void launch_refresh(const Geom& g, const Real* s_coefs, const int* knot_first, const Real* knot_val,
                     const Real* perm, double mu_w, double mu_g, double nexp, double rho_w,
-                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st);
+                    double rho_g, Real* s_nodal, Real* alpha, Real* flux, hipStream_t st,
+                    Batch bz = Batch{});
 // pressure right-hand side with gravity (g = -gravity e_v, e_v = y in 2D, z in
 // 3D): hq = h^d (qi + qp) + gravity h^(d-1) (F_{p+e_v} - F_p)
 template <typename Real>
 void launch_gravity_rhs(const Geom& g, const Real* flux, const Real* qi, const Real* qp,
-                        double gravity, Real* hq, hipStream_t st);
+                        double gravity, Real* hq, hipStream_t st, Batch bz = Batch{});
 
 // a3: RES on the interior nodes (padded layout, pitch mp).
 template <typename Real>
 void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real* hq, Real* res,
-                     hipStream_t st);
+                     hipStream_t st, Batch bz = Batch{});
 
 // a5: g_u = 2 A^T q (zero on the boundary) and per-block partial sums of RES.q.
 // Returns the number of partials written.
@@ -45,7 +46,8 @@ void launch_grad_logperm(const Geom& g, const Real* u, const Real* q, const Real
 
 // a8: b_kl = int I_h(u) B_kl (Q1 nodal interpolant, exact Gauss).
 template <typename Real>
-void launch_project(const Geom& g, const Real* u, const Real* proj_val, Real* b, hipStream_t st);
+void launch_project(const Geom& g, const Real* u, const Real* proj_val, Real* b, hipStream_t st,
+                    Batch bz = Batch{});
 
 // a10: b_kl = int [S B_kl + tau/phi (-lambda_g K (grad p - rho_g g) . grad B_kl + q_g B_kl)];
 // gshift = rho_g gravity is added to the vertical derivative of p (g = -gravity e_v);
@@ -55,7 +57,7 @@ void launch_ads_assemble(const Geom& g, const Real* s, const Real* p, const Real
                          const Real* poro, const Real* qi, const Real* qp, const Real* gb,
                          const Real* gdb, const Real* gxi, const Real* gw, const double* tau,
                          double mu_w, double mu_g, double nexp, double gshift, Real* b,
-                         hipStream_t st);
+                         hipStream_t st, Batch bz = Batch{});
 
 // ---- IGA Galerkin pressure system, 2D (k_galerkin.hip; eq. 15-20) --------
 // Device arrays of one solve (owned by the context): Gauss-point arrays
@@ -109,13 +111,15 @@ void launch_factor_shifted(const double* shifts, int nlines, int m, int mp, doub
 
 // *p = v on the stream (device memory, no host synchronisation)
 void launch_set_f64(double* p, double v, hipStream_t st);
+// the same for n scenarios: *(p + k zb bytes) = v[k], k < n
+void launch_set_f64_batch(double* p, int64_t zb, const double* v, int n, hipStream_t st);
 template <typename Real>
 void launch_fill(Real* p, size_t n, Real v, hipStream_t st);
 template <typename Src, typename Dst>
 void launch_convert(const Src* in, Dst* out, size_t n, hipStream_t st);
 // non-finite check: sets *flag = 1 if any entry is NaN/Inf
 template <typename Real>
-void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st);
+void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st, Batch bz = Batch{});
 
 // ---- solves (k_solve.hip) --------------------------------------------------
 // Banded unit-lower L D L^T solves along contiguous lines: one wavefront per
@@ -125,13 +129,14 @@ void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st);
 template <typename Real>
 void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t coef_stride,
-                      int64_t coef_stride_d, hipStream_t st);
+                      int64_t coef_stride_d, hipStream_t st, Batch bz = Batch{});
 // Same solve along strided lines (element j of line c at x[j*row_stride + c]),
-// one thread per line, shared coefficients.
+// shared coefficients, over batch planes batch_stride apart.  A scenario batch
+// (2D passes only, batch = 1) takes the place of the planes.
 template <typename Real>
 void launch_band_cols(const Real* b, Real* x, int n, int nlines, int64_t row_stride, int r,
                       const Real* lt, const Real* inv_d, int64_t batch, int64_t batch_stride,
-                      hipStream_t st);
+                      hipStream_t st, Batch bz = Batch{});
 
 // C = A B, row-major, all dims multiples of 64, pitches in elements.
 // a_packed (nullable, float32 only): A as packed matrix-core fragments
@@ -189,7 +194,8 @@ int64_t mlp_fragment_bytes(int width, int hidden);
 void launch_pack_fragments(const float* theta, int dim, int width, int hidden, int mode,
                            void* frag, hipStream_t st);
 void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, const float* theta,
-                             const void* frag, float* u, long long* t_bump, hipStream_t st);
+                             const void* frag, float* u, long long* t_bump, hipStream_t st,
+                             Batch bz = Batch{});
 // backward blocks: at most cu_count x the blocks per CU that one block's LDS
 // allows; with query, also capped by the occupancy the compiled kernel reaches
 int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_count, bool query);
@@ -199,13 +205,13 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
-                              float* loss_part, int blocks, hipStream_t st);
+                              float* loss_part, int blocks, hipStream_t st, Batch bz = Batch{});
 // fixed-order sum of the partial rows + Adam + fragment update; one extra
 // block sums the loss partials into loss_hist[(t-1) % cap]
 void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t ldp, float* theta, float* m,
                              float* v, double lr, double b1, double b2, double eps,
                              const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
-                             int cap, hipStream_t st);
+                             int cap, hipStream_t st, Batch bz = Batch{});
 
 }  // namespace crv

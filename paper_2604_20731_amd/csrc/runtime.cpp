@@ -276,7 +276,25 @@ struct SolverBase {
                                        int* iters, double* relres) = 0;
   virtual crv_status step_galerkin(double dt, int max_iters, double rtol, int precond,
                                    int* iters, double* relres) = 0;
+  // scenario batching (2D float32 matrix-core contexts of one configuration)
+  virtual bool batchable() const { return false; }
+  virtual int64_t batch_tag() const { return 0; }
+  virtual crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb) {
+    (void)all, (void)dts, (void)n, (void)zb;
+    return fail(CRV_EINVAL, "this context cannot run a batched step");
+  }
 };
+
+// the fields of two configurations are all equal
+static bool same_config(const crv_config& a, const crv_config& b) {
+  return a.dim == b.dim && a.n_elem == b.n_elem && a.degree == b.degree && a.width == b.width &&
+         a.hidden == b.hidden && a.precision == b.precision && a.mu_w == b.mu_w &&
+         a.mu_g == b.mu_g && a.relperm_exp == b.relperm_exp && a.lr == b.lr &&
+         a.beta1 == b.beta1 && a.beta2 == b.beta2 && a.eps == b.eps &&
+         a.adam_iters == b.adam_iters && a.substeps == b.substeps &&
+         a.well_radius == b.well_radius && a.gravity == b.gravity && a.rho_w == b.rho_w &&
+         a.rho_g == b.rho_g;
+}
 
 template <typename Real>
 struct Solver : SolverBase {
@@ -286,6 +304,8 @@ struct Solver : SolverBase {
   bool mfma = false;
   int mode = NET_F32;
   int bwd_blocks = 0;
+  // the scenario batch of the launches being enqueued ({1, 0}: this context)
+  Batch bz{};
 
   // -------- host <-> device helpers --------
   crv_status upload(Real* dst, const double* src, size_t n) {
@@ -434,8 +454,8 @@ struct Solver : SolverBase {
     tb(CRV_K_REFRESH);
     launch_refresh<Real>(g, b.s, b.knot_first, b.knot_val, b.perm, cfg.mu_w, cfg.mu_g,
                          cfg.relperm_exp, cfg.rho_w, cfg.rho_g, b.s_nodal, b.alpha,
-                         gravity() ? b.gflux : nullptr, st);
-    if (gravity()) launch_gravity_rhs<Real>(g, b.gflux, b.qi, b.qp, cfg.gravity, b.hq, st);
+                         gravity() ? b.gflux : nullptr, st, bz);
+    if (gravity()) launch_gravity_rhs<Real>(g, b.gflux, b.qi, b.qp, cfg.gravity, b.hq, st, bz);
     te();
   }
 
@@ -461,14 +481,17 @@ struct Solver : SolverBase {
       te();
       return;
     }
+    // a scenario batch is the batch of the products (the sine basis, the A
+    // operand, is the same table in every scenario's workspace)
+    const int64_t zs = bz.zb / int64_t(sizeof(Real));
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.res, mp, b.rhat, mp, st, b.dst_pk);
+    launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.res, mp, zs, b.rhat, mp, zs, bz.n, st, b.dst_pk);
     te();
     tb(CRV_K_GRAM_LINES);
-    launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, mp, 1, b.g_lt, b.g_invd, mp, mp, st);
+    launch_band_rows<Real>(b.rhat, b.qhat, g.m, g.m, mp, 1, b.g_lt, b.g_invd, mp, mp, st, bz);
     te();
     tb(CRV_K_GRAM_DST);
-    launch_gemm<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, b.q, mp, st, b.dst_pk);
+    launch_gemm_batched<Real>(mp, mp, mp, b.dst, mp, b.qhat, mp, zs, b.q, mp, zs, bz.n, st, b.dst_pk);
     te();
   }
 
@@ -479,11 +502,11 @@ struct Solver : SolverBase {
     const int64_t nb2 = int64_t(nb) * nb;
     tb(CRV_K_MASS_ROWS);
     launch_band_rows<Real>(src, dst, nb, g.dim == 3 ? int(nb2) : nb, nb, g.r, b.m_lt, b.m_invd, 0,
-                           0, st);
+                           0, st, bz);
     te();
     tb(CRV_K_MASS_COLS);
     launch_band_cols<Real>(dst, dst, nb, nb, nb, g.r, b.m_lt, b.m_invd, g.dim == 3 ? nb : 1,
-                           g.dim == 3 ? nb2 : 0, st);
+                           g.dim == 3 ? nb2 : 0, st, bz);
     if (g.dim == 3)
       launch_band_cols<Real>(dst, dst, nb, int(nb2), nb2, g.r, b.m_lt, b.m_invd, 1, 0, st);
     te();
@@ -502,7 +525,7 @@ struct Solver : SolverBase {
     tb(CRV_K_MLP_FWD);
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
-        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, mode, b.theta, b.frag, b.u, t_bump, st);
+        launch_mlp_forward_mfma(g, cfg.width, cfg.hidden, mode, b.theta, b.frag, b.u, t_bump, st, bz);
         te();
         return;
       }
@@ -516,7 +539,7 @@ struct Solver : SolverBase {
   void loss_pass(long long* t_bump) {
     forward(t_bump);
     tb(CRV_K_RESIDUAL);
-    launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st);
+    launch_residual<Real>(g, b.u, b.alpha, b.hq, b.res, st, bz);
     te();
     gram_solve();
     if (mfma) return;
@@ -536,7 +559,7 @@ struct Solver : SolverBase {
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
         launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, ldp(), b.theta, b.frag, b.q, b.alpha,
-                                 b.res, b.partials, b.loss_part, bwd_blocks, st);
+                                 b.res, b.partials, b.loss_part, bwd_blocks, st, bz);
         rows = bwd_blocks;
       }
     }
@@ -562,7 +585,7 @@ struct Solver : SolverBase {
         tb(CRV_K_ADAM);
         launch_reduce_adam_pack(b.partials, rows, P, ldp(), b.theta, b.am, b.av, cfg.lr, cfg.beta1,
                                 cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, mode,
-                                b.frag, b.loss_part, loss_count(), b.loss_hist, kLossCap, st);
+                                b.frag, b.loss_part, loss_count(), b.loss_hist, kLossCap, st, bz);
         te();
         return;
       }
@@ -729,6 +752,8 @@ struct Solver : SolverBase {
   }
 
   ~Solver() override {
+    for (BatchGraph& bg : g_batch) (void)hipGraphExecDestroy(bg.exec);
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
     for (hipGraphExec_t& e : g_gal)
       if (e) (void)hipGraphExecDestroy(e);
     if (gw_mem) (void)hipFree(gw_mem);
@@ -780,7 +805,7 @@ struct Solver : SolverBase {
   void project_into_p() {
     forward();
     tb(CRV_K_PROJECT);
-    launch_project<Real>(g, b.u, b.proj_val, b.bvec, st);
+    launch_project<Real>(g, b.u, b.proj_val, b.bvec, st, bz);
     te();
     mass_solve(b.bvec, b.p);
   }
@@ -790,7 +815,7 @@ struct Solver : SolverBase {
     tb(CRV_K_ADS_ASSEMBLE);
     launch_ads_assemble<Real>(g, b.s, b.p, b.perm, b.poro, b.qi, b.qp, b.gb, b.gdb, b.gxi, b.gw,
                               b.tau, cfg.mu_w, cfg.mu_g, cfg.relperm_exp, cfg.rho_g * cfg.gravity,
-                              b.bvec, st);
+                              b.bvec, st, bz);
     te();
     mass_solve(b.bvec, b.s);
   }
@@ -798,7 +823,7 @@ struct Solver : SolverBase {
   void step_body() {
     project_into_p();
     for (int k = 0; k < cfg.substeps; ++k) substep();
-    launch_check_finite<Real>(b.s, nc, b.flag, st);
+    launch_check_finite<Real>(b.s, nc, b.flag, st, bz);
     refresh();
     for (int i = 0; i < cfg.adam_iters; ++i) iteration();
   }
@@ -824,6 +849,84 @@ struct Solver : SolverBase {
       step_body();
     }
     return check_launch();
+  }
+
+  // ---- batched coupled step ----
+  // Scenarios of this context's configuration whose workspaces lie zb bytes
+  // apart, starting with this one, advance together: every kernel of the step
+  // runs once for all of them (blockIdx.z selects the scenario), replayed
+  // from a graph captured per (count, stride) on this context's stream.  The
+  // kernels reduce in an order that does not depend on the batch, so each
+  // scenario's result is bitwise the one of its own crv_step.
+  struct BatchGraph {
+    int n;
+    int64_t zb;
+    hipGraphExec_t exec;
+  };
+  std::vector<BatchGraph> g_batch;
+  std::vector<hipEvent_t> join_ev;
+
+  bool batchable() const override {
+    return std::is_same<Real, float>::value && mfma && g.dim == 2;
+  }
+  int64_t batch_tag() const override { return bwd_blocks; }
+
+  hipEvent_t join_event(size_t k) {
+    while (join_ev.size() <= k) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+      join_ev.push_back(e);
+    }
+    return join_ev[k];
+  }
+
+  crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb) override {
+    // order after the work already queued on the other scenarios' streams
+    size_t ev = 0;
+    for (int k = 1; k < n; ++k) {
+      if (all[k]->st == st) continue;
+      hipEvent_t e = join_event(ev++);
+      if (!e) return fail(CRV_EHIP, "hipEventCreate failed");
+      CRV_HIP(hipEventRecord(e, all[k]->st));
+      CRV_HIP(hipStreamWaitEvent(st, e, 0));
+    }
+    std::vector<double> taus(static_cast<size_t>(n));
+    for (int k = 0; k < n; ++k) taus[k] = dts[k] / cfg.substeps;
+    launch_set_f64_batch(b.tau, zb, taus.data(), n, st);
+    crv_status s = check_launch();
+    if (s) return s;
+    const Batch one = bz;
+    if (use_graphs()) {
+      hipGraphExec_t exec = nullptr;
+      for (const BatchGraph& bg : g_batch)
+        if (bg.n == n && bg.zb == zb) exec = bg.exec;
+      if (!exec) {
+        bz = Batch{n, zb};
+        s = capture(&exec, [&] { step_body(); });
+        bz = one;
+        if (s) return s;
+        g_batch.push_back(BatchGraph{n, zb, exec});
+      }
+      CRV_HIP(hipGraphLaunch(exec, st));
+    } else {
+      bz = Batch{n, zb};
+      step_body();
+      bz = one;
+    }
+    if ((s = check_launch())) return s;
+    // and the other streams' later work after the batch
+    hipEvent_t done = join_event(ev);
+    if (!done) return fail(CRV_EHIP, "hipEventCreate failed");
+    bool recorded = false;
+    for (int k = 1; k < n; ++k) {
+      if (all[k]->st == st) continue;
+      if (!recorded) {
+        CRV_HIP(hipEventRecord(done, st));
+        recorded = true;
+      }
+      CRV_HIP(hipStreamWaitEvent(all[k]->st, done, 0));
+    }
+    return CRV_OK;
   }
 
   crv_status substeps(double tau, int n) override {
@@ -1132,6 +1235,27 @@ crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
     if (!ctxs[i] || !ctxs[i]->impl) return fail(CRV_EINVAL, "context is NULL");
     if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(CRV_EINVAL, "dt must be > 0");
     if (!ctxs[i]->impl->pretrained) return fail(CRV_ESTATE, "crv_step_batch before crv_pretrain_pressure");
+  }
+  // one batched launch per kernel when every context has the first one's
+  // configuration and the workspaces lie at one stride, in order, without
+  // overlap; otherwise each context steps on its own stream
+  if (n >= 2) {
+    SolverBase& s0 = *ctxs[0]->impl;
+    const char* base = static_cast<const char*>(s0.ws);
+    const int64_t zb = static_cast<const char*>(ctxs[1]->impl->ws) - base;
+    size_t need = 0;
+    crv_workspace_size(&s0.cfg, &need);
+    bool ok = s0.batchable() && zb > 0 && uint64_t(zb) >= need;
+    for (int i = 1; ok && i < n; ++i) {
+      SolverBase& si = *ctxs[i]->impl;
+      ok = si.batchable() && same_config(si.cfg, s0.cfg) && si.batch_tag() == s0.batch_tag() &&
+           static_cast<const char*>(si.ws) == base + int64_t(i) * zb;
+    }
+    if (ok) {
+      std::vector<SolverBase*> all(static_cast<size_t>(n));
+      for (int i = 0; i < n; ++i) all[size_t(i)] = ctxs[i]->impl.get();
+      return s0.step_batched(all.data(), dts, n, zb);
+    }
   }
   for (int i = 0; i < n; ++i) {
     const crv_status s = ctxs[i]->impl->step(dts[i]);
