@@ -317,26 +317,49 @@ struct NoSink {
   __device__ void operator()(int, const H&) const {}
 };
 
+// Layer 1 as a float32 matrix-core product: for row block mb, the 16 x 4
+// operand [W1 | b1 | 0] (2D) or [W1 | b1] (3D) times [z; 1; 0] (4 x 16
+// nodes) gives the pre-activations in the accumulator layout that the next
+// layer reads.  Lane (r = lane%16, q = lane/16) holds A[r][q] and B[q][r].
+template <int W, int L, int DIM>
+struct Layer1 {
+  float a[W / 16];  // this lane's entry of the A operand of each row block
+  __device__ void load(const float* sp, int lane) {
+    using SM = Small<W, L, DIM>;
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int mb = 0; mb < W / 16; ++mb) {
+      const int f = 16 * mb + r;
+      a[mb] = q < DIM ? sp[SM::W1 + f * DIM + q] : (q == DIM ? sp[SM::B1 + f] : 0.f);
+    }
+  }
+};
+
+__device__ inline float layer1_operand(const float* z, int q, int dim) {
+  float v = 0.f;
+  for (int c = 0; c < 3; ++c)
+    if (c < dim && q == c) v = z[c];
+  return q == dim ? 1.f : v;
+}
+
 // Forward of one 16-node tile held by this wave.  The operands that hidden
 // layer l (0-based, l < L-1) feeds into the next product go to sink(l, bop)
 // as soon as they are built; on return h holds the last hidden layer.
 template <int W, int L, int MODE, int DIM, bool PIPE, typename Sink>
 __device__ inline void forward_tile(const float* sp, const typename MM<MODE>::felem* __restrict__ frag,
-                                    const float* z, int q, int lane, float (&h)[W / 4],
-                                    const Sink& sink) {
+                                    const Layer1<W, L, DIM>& l1, const float* z, int q, int lane,
+                                    float (&h)[W / 4], const Sink& sink) {
   using T = MM<MODE>;
   using SM = Small<W, L, DIM>;
-  constexpr int NR = W / 4, NKS = W / T::KS, NMB = W / 16;
+  constexpr int NKS = W / T::KS, NMB = W / 16;
   {
-    const float* W1 = sp + SM::W1;
-    const float* b1 = sp + SM::B1;
+    const float zb = layer1_operand(z, q, DIM);
+    const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-      const int f = cfeat(t, q);
-      float a = b1[f];
+    for (int mb = 0; mb < NMB; ++mb) {
+      const f32x4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(l1.a[mb], zb, zero, 0, 0, 0);
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) a += W1[f * DIM + c] * z[c];
-      h[t] = tanh_of_scaled(a);
+      for (int i = 0; i < 4; ++i) h[4 * mb + i] = tanh_of_scaled(a[i]);
     }
   }
 #pragma unroll
@@ -408,8 +431,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
   if (p < total) node_z<DIM>(p, geo.n, geo.ne, z, &interior);
   else
     for (int c = 0; c < DIM; ++c) z[c] = 0.f;
+  Layer1<W, L, DIM> l1;
+  l1.load(sp, lane);
   float h[NR];
-  forward_tile<W, L, MODE, DIM, true>(sp, frag, z, q, lane, h, NoSink());
+  forward_tile<W, L, MODE, DIM, true>(sp, frag, l1, z, q, lane, h, NoSink());
   const float* wo = sp + SM::WO;
   float s = 0.f;
 #pragma unroll
@@ -430,7 +455,18 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 // output-weight gradient.  Biases, first-layer and output weights are summed
 // over nodes per thread from LDS: thread t owns feature t/4 (+ multiples of
 // NTH/4) and a quarter of the block's nodes.
+// With two copies of Dt (ND = 2) successive uses of it alternate between
+// them, so a use's writes need only the barrier before its reads: the
+// readers of the copy being overwritten passed a later barrier first.  The
+// node data (g_u, coordinates) alternate by block step for the same reason.
 // ---------------------------------------------------------------------------
+// waves per SIMD the register allocation must leave room for: plain-bf16
+// operands at width <= 64 fit three, everything else two
+template <int W, int MODE>
+constexpr int bwd_min_waves() {
+  return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64) ? 3 : 2;
+}
+
 template <int W, int L, int MODE, int DIM, int NW>
 struct BwdShape {
   using T = MM<MODE>;
@@ -438,18 +474,25 @@ struct BwdShape {
   static constexpr int NB = 16 * NW;           // nodes per block step
   static constexpr int LD = NB + T::PAD;       // row pitch of the transposed buffers
   static constexpr int NTH = 64 * NW;
-  static constexpr size_t lds_bytes() {
-    return sizeof(E) * size_t(T::NPL * L * W * LD) +
-           sizeof(float) * size_t(Small<W, L, DIM>::SIZE + NB + DIM * NB + NTH);
+  // LDS of one block with nd copies of the delta tile and the node data
+  static constexpr size_t bytes(int nd) {
+    return sizeof(E) * size_t(T::NPL * ((L - 1) + nd) * W * LD) +
+           sizeof(float) * size_t(Small<W, L, DIM>::SIZE + nd * (NB + DIM * NB) + NTH);
   }
+  // resident blocks per CU with nd copies: what 160 KB of LDS and the
+  // register budget (bwd_min_waves per SIMD) allow (0: does not fit)
+  static constexpr int blocks_per_cu(int nd) {
+    const int by_lds = int((160u * 1024u) / bytes(nd));
+    const int by_regs = bwd_min_waves<W, MODE>() * 4 / NW;
+    const int b = by_lds < by_regs ? by_lds : (by_regs < 1 ? 1 : by_regs);
+    return b > 4 ? 4 : b;
+  }
+  // two copies (one barrier per layer instead of two) whenever they fit and
+  // keep the blocks per CU
+  static constexpr int ND =
+      (blocks_per_cu(2) >= 1 && blocks_per_cu(2) >= blocks_per_cu(1)) ? 2 : 1;
+  static constexpr size_t lds_bytes() { return bytes(ND); }
 };
-
-// waves per SIMD the register allocation must leave room for: plain-bf16
-// operands at width <= 64 fit three, everything else two
-template <int W, int MODE>
-constexpr int bwd_min_waves() {
-  return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64) ? 3 : 2;
-}
 
 template <int W, int L, int MODE, int DIM, int NW>
 __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd_mfma(Geom geo, int64_t ldp,
@@ -474,11 +517,12 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   constexpr int FPT = (W * 4 + NTH - 1) / NTH;  // features per thread
   constexpr int QN = NB / 4;                  // nodes per quarter
   constexpr int HPL = (L - 1) * W * LD, DPL = W * LD;  // plane strides (split storage)
+  constexpr int ND = BS::ND;
   __shared__ __attribute__((aligned(16))) E Hall[T::NPL * HPL];
-  __shared__ __attribute__((aligned(16))) E Dt[T::NPL * DPL];
+  __shared__ __attribute__((aligned(16))) E Dts[ND][T::NPL * DPL];
   __shared__ float sp[SM::SIZE];
-  __shared__ float Gs[NB];
-  __shared__ float Zs[DIM][NB];
+  __shared__ float Gss[ND][NB];
+  __shared__ float Zss[ND][DIM][NB];
   __shared__ float Red[NTH];
 
   // When a wave's tiles do not start a row block at a fixed slot (OWN not a
@@ -494,6 +538,8 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   const int q4 = tid & 3;
   SM::stage(th, sp, tid, NTH);
   __syncthreads();
+  Layer1<W, L, DIM> l1;
+  l1.load(sp, lane);
   const int64_t total = ipow(geo.n, DIM);
   const int64_t nsteps = (total + NB - 1) / NB;
   const float* wo = sp + SM::WO;
@@ -526,7 +572,11 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
         T::lds_put_elem(Hall + (l * W + cfeat(ks * T::S + v, q)) * LD + col, HPL, bo[ks], v);
   };
 
+  int ub = 0, gb = 0;  // copy of Dt for the next use; copy of the node data
   for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
+    E* Dt = Dts[ub];
+    float* Gs = Gss[gb];
+    float(*Zs)[NB] = Zss[gb];
     // the weight fragments are re-read from cache each step: an opaque copy
     // of the pointer keeps the compiler from hoisting every fragment of every
     // layer into registers for the whole loop (which only spills them).  Up
@@ -550,11 +600,12 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
     if (valid) node_z<DIM>(p, geo.n, geo.ne, z, &interior);
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
-    float d[NR];
-    forward_tile<W, L, MODE, DIM, (W <= 64)>(sp, fr, z, q, lane, d, sink);
+    // the adjoint's loads first: their latency hides behind the recompute
     int64_t iq = -1;
     const float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
     if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
+    float d[NR];
+    forward_tile<W, L, MODE, DIM, (W <= 64)>(sp, fr, l1, z, q, lane, d, sink);
     if (q == 0) {
       Gs[col] = gv;
 #pragma unroll
@@ -583,9 +634,13 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
       for (int k = 0; k < QN; ++k) s += Gs[tid * QN + k];
       s_bout += s;
     }
-    __syncthreads();
+    if constexpr (ND == 1) __syncthreads();
 #pragma unroll
     for (int l = L; l >= 1; --l) {
+      if constexpr (ND == 2) {
+        ub ^= 1;
+        Dt = Dts[ub];
+      }
       // delta_l into Dt; for l >= 2 as the split operands the chain below uses
       typename T::op bop[NKS];
       if (l >= 2) {
@@ -659,7 +714,11 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
           }
         }
       }
-      __syncthreads();  // Dt (and Hall in the next step) are rewritten
+      if constexpr (ND == 1) __syncthreads();  // Dt (and Hall in the next step) are rewritten
+    }
+    if constexpr (ND == 2) {
+      ub ^= 1;
+      gb ^= 1;
     }
   }
 
