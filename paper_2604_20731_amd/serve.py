@@ -15,7 +15,9 @@ so a scenario's results are the same alone and in any mix.
 
 Reported: scenarios/s (completed / span from first arrival to last
 completion), p50/p99 latency of a coupled step (GPU time from the moment the
-step reaches the head of its stream to its completion), queue waits.
+step reaches the head of its stream to its completion), queue waits, the
+largest number of scenarios active at once, and the arrivals refused because
+their workspace alone exceeds the HBM budget.
 """
 from __future__ import annotations
 
@@ -89,7 +91,10 @@ class Server:
         pending = deque(sorted(arrivals, key=lambda a: a.t))
         active: List[Job] = []
         results = {}
+        refused = []
         used = 0
+        most_active = 0
+        peak_bytes = 0
         waits, lat = [], []
         t0 = time.perf_counter()
         first_arrival = pending[0].t if pending else 0.0
@@ -103,6 +108,11 @@ class Server:
                 cfg = crv.config(dim=2, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
                                  hidden=prob.hidden, precision=self.precision_for(prob.width))
                 ws = crv.workspace_size(cfg)
+                if ws > self.budget:
+                    # can never fit: refuse it rather than wait for memory
+                    # that no retirement frees
+                    refused.append(pending.popleft().seed)
+                    continue
                 if used + ws > self.budget:
                     break
                 pending.popleft()
@@ -116,6 +126,8 @@ class Server:
                 job.ev_end = torch.cuda.Event()
                 job.ev_end.record(stream)
                 active.append(job)
+                most_active = max(most_active, len(active))
+                peak_bytes = max(peak_bytes, used)
             # ---- progress: every job whose in-flight work finished moves on
             progressed = False
             for job in list(active):
@@ -161,5 +173,8 @@ class Server:
             "mean_queue_wait_s": float(np.mean(waits)) if waits else 0.0,
             "max_queue_wait_s": float(np.max(waits)) if waits else 0.0,
             "span_s": span,
+            "max_active_seen": most_active,
+            "peak_workspace_bytes": peak_bytes,
+            "refused": refused,
             "results": results,
         }

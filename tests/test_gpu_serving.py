@@ -10,28 +10,39 @@ from paper_2604_20731_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _mix():
+def _mix(big=False):
+    """Arrivals 2 ms apart; with big, one 256^2 scenario and one of width 128
+    join the small ones (quadratic elements, 4 hidden layers)."""
+    shapes = [(32, 32, 1), (64, 64, 3), (32, 64, 5), (64, 32, 2), (48, 64, 8), (64, 64, 4)]
+    if big:
+        shapes = [(256, 64, 5), (32, 32, 1), (64, 128, 3), (64, 64, 2), (48, 64, 8)]
     arr = []
     t = 0.0
-    for k, (ne, w, nw) in enumerate([(32, 32, 1), (64, 64, 3), (32, 64, 5), (64, 32, 2),
-                                     (48, 64, 8), (64, 64, 4)]):
+    for k, (ne, w, nw) in enumerate(shapes):
         arr.append(inputs.Arrival(t=t, n_elem=ne, width=w, seed=100 + k, n_wells=nw))
         t += 0.002
     return arr
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
-def test_alone_equals_mix(prec):
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,big", [("bf16x3f", False), ("bf16x3f", True), ("bf16x3", False),
+                                      ("fp32", False)])
+def test_alone_equals_mix(prec, big):
+    """The default served form (the mixed network) included, with a 256^2
+    scenario and a width-128 one in the mix; the mix must actually overlap
+    (two or more scenarios active at once)."""
     from paper_2604_20731_amd.serve import Server
-    arrivals = _mix()
-    srv = Server(hbm_budget_bytes=1 << 30, max_active=4, precision=prec, pretrain_iters=30,
+    arrivals = _mix(big)
+    srv = Server(hbm_budget_bytes=4 << 30, max_active=4, precision=prec, pretrain_iters=30,
                  steps=3, keep_fields=True)
     mix = srv.run(arrivals)
-    say(f"mix {prec}: {mix['scenarios']} scenarios, {mix['scenarios_per_s']:.1f}/s, "
-        f"p50 {mix['p50_step_ms']:.2f} ms p99 {mix['p99_step_ms']:.2f} ms")
+    say(f"mix {prec} big={big}: {mix['scenarios']} scenarios, {mix['scenarios_per_s']:.1f}/s, "
+        f"p50 {mix['p50_step_ms']:.2f} ms p99 {mix['p99_step_ms']:.2f} ms, "
+        f"at most {mix['max_active_seen']} active")
     assert mix["scenarios"] == len(arrivals)
+    assert mix["max_active_seen"] >= 2
     for a in arrivals:
-        alone = Server(hbm_budget_bytes=1 << 30, max_active=1, precision=prec, pretrain_iters=30,
+        alone = Server(hbm_budget_bytes=4 << 30, max_active=1, precision=prec, pretrain_iters=30,
                        steps=3, keep_fields=True).run([a])
         pm, sm, _ = mix["results"][a.seed]["fields"]
         pa, sa, _ = alone["results"][a.seed]["fields"]
@@ -49,6 +60,22 @@ def test_budget_limits_concurrency():
     out = srv.run(arrivals)
     assert out["scenarios"] == len(arrivals)
     assert out["max_queue_wait_s"] >= 0.0
+    assert out["peak_workspace_bytes"] <= int(1.5 * one)
+
+
+def test_arrival_larger_than_budget_is_refused():
+    """An arrival whose workspace alone exceeds the budget is refused (it
+    would otherwise wait forever); the others still run."""
+    from paper_2604_20731_amd import crv
+    from paper_2604_20731_amd.serve import Server
+    arrivals = _mix()[:3]
+    big = inputs.Arrival(t=0.0, n_elem=512, width=128, seed=999, n_wells=2)
+    small = crv.workspace_size(crv.config(n_elem=64, width=64, hidden=4, precision="bf16x3f"))
+    srv = Server(hbm_budget_bytes=4 * small, max_active=4, precision="bf16x3f",
+                 pretrain_iters=5, steps=1)
+    out = srv.run([big] + arrivals)
+    assert out["refused"] == [999]
+    assert out["scenarios"] == len(arrivals)
 
 
 def test_step_batch_equals_single_steps():
