@@ -231,6 +231,24 @@ crv_status crv_loss_history(crv_ctx* ctx, double* out, int cap, int* n);
  * crv_saturation_substeps  steps 4-6 only: project the pressure and run n
  *                       substeps of length tau (no retraining). */
 crv_status crv_gram_solve(crv_ctx* ctx, const double* res, double* q);
+
+/* crv_gram_solve without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same
+ * q = G^-1 res (2D) on caller-owned device arrays, with no context.
+ *   n_elem  Ne, 4 <= Ne <= 512 (larger: CRV_EINVAL, before any device work)
+ *   d_res   device float32, (Ne-1)^2 interior residual entries, x fastest
+ *   d_q     device float32, (Ne-1)^2 entries, receives G^-1 res
+ *   d_loss  device double, nullable: receives res . q (the robust loss)
+ *   stream  hipStream_t the kernels are enqueued on (NULL: the null stream)
+ * The call only enqueues kernels and returns; no host synchronisation, no
+ * device or host allocation.  Its tables and work arrays live in one fixed
+ * device array of about 7.3 MB that every GPU the library runs on holds
+ * until the process ends; the call rebuilds what it reads there.  Calls
+ * that overlap on one GPU (other streams, other threads) share that array
+ * and race: order them on one stream.  Errors: CRV_EINVAL for a bad size or
+ * a NULL array, CRV_EHIP for a launch or symbol-lookup failure. */
+crv_status crv_gram_solve_noalloc(int n_elem, const float* d_res, float* d_q, double* d_loss,
+                                  void* stream);
 crv_status crv_mass_solve(crv_ctx* ctx, const double* b, double* x);
 crv_status crv_project_pressure(crv_ctx* ctx, double* p_coefs);
 crv_status crv_saturation_substeps(crv_ctx* ctx, double tau, int n);

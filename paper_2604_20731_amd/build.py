@@ -28,6 +28,7 @@ SOURCES = [
     "k_mlp.hip",
     "k_mlp_mfma.hip",
     "k_galerkin.hip",
+    "noalloc.hip",
 ]
 
 ARCH = os.environ.get("CRV_OFFLOAD_ARCH", "gfx950")

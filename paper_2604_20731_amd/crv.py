@@ -27,7 +27,7 @@ EXPORTED = [
     "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_step_batch",
     "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
-    "crv_gram_solve", "crv_mass_solve", "crv_project_pressure",
+    "crv_gram_solve", "crv_gram_solve_noalloc", "crv_mass_solve", "crv_project_pressure",
     "crv_saturation_substeps", "crv_pressure_galerkin", "crv_step_galerkin",
     "crv_profile_enable", "crv_profile_read", "crv_destroy", "crv_last_error",
 ]
@@ -83,6 +83,7 @@ def _load() -> C.CDLL:
         "crv_set_log_perm": [vp, dp],
         "crv_loss_history": [vp, dp, C.c_int, C.POINTER(C.c_int)],
         "crv_gram_solve": [vp, dp, dp],
+        "crv_gram_solve_noalloc": [C.c_int, vp, vp, vp, vp],
         "crv_mass_solve": [vp, dp, dp],
         "crv_project_pressure": [vp, dp],
         "crv_saturation_substeps": [vp, C.c_double, C.c_int],
@@ -318,6 +319,26 @@ class Scenario:
             _check(LIB.crv_profile_read(self.ctx, k, C.byref(ms), C.byref(n)))
             out[name] = (ms.value, n.value)
         return out
+
+
+def gram_solve_noalloc(n_elem: int, res, q, loss=None, stream=None):
+    """crv_gram_solve_noalloc: q = G^-1 res (2D) on device tensors with no
+    allocation.  res, q: contiguous float32 CUDA tensors of (n_elem-1)^2
+    entries; loss (optional): a float64 CUDA tensor of one entry that
+    receives res . q.  Enqueued on stream (default: the current torch
+    stream); returns without waiting."""
+    import torch
+    m2 = (int(n_elem) - 1) ** 2
+    for name, t, dt in (("res", res, torch.float32), ("q", q, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != m2:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {m2} entries")
+    if loss is not None and (loss.dtype != torch.float64 or not loss.is_cuda or loss.numel() != 1):
+        raise ValueError("loss must be a float64 CUDA tensor of one entry")
+    st = stream if stream is not None else torch.cuda.current_stream(res.device)
+    _check(LIB.crv_gram_solve_noalloc(int(n_elem), C.c_void_p(res.data_ptr()),
+                                      C.c_void_p(q.data_ptr()),
+                                      None if loss is None else C.c_void_p(loss.data_ptr()),
+                                      C.c_void_p(st.cuda_stream)))
 
 
 def step_batch(scenarios, dts):

@@ -28,6 +28,9 @@ static crv_status fail(crv_status s, const std::string& msg) {
   return s;
 }
 
+// the same for the library's other translation units
+crv_status report(crv_status s, const char* msg) { return fail(s, msg); }
+
 #define CRV_HIP(x)                                                                     \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \
