@@ -1,10 +1,17 @@
 """Build libcrv.so (HIP kernels for gfx950 + host runtime) in-tree with hipcc.
 
-    python -m paper_2604_20731_amd.build
+    python -m paper_2604_20731_amd.build              # libcrv.so
+    python -m paper_2604_20731_amd.build --sanitize   # host sanitizer check
 
 Every source is compiled to an object under csrc/_build (in parallel), then
 linked into paper_2604_20731_amd/libcrv.so.  All device code is built with
 the packed-FP32 instructions disabled.
+
+--sanitize compiles the host side of every source with AddressSanitizer and
+UndefinedBehaviorSanitizer (device code as usual, uninstrumented), links it
+with the
+csrc/abi_check.cpp driver into csrc/_build/asan/abi_check and runs it: the
+C ABI's argument and configuration checks, which need no GPU.
 """
 from __future__ import annotations
 
@@ -80,6 +87,58 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     return LIB
 
 
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _clangxx() -> str:
+    for c in ("/opt/rocm/llvm/bin/clang++", shutil.which("clang++")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("clang++ not found")
+
+
+def build_sanitized(jobs: int | None = None) -> int:
+    """Host-only sanitized build of the library plus the ABI driver; runs the
+    driver and returns its exit status (0: every check passed, no report)."""
+    out = os.path.join(BUILD, "asan")
+    os.makedirs(out, exist_ok=True)
+    hipcc = _hipcc()
+
+    def one(src):
+        obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
+        path = os.path.join(CSRC, src)
+        if src.endswith(".hip") or src == "runtime.cpp":
+            cmd = [hipcc, "-x", "hip", *HIP_FLAGS, "-Xarch_host", "-g", *SAN_FLAGS, "-I", INCLUDE,
+                   "-c", path, "-o", obj]
+        else:
+            cmd = [hipcc, "-x", "c++", "-O1", "-g", "-fPIC", "-std=c++17", *SAN_FLAGS, "-I",
+                   INCLUDE, "-c", path, "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stderr}")
+        return obj
+
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, SOURCES + ["abi_check.cpp"]))
+    exe = os.path.join(out, "abi_check")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    link = [_clangxx(), "-fsanitize=address,undefined", "-o", exe, *objs,
+            f"-L{rocm}/lib", "-lamdhip64", f"-Wl,-rpath,{rocm}/lib"]
+    res = subprocess.run(link, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(link)}\n{res.stderr}")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    run = subprocess.run([exe], capture_output=True, text=True, env=env)
+    sys.stdout.write(run.stdout)
+    sys.stderr.write(run.stderr)
+    return run.returncode
+
+
 if __name__ == "__main__":
+    if "--sanitize" in sys.argv[1:]:
+        sys.exit(build_sanitized())
     build(verbose=True)
     sys.exit(0)

@@ -42,10 +42,12 @@ constexpr int kLossCap = 1 << 16;
 // ---------------------------------------------------------------------------
 // workspace layout (identical dry run for crv_workspace_size)
 // ---------------------------------------------------------------------------
+// Addresses are formed as integers: the sizing dry run carves from a null
+// base, and pointer arithmetic on a null pointer is undefined.
 struct Carve {
-  char* base;
+  uintptr_t base;
   size_t off = 0;
-  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  explicit Carve(void* b) : base(reinterpret_cast<uintptr_t>(b)) {}
   template <typename T>
   T* take(size_t n) {
     off = (off + 255) & ~size_t(255);
