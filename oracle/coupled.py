@@ -33,7 +33,8 @@ class Oracle:
         self.mu_w, self.mu_g, self.n_exp = mu_w, mu_g, relperm_exp
         self.gravity, self.rho_w, self.rho_g = gravity, rho_w, rho_g
         self.adam_iters, self.substeps = adam_iters, substeps
-        self.perm = np.exp(np.asarray(log_perm, dtype=np.float64))
+        self.log_perm = np.asarray(log_perm, dtype=np.float64).copy()
+        self.perm = np.exp(self.log_perm)
         self.poro = np.asarray(porosity, dtype=np.float64)
         self.q_inj, self.q_prod = wells_mod.nodal_sources(wells, n_elem, dim, well_radius)
         self.q = self.q_inj + self.q_prod
@@ -46,6 +47,7 @@ class Oracle:
         self.z = mlp.node_inputs(n_elem, dim)
         self.mask = pressure.interior_mask(n_elem, dim)
         self.loss_history = []
+        self.obs_d = self.obs_w = None
         self.refresh()
 
     # algorithm step 1 / after step 6: alpha from the current saturation
@@ -64,16 +66,32 @@ class Oracle:
         out = mlp.forward(th, self.dims, self.z)[-1]
         return self.mask * out.reshape(self.mask.shape)
 
+    def set_observations(self, data, weights):
+        """Nodal pressure observations d with weights w >= 0 (0: not
+        observed); None clears them.  With observations the objective is
+        LOSS + sum_p w_p (u_p - d_p)^2 (the data misfit of the inverse
+        problem the paper names as future work)."""
+        if data is None:
+            self.obs_d = self.obs_w = None
+            return
+        self.obs_d = np.asarray(data, dtype=np.float64).reshape(self.mask.shape).copy()
+        self.obs_w = np.asarray(weights, dtype=np.float64).reshape(self.mask.shape).copy()
+
     def loss_and_grad(self, theta=None):
-        """Robust loss and its gradient with respect to the flat parameters."""
+        """Robust loss (plus the data misfit when observations are set) and
+        its gradient with respect to the flat parameters."""
         th = self.theta if theta is None else theta
         acts = mlp.forward(th, self.dims, self.z)
         u = self.mask * acts[-1].reshape(self.mask.shape)
         res = pressure.residual(u, self.alpha, self.q_eff)
         q = pressure.gram_solve(res)
         lval = pressure.loss(res, q)
-        gu = pressure.grad_u(q, self.alpha) * self.mask
-        g = mlp.backward(th, self.dims, acts, gu.ravel())
+        gu = pressure.grad_u(q, self.alpha)
+        if self.obs_w is not None:
+            r = u - self.obs_d
+            lval = lval + float(np.sum(self.obs_w * r * r))
+            gu = gu + 2.0 * self.obs_w * r
+        g = mlp.backward(th, self.dims, acts, (gu * self.mask).ravel())
         return lval, g
 
     def loss_grad_logperm(self, theta=None):
@@ -97,6 +115,34 @@ class Oracle:
             below[1:] = qt[:-1]          # q~ at m - e_v
             g = g - 2.0 * self.gravity * h ** (self.dim - 1) * f * (below - qt)
         return g
+
+    def set_log_perm(self, log_perm):
+        self.log_perm = np.asarray(log_perm, dtype=np.float64).reshape(self.mask.shape).copy()
+        self.perm = np.exp(self.log_perm)
+        self.refresh()
+
+    def invert(self, iters, lr_logk):
+        """Joint Adam on the network parameters and the nodal log K, both at
+        the gradient of the objective at the current (theta, log K): the
+        parameters with the configured Adam, log K with a second Adam of rate
+        lr_logk (same betas and eps) whose moments and step count start at
+        zero with the first call.  K = exp(log K) and alpha follow each step."""
+        if not hasattr(self, "lk_m"):
+            self.lk_m = np.zeros_like(self.log_perm)
+            self.lk_v = np.zeros_like(self.log_perm)
+            self.lk_t = 0
+        a = self.adam
+        for _ in range(iters):
+            lval, g = self.loss_and_grad()
+            glk = self.loss_grad_logperm()
+            self.loss_history.append(lval)
+            self.theta = a.step(self.theta, g)
+            self.lk_t += 1
+            self.lk_m = a.b1 * self.lk_m + (1.0 - a.b1) * glk
+            self.lk_v = a.b2 * self.lk_v + (1.0 - a.b2) * glk * glk
+            mhat = self.lk_m / (1.0 - a.b1 ** self.lk_t)
+            vhat = self.lk_v / (1.0 - a.b2 ** self.lk_t)
+            self.set_log_perm(self.log_perm - lr_logk * mhat / (np.sqrt(vhat) + a.eps))
 
     def train(self, iters):
         for _ in range(iters):
