@@ -219,6 +219,26 @@ crv_status crv_set_saturation(crv_ctx* ctx, const double* s_coefs);
  * to evaluate the loss at a new log K. */
 crv_status crv_set_log_perm(crv_ctx* ctx, const double* log_perm);
 
+/* Inverse problem (the paper's conclusions name recovering reservoir
+ * parameters as future work), read as a joint Adam on the network parameters
+ * and the nodal log K.
+ * crv_set_observations: host (N+1)^d arrays of pressure data d and weights
+ *   w >= 0 (0: not observed; boundary nodes are ignored); data NULL clears
+ *   them.  With observations every training call (pretrain, step, loss_grad,
+ *   invert) uses the objective LOSS + sum_p w_p (u_p - d_p)^2, whose
+ *   gradient in u gains 2 w (u - d).  CRV_EINVAL for non-finite entries or
+ *   negative weights.
+ * crv_invert: iters joint iterations, each: the objective's gradients in
+ *   theta and in log K (dLOSS/dlogK = dLOSS/dalpha * alpha) at the current
+ *   point; Adam on theta with the configured rate; Adam on log K with rate
+ *   lr_logk (same betas and eps, its own moments and step count, started at
+ *   zero by crv_init); then K = exp(log K) and alpha.  The objective of each
+ *   iteration joins the loss history.  Synchronises with the host at the end.
+ * crv_get_log_perm: the current nodal log K into a host (N+1)^d array. */
+crv_status crv_set_observations(crv_ctx* ctx, const double* data, const double* weights);
+crv_status crv_invert(crv_ctx* ctx, int iters, double lr_logk);
+crv_status crv_get_log_perm(crv_ctx* ctx, double* log_perm);
+
 /* Loss of each Adam iteration so far (oldest first, at most cap entries,
  * the most recent ones when more were run); *n receives the count. */
 crv_status crv_loss_history(crv_ctx* ctx, double* out, int cap, int* n);

@@ -27,6 +27,7 @@ EXPORTED = [
     "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_step_batch",
     "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
+    "crv_set_observations", "crv_invert", "crv_get_log_perm",
     "crv_gram_solve", "crv_gram_solve_noalloc", "crv_mass_solve", "crv_project_pressure",
     "crv_saturation_substeps", "crv_pressure_galerkin", "crv_step_galerkin",
     "crv_profile_enable", "crv_profile_read", "crv_destroy", "crv_last_error",
@@ -82,6 +83,9 @@ def _load() -> C.CDLL:
         "crv_set_saturation": [vp, dp],
         "crv_set_log_perm": [vp, dp],
         "crv_loss_history": [vp, dp, C.c_int, C.POINTER(C.c_int)],
+        "crv_set_observations": [vp, dp, dp],
+        "crv_invert": [vp, C.c_int, C.c_double],
+        "crv_get_log_perm": [vp, dp],
         "crv_gram_solve": [vp, dp, dp],
         "crv_gram_solve_noalloc": [C.c_int, vp, vp, vp, vp],
         "crv_mass_solve": [vp, dp, dp],
@@ -253,6 +257,26 @@ class Scenario:
         if a.size != self.nn:
             raise ValueError(f"log_perm has {a.size} entries, expected {self.nn}")
         _check(LIB.crv_set_log_perm(self.ctx, _dp(a)))
+
+    def set_observations(self, data, weights):
+        """Nodal pressure data and weights (>= 0) of the inverse problem;
+        data None clears them."""
+        if data is None:
+            _check(LIB.crv_set_observations(self.ctx, None, None))
+            return
+        d, w = _f64(data).ravel(), _f64(weights).ravel()
+        if d.size != self.nn or w.size != self.nn:
+            raise ValueError(f"observations need {self.nn} nodal entries")
+        _check(LIB.crv_set_observations(self.ctx, _dp(d), _dp(w)))
+
+    def invert(self, iters: int, lr_logk: float):
+        """crv_invert: joint Adam iterations on the network and log K."""
+        _check(LIB.crv_invert(self.ctx, int(iters), float(lr_logk)))
+
+    def log_perm(self) -> np.ndarray:
+        out = np.empty((self.ne + 1,) * self.dim)
+        _check(LIB.crv_get_log_perm(self.ctx, _dp(out)))
+        return out
 
     def set_theta(self, theta):
         """Replace the network parameters, keeping the Adam moments and step count."""

@@ -114,6 +114,9 @@ int main() {
   expect("pressure_galerkin NULL", crv_pressure_galerkin(nullptr, 10, 1e-6, 1, &d, &it, &d),
          CRV_EINVAL);
   expect("step_galerkin NULL", crv_step_galerkin(nullptr, 1e-3, 10, 1e-6, 1, &it, &d), CRV_EINVAL);
+  expect("set_observations NULL", crv_set_observations(nullptr, &d, &d), CRV_EINVAL);
+  expect("invert NULL", crv_invert(nullptr, 1, 1e-3), CRV_EINVAL);
+  expect("get_log_perm NULL", crv_get_log_perm(nullptr, &d), CRV_EINVAL);
   expect("profile_enable NULL", crv_profile_enable(nullptr, 1), CRV_EINVAL);
   expect("profile_read NULL", crv_profile_read(nullptr, 0, &d, &cnt), CRV_EINVAL);
   expect("destroy NULL", crv_destroy(nullptr), CRV_OK);

@@ -189,14 +189,19 @@ void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real
 // ---------------------------------------------------------------------------
 // a5: g_u = 2 A^T q~ on the full grid (q~ = q inside, 0 on the boundary; the
 // boundary entries are zero because the trial functions vanish there), and
-// per-block partial sums of LOSS = RES . q (eq. 27).
+// per-block partial sums of LOSS = RES . q (eq. 27).  With observations
+// (obs_w non-null) the data misfit w (u - d)^2 of the inverse problem joins
+// the loss and 2 w (u - d) joins g_u at interior nodes.
 // ---------------------------------------------------------------------------
 template <typename Real, int DIM>
 __global__ __launch_bounds__(256) void k_adjoint(Geom g, const Real* __restrict__ q,
                                                  const Real* __restrict__ alpha,
                                                  const Real* __restrict__ res,
                                                  Real* __restrict__ gu,
-                                                 Real* __restrict__ partials) {
+                                                 Real* __restrict__ partials,
+                                                 const Real* __restrict__ obs_w,
+                                                 const Real* __restrict__ obs_d,
+                                                 const Real* __restrict__ u) {
   __shared__ Real sbuf[256];
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -206,8 +211,16 @@ __global__ __launch_bounds__(256) void k_adjoint(Geom g, const Real* __restrict_
   if (i < n && j < n) {
     const int64_t p = (int64_t(k) * n + j) * n + i;
     int64_t iq;
-    gu[p] = adjoint_at<Real, DIM>(g, q, alpha, p, &iq);
-    if (iq >= 0) lpart = res[iq] * q[iq];
+    Real gv = adjoint_at<Real, DIM>(g, q, alpha, p, &iq);
+    if (iq >= 0) {
+      lpart = res[iq] * q[iq];
+      if (obs_w) {
+        const Real w = obs_w[p], r = u[p] - obs_d[p];
+        gv += Real(2) * w * r;
+        lpart += w * r * r;
+      }
+    }
+    gu[p] = gv;
   }
   const Real tot = block_sum(lpart, sbuf);
   if (threadIdx.x == 0) partials[(int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
@@ -219,15 +232,46 @@ int adjoint_partials(const Geom& g) {
 
 template <typename Real>
 int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* res, Real* gu,
-                   Real* partials, hipStream_t st) {
+                   Real* partials, hipStream_t st, const Real* obs_w, const Real* obs_d,
+                   const Real* u) {
   if (g.dim == 3) {
     dim3 grid3(cdiv(g.n, 64), cdiv(g.n, 4), g.n);
-    k_adjoint<Real, 3><<<grid3, 256, 0, st>>>(g, q, alpha, res, gu, partials);
+    k_adjoint<Real, 3><<<grid3, 256, 0, st>>>(g, q, alpha, res, gu, partials, obs_w, obs_d, u);
     return grid3.x * grid3.y * grid3.z;
   }
   dim3 grid(cdiv(g.n, 64), cdiv(g.n, 4));
-  k_adjoint<Real, 2><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials);
+  k_adjoint<Real, 2><<<grid, 256, 0, st>>>(g, q, alpha, res, gu, partials, obs_w, obs_d, u);
   return grid.x * grid.y;
+}
+
+// Adam on the nodal log K of the inverse problem (its own moments; step
+// count *t, advanced before the launch), then K = exp(log K)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adam_logk(int64_t n, Real* __restrict__ logk,
+                                                   Real* __restrict__ m, Real* __restrict__ v,
+                                                   const Real* __restrict__ g,
+                                                   Real* __restrict__ perm, double lr, double b1,
+                                                   double b2, double eps,
+                                                   const long long* __restrict__ t) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double tt = double(*t);
+  const Real c1 = Real(1.0 - pow(b1, tt)), c2 = Real(1.0 - pow(b2, tt));
+  const Real gg = g[p];
+  const Real mm = Real(b1) * m[p] + Real(1.0 - b1) * gg;
+  const Real vv = Real(b2) * v[p] + Real(1.0 - b2) * gg * gg;
+  m[p] = mm;
+  v[p] = vv;
+  const Real nl = logk[p] - Real(lr) * (mm / c1) / (sqrt(vv / c2) + Real(eps));
+  logk[p] = nl;
+  perm[p] = exp(nl);
+}
+
+template <typename Real>
+void launch_adam_logk(int64_t n, Real* logk, Real* m, Real* v, const Real* g, Real* perm,
+                      double lr, double b1, double b2, double eps, const long long* t,
+                      hipStream_t st) {
+  k_adam_logk<Real><<<cdiv(n, 256), 256, 0, st>>>(n, logk, m, v, g, perm, lr, b1, b2, eps, t);
 }
 
 template <typename Real>
@@ -906,7 +950,10 @@ void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st, Bat
                                       hipStream_t, Batch);                                       \
   template void launch_residual<R>(const Geom&, const R*, const R*, const R*, R*, hipStream_t,   \
                                    Batch);                                                       \
-  template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t); \
+  template int launch_adjoint<R>(const Geom&, const R*, const R*, const R*, R*, R*, hipStream_t, \
+                                 const R*, const R*, const R*);                                 \
+  template void launch_adam_logk<R>(int64_t, R*, R*, R*, const R*, R*, double, double, double,  \
+                                    double, const long long*, hipStream_t);                     \
   template void launch_loss_finalize<R>(const R*, int, double*, int, const long long*, int,      \
                                         hipStream_t);                                            \
   template void launch_grad_logperm<R>(const Geom&, const R*, const R*, const R*, const R*, double, \

@@ -503,9 +503,13 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
                                                              const float* __restrict__ res,
                                                              float* __restrict__ partials,
                                                              float* __restrict__ loss_part,
-                                                             int64_t zb) {
+                                                             int64_t zb,
+                                                             const float* __restrict__ obs_w,
+                                                             const float* __restrict__ obs_d,
+                                                             const float* __restrict__ u) {
   th = zofs(th, zb); frag = zofs(frag, zb); qg = zofs(qg, zb); alpha = zofs(alpha, zb);
   res = zofs(res, zb); partials = zofs(partials, zb); loss_part = zofs(loss_part, zb);
+  obs_w = zofs(obs_w, zb); obs_d = zofs(obs_d, zb); u = zofs(u, zb);
   using T = MM<MODE>;
   using BS = BwdShape<W, L, MODE, DIM, NW>;
   using E = typename BS::E;
@@ -602,8 +606,14 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
       for (int c = 0; c < DIM; ++c) z[c] = 0.f;
     // the adjoint's loads first: their latency hides behind the recompute
     int64_t iq = -1;
-    const float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
+    float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
     if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
+    if (obs_w && iq >= 0) {
+      // data misfit w (u - d)^2 of the inverse problem (interior nodes)
+      const float wo = obs_w[p], r = u[p] - obs_d[p];
+      gv += 2.f * wo * r;
+      if (q == 0) lacc += wo * r * r;
+    }
     float d[NR];
     forward_tile<W, L, MODE, DIM, (W <= 64)>(sp, fr, l1, z, q, lane, d, sink);
     if (q == 0) {
@@ -1000,28 +1010,31 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 template <int W, int L, int MODE>
 static void bwd_inst(const Geom& g, int64_t ldp, const float* th, const void* frag, const float* q,
                      const float* alpha, const float* res, float* partials, float* loss_part,
-                     int blocks, hipStream_t st, Batch bz) {
+                     int blocks, hipStream_t st, Batch bz, const float* ow, const float* od,
+                     const float* u) {
   constexpr int NW = bwd_nw(W, MODE);
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
   const dim3 grid(blocks, 1, bz.n);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<grid, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
-                                                                  partials, loss_part, bz.zb);
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<grid, 64 * NW, 0, st>>>(
+          g, ldp, th, fr, q, alpha, res, partials, loss_part, bz.zb, ow, od, u);
       return;
     }
   }
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<grid, 64 * NW, 0, st>>>(g, ldp, th, fr, q, alpha, res,
-                                                              partials, loss_part, bz.zb);
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<grid, 64 * NW, 0, st>>>(
+      g, ldp, th, fr, q, alpha, res, partials, loss_part, bz.zb, ow, od, u);
 }
 
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
-                              float* loss_part, int blocks, hipStream_t st, Batch bz) {
+                              float* loss_part, int blocks, hipStream_t st, Batch bz,
+                              const float* obs_w, const float* obs_d, const float* u) {
 #define CRV_BW(WW, LL, MM_) \
   if (width == WW && hidden == LL && mode == MM_) \
-    return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, st, bz);
+    return bwd_inst<WW, LL, MM_>(g, ldp, theta, frag, q, alpha, res, partials, loss_part, blocks, \
+                                 st, bz, obs_w, obs_d, u);
   CRV_BWD_SHAPES(CRV_BW)
 #undef CRV_BW
 }

@@ -25,10 +25,18 @@ void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real
                      hipStream_t st, Batch bz = Batch{});
 
 // a5: g_u = 2 A^T q (zero on the boundary) and per-block partial sums of RES.q.
+// With observations (obs_w non-null; obs_d the data, u the network pressure)
+// 2 w (u - d) joins g_u and w (u - d)^2 the loss at interior nodes.
 // Returns the number of partials written.
 template <typename Real>
 int launch_adjoint(const Geom& g, const Real* q, const Real* alpha, const Real* res, Real* gu,
-                   Real* loss_partials, hipStream_t st);
+                   Real* loss_partials, hipStream_t st, const Real* obs_w = nullptr,
+                   const Real* obs_d = nullptr, const Real* u = nullptr);
+// Adam step on the nodal log K (moments m, v, step count *t) and K = exp(log K)
+template <typename Real>
+void launch_adam_logk(int64_t n, Real* logk, Real* m, Real* v, const Real* g, Real* perm,
+                      double lr, double b1, double b2, double eps, const long long* t,
+                      hipStream_t st);
 int adjoint_partials(const Geom& g);
 
 // Sum of the loss partials (fixed order) into loss_hist[(t + slot_offset) % cap].
@@ -205,7 +213,9 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
 void launch_mlp_backward_mfma(const Geom& g, int width, int hidden, int mode, int64_t ldp,
                               const float* theta, const void* frag, const float* q,
                               const float* alpha, const float* res, float* partials,
-                              float* loss_part, int blocks, hipStream_t st, Batch bz = Batch{});
+                              float* loss_part, int blocks, hipStream_t st, Batch bz = Batch{},
+                              const float* obs_w = nullptr, const float* obs_d = nullptr,
+                              const float* u = nullptr);
 // fixed-order sum of the partial rows + Adam + fragment update; one extra
 // block sums the loss partials into loss_hist[(t-1) % cap]
 void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t ldp, float* theta, float* m,

@@ -100,6 +100,10 @@ struct Buffers {
   long long *t_dev, *t_zero;
   double* tau;     // substep length of the current step (device, read by the assembly)
   int* flag;
+  // inverse problem: observation weights and data (nodal), log K and the
+  // moments and step count of its Adam
+  Real *obs_w, *obs_d, *logk, *lk_m, *lk_v;
+  long long* t_k;
   void* frag;      // MFMA weight fragments (bf16 or float32)
   int bwd_rows;
   int loss_np;
@@ -180,6 +184,12 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.t_zero = cv.take<long long>(1);
   b.tau = cv.take<double>(1);
   b.flag = cv.take<int>(1);
+  b.obs_w = cv.take<Real>(nn);
+  b.obs_d = cv.take<Real>(nn);
+  b.logk = cv.take<Real>(nn);
+  b.lk_m = cv.take<Real>(nn);
+  b.lk_v = cv.take<Real>(nn);
+  b.t_k = cv.take<long long>(1);
   return (cv.off + 255) & ~size_t(255);
 }
 
@@ -271,6 +281,9 @@ struct SolverBase {
   virtual crv_status set_state(const double*, const double*, const double*, int64_t) = 0;
   virtual crv_status set_saturation(const double*) = 0;
   virtual crv_status set_log_perm(const double*) = 0;
+  virtual crv_status set_observations(const double*, const double*) = 0;
+  virtual crv_status invert(int iters, double lr_logk) = 0;
+  virtual crv_status get_log_perm(double*) = 0;
   virtual crv_status loss_history(double*, int, int*) = 0;
   virtual crv_status gram_solve_host(const double*, double*) = 0;
   virtual crv_status mass_solve_host(const double*, double*) = 0;
@@ -396,6 +409,7 @@ struct Solver : SolverBase {
     }
     crv_status s;
     if ((s = upload(b.perm, perm.data(), nn))) return s;
+    if ((s = upload(b.logk, log_perm, nn))) return s;
     if ((s = upload(b.poro, poro, nn))) return s;
     if ((s = upload(b.qi, qi.data(), nn))) return s;
     if ((s = upload(b.qp, qp.data(), nn))) return s;
@@ -549,9 +563,14 @@ struct Solver : SolverBase {
     gram_solve();
     if (mfma) return;
     tb(CRV_K_ADJOINT);
-    adj_np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st);
+    adj_np = launch_adjoint<Real>(g, b.q, b.alpha, b.res, b.gu, b.loss_part, st,
+                                  obs_on ? b.obs_w : nullptr, b.obs_d, b.u);
     te();
   }
+
+  // pressure observations of the inverse problem are in use (they change
+  // the captured work, so switching them on or off drops the graphs)
+  bool obs_on = false;
 
   // partial gradient rows of the network backward; returns the row count.
   // The matrix-core backward also leaves bwd_blocks loss partials.
@@ -564,7 +583,8 @@ struct Solver : SolverBase {
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
         launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, ldp(), b.theta, b.frag, b.q, b.alpha,
-                                 b.res, b.partials, b.loss_part, bwd_blocks, st, bz);
+                                 b.res, b.partials, b.loss_part, bwd_blocks, st, bz,
+                                 obs_on ? b.obs_w : nullptr, b.obs_d, b.u);
         rows = bwd_blocks;
       }
     }
@@ -1014,9 +1034,79 @@ struct Solver : SolverBase {
     CRV_HIP(hipStreamSynchronize(st));
     crv_status s = upload(b.perm, perm.data(), nn);
     if (s) return s;
+    if ((s = upload(b.logk, lk, nn))) return s;
     refresh();
     return check_launch();
   }
+
+  // ---- inverse problem ----
+  void drop_graphs() {
+    if (g_train) (void)hipGraphExecDestroy(g_train);
+    if (g_step) (void)hipGraphExecDestroy(g_step);
+    g_train = g_step = nullptr;
+    for (BatchGraph& bg : g_batch) (void)hipGraphExecDestroy(bg.exec);
+    g_batch.clear();
+  }
+
+  crv_status set_observations(const double* data, const double* weights) override {
+    const bool on = data != nullptr;
+    if (on) {
+      for (size_t i = 0; i < nn; ++i)
+        if (!std::isfinite(data[i]) || !std::isfinite(weights[i]) || weights[i] < 0)
+          return fail(CRV_EINVAL, "observations must be finite with weights >= 0");
+      crv_status s = upload(b.obs_d, data, nn);
+      if (s) return s;
+      if ((s = upload(b.obs_w, weights, nn))) return s;
+    }
+    if (on != obs_on) {
+      CRV_HIP(hipStreamSynchronize(st));
+      drop_graphs();
+    }
+    obs_on = on;
+    return CRV_OK;
+  }
+
+  // one joint iteration: the objective's gradients in theta and log K at the
+  // current (theta, log K), Adam on theta, Adam on log K (its own moments and
+  // count), K and alpha from the new log K
+  void invert_iteration(double lr_logk) {
+    loss_pass(b.t_dev);
+    if constexpr (std::is_same<Real, float>::value) {
+      if (mfma) {
+        const int rows = backward();
+        launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, gravity() ? b.gflux : nullptr,
+                                  cfg.gravity, b.tmp_nodal, st);
+        launch_reduce_adam_pack(b.partials, rows, P, ldp(), b.theta, b.am, b.av, cfg.lr, cfg.beta1,
+                                cfg.beta2, cfg.eps, b.t_dev, cfg.dim, cfg.width, cfg.hidden, mode,
+                                b.frag, b.loss_part, loss_count(), b.loss_hist, kLossCap, st);
+        invert_logk(lr_logk);
+        return;
+      }
+    }
+    launch_loss_finalize<Real>(b.loss_part, loss_count(), b.loss_hist, kLossCap, b.t_dev, -1, st);
+    grad_pass();
+    launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, gravity() ? b.gflux : nullptr, cfg.gravity,
+                              b.tmp_nodal, st);
+    launch_adam<Real>(P, b.theta, b.am, b.av, b.grad, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps,
+                      b.t_dev, st);
+    pack();
+    invert_logk(lr_logk);
+  }
+  void invert_logk(double lr_logk) {
+    launch_bump(b.t_k, st);
+    launch_adam_logk<Real>(int64_t(nn), b.logk, b.lk_m, b.lk_v, b.tmp_nodal, b.perm, lr_logk,
+                           cfg.beta1, cfg.beta2, cfg.eps, b.t_k, st);
+    refresh();
+  }
+  crv_status invert(int iters, double lr_logk) override {
+    if (iters < 0 || !(lr_logk >= 0) || !std::isfinite(lr_logk))
+      return fail(CRV_EINVAL, "iters must be >= 0 and lr_logk finite and >= 0");
+    for (int i = 0; i < iters; ++i) invert_iteration(lr_logk);
+    crv_status s = check_launch();
+    if (s) return s;
+    return sync_and_check();
+  }
+  crv_status get_log_perm(double* out) override { return download(out, b.logk, nn); }
 
   crv_status set_saturation(const double* sc) override {
     for (size_t i = 0; i < nc; ++i)
@@ -1300,6 +1390,23 @@ crv_status crv_set_log_perm(crv_ctx* c, const double* log_perm) {
   CRV_CTX(c);
   if (!log_perm) return fail(CRV_EINVAL, "log_perm is NULL");
   return sv.set_log_perm(log_perm);
+}
+
+crv_status crv_set_observations(crv_ctx* c, const double* data, const double* weights) {
+  CRV_CTX(c);
+  if (data && !weights) return fail(CRV_EINVAL, "weights are required with data");
+  return sv.set_observations(data, weights);
+}
+
+crv_status crv_invert(crv_ctx* c, int iters, double lr_logk) {
+  CRV_CTX(c);
+  return sv.invert(iters, lr_logk);
+}
+
+crv_status crv_get_log_perm(crv_ctx* c, double* log_perm) {
+  CRV_CTX(c);
+  if (!log_perm) return fail(CRV_EINVAL, "log_perm is NULL");
+  return sv.get_log_perm(log_perm);
 }
 
 crv_status crv_loss_history(crv_ctx* c, double* out, int cap, int* n) {
