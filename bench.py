@@ -67,6 +67,25 @@ def algorithmic_work(name, prob, n_launch_units):
 
 NET_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x3f": 3}
 
+# tanh = 1 - 2 / (2^(Ka) + 1): one exp2 and one reciprocal, both quarter-rate
+# transcendental instructions: 256 CUs x 4 SIMDs x 16 lanes / 4 x 2.4 GHz
+TRANS_PEAK_PER_S = 256 * 4 * 16 / 4 * 2.4e9
+
+
+def transcendental_floor(name, prob, us_per_launch, scenarios=1):
+    """The network kernels' ALU bound: every pass over the nodes evaluates
+    hidden x width activations per node (the backward recomputes them), two
+    transcendental instructions each."""
+    if name not in ("mlp_fwd", "mlp_bwd"):
+        return None
+    nodes = (prob.n_elem + 1) ** prob.dim
+    ops = 2.0 * nodes * prob.hidden * prob.width * scenarios
+    achieved = ops / (us_per_launch * 1e-6)
+    return {"bound": "alu", "what": "transcendental instructions (tanh: exp2 + reciprocal)",
+            "work_per_launch": ops, "achieved": achieved / 1e9, "peak": TRANS_PEAK_PER_S / 1e9,
+            "unit": "G/s", "frac": achieved / TRANS_PEAK_PER_S,
+            "floor_us": ops / TRANS_PEAK_PER_S * 1e6}
+
 
 def kernel_symbol(name, prob, precision):
     """Device symbol of the launch the event timer calls `name` (matrix-core
@@ -178,16 +197,46 @@ def run_single(prob, precision, steps, warmup, pretrain, profile, **cfg):
     pf, scf, _ = sc.fields()  # raises on a non-finite saturation
     assert np.all(np.isfinite(pf)) and np.all(np.isfinite(scf))
     prof, nprof = {}, max(1, min(2, steps))
+    cache = None
     if profile:
         sc.profile_enable(True)
         for _ in range(nprof):
             sc.step(dt)
         prof = sc.profile_read()
         sc.profile_enable(False)
+        cache = warm_cold_iteration(sc)
     sc.close()
     kernels = {name: {"ms_per_step": ms / nprof, "launches_per_step": n / nprof,
                       "us_per_launch": 1e3 * ms / n} for name, (ms, n) in prof.items() if n}
-    return {"value": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "dt": dt}, kernels
+    out = {"value": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "dt": dt}
+    if cache:
+        out["adam_iteration_us"] = cache
+    return out, kernels
+
+
+def warm_cold_iteration(sc, reps=9):
+    """One Adam iteration (launched without a graph), HIP-event timed on the
+    scenario's stream: warm (its arrays already in the 256 MB last-level
+    cache from the previous iteration) and cold (a 512 MB device write just
+    before evicts them, so every array comes from HBM); medians."""
+    import torch
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+
+    def one(cold):
+        if cold:
+            flush.fill_(1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sc.stream)
+        sc.train_async(1)
+        e1.record(sc.stream)
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1)
+
+    warm = sorted(one(False) for _ in range(reps))[reps // 2]
+    cold = sorted(one(True) for _ in range(reps))[reps // 2]
+    return {"warm": warm, "cold": cold, "what": "one Adam iteration, eager launches, median of "
+            f"{reps}; cold after a 512 MB device write"}
 
 
 def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
@@ -324,7 +373,10 @@ def main():
     prob = inputs.make_problem(args.workload, seed=0)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     log(f"plain fp32 single scenario, {args.steps} steps")
-    plain, kern_plain = run_single(prob, "fp32", args.steps, args.warmup, args.pretrain, False)
+    runs = [run_single(prob, "fp32", args.steps, args.warmup, args.pretrain, False)[0]
+            for _ in range(3)]
+    plain = dict(sorted(runs, key=lambda r: r["value"])[1])   # median of three runs
+    plain["runs"] = [r["value"] for r in runs]
     log(f"{args.precision} single scenario, {args.steps} steps (+ event-timed kernels)")
     single, kernels = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain,
                                  not args.no_profile)
@@ -391,7 +443,8 @@ def main():
                 roofline = {"kernel": dom, "bound": "alu" if args.precision == "fp64" else "mfma",
                             "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                             "frac": achieved / peak, "traffic": traffic, "work_per_launch": amount,
-                            "us_per_launch": us}
+                            "us_per_launch": us,
+                            "alu": transcendental_floor(dom, prob, us)}
             else:
                 achieved = amount / (us * 1e-6) / 1e9
                 roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved,

@@ -185,12 +185,20 @@ crv_status crv_step_galerkin(crv_ctx* ctx, double dt, int max_iters, double rtol
  * saturation) surface as CRV_ENUMERIC at the next synchronising call. */
 crv_status crv_step(crv_ctx* ctx, double dt);
 
-/* Serving form of crv_step: one coupled step of length dts[i] for each of
- * the n contexts (all validated first: CRV_EINVAL for a NULL context or a
- * bad dt, CRV_ESTATE for a context not pretrained; nothing is enqueued
- * then).  Each step is enqueued on its own context's stream without any host
- * wait, so contexts on distinct streams advance concurrently on the device;
- * results are those of n crv_step calls.  Asynchronous like crv_step. */
+/* Serving form of crv_step (IGA-ADS-CRVPINN algorithm, steps 4-7, for n
+ * scenarios): one coupled step of length dts[i] for each of the n contexts
+ * (all validated first: CRV_EINVAL for a NULL context or a bad dt,
+ * CRV_ESTATE for a context not pretrained; nothing is enqueued then).
+ * Contexts of one configuration (2D, matrix-core network) whose workspaces
+ * lie at one stride, in order and without overlap, advance together: every
+ * kernel of the step runs once for all of them (the scenario selects the
+ * workspace), on the first context's stream, ordered after the work queued
+ * on the others' streams and before their later work.  The network backward
+ * then shares the blocks that fit on the device among the scenarios, so
+ * their gradients round differently from crv_step's (the same sums grouped
+ * otherwise).  Any other set of contexts steps each on its own stream with
+ * no host wait, with exactly the results of n crv_step calls.  Asynchronous
+ * like crv_step. */
 crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n);
 
 /* Outputs (any may be NULL): p_nodal (N+1)^d network pressure m*NN,

@@ -777,14 +777,17 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
 
 // ---------------------------------------------------------------------------
 // Fused gradient reduction + Adam + fragment update.  Partial rows have pitch
-// ldp (a multiple of 4 floats).  Block = RW waves over 64 parameters: lane
-// (c = lane%16, g = lane/16) of wave w reads parameters 4c..4c+3 (one 16-byte
-// load) of rows 4w+g, 4w+g+4RW, ...; the 4RW partial sums are added in a
-// fixed order.  The updated weight of a hidden-to-hidden layer is written
-// straight into its two fragment slots.  One extra block sums the
-// iteration's loss partials.
+// ldp (a multiple of 4 floats).  Block = RW waves over 4 RC parameters: lane
+// (c = lane % RC, g = lane / RC) of wave w reads parameters 4c..4c+3 (one
+// 16-byte load) of rows (64/RC) w + g, then every (64/RC) RW rows further;
+// the per-thread sums are added in a fixed order (RC = 16: 64 parameters
+// per block; 32 per block measured slower, its final sum twice as long).
+// The updated weight of a hidden-to-hidden layer is written straight
+// into its two fragment slots.  One extra block sums the iteration's loss
+// partials.
 // ---------------------------------------------------------------------------
 constexpr int RW = 16;  // waves per reduction block
+constexpr int RC = 16;  // 16-byte column groups per reduction block
 
 template <int MODE>
 __device__ inline void adam_one(int64_t p, float gg, float* __restrict__ th, float* __restrict__ m,
@@ -825,7 +828,9 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
   part = zofs(part, zb); th = zofs(th, zb); m = zofs(m, zb); v = zofs(v, zb);
   t_dev = zofs(t_dev, zb); frag = zofs(frag, zb); loss_part = zofs(loss_part, zb);
   hist = zofs(hist, zb);
-  __shared__ f32x4_t red[4 * RW][16];
+  constexpr int RG = 64 / RC;   // row groups per wave
+  constexpr int RS = RG * RW;   // row stride of a thread
+  __shared__ f32x4_t red[RS][RC];
   if (blockIdx.x == gridDim.x - 1) {
     __shared__ double lb[64 * RW];
     double s = 0;
@@ -834,13 +839,12 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
     if (threadIdx.x == 0) hist[(*t_dev - 1) % cap] = tot;
     return;
   }
-  constexpr int RS = 4 * RW;  // row stride
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, c = lane & 15, rg = lane >> 4;
-  const int64_t p0 = int64_t(blockIdx.x) * 64 + 4 * c;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, c = lane % RC, rg = lane / RC;
+  const int64_t p0 = int64_t(blockIdx.x) * (4 * RC) + 4 * c;
   f32x4_t s = {0.f, 0.f, 0.f, 0.f};
   if (p0 < P) {
     const float* col = part + p0;
-    int r = 4 * w + rg;
+    int r = RG * w + rg;
     for (; r + 3 * RS < rows; r += 4 * RS) {
       const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r) * ldp);
       const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(col + int64_t(r + RS) * ldp);
@@ -853,15 +857,15 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
     }
     for (; r < rows; r += RS) s += *reinterpret_cast<const f32x4_t*>(col + int64_t(r) * ldp);
   }
-  red[4 * w + rg][c] = s;
+  red[RG * w + rg][c] = s;
   __syncthreads();
   // wave 0: one parameter per lane (lane = 4 c + component)
-  const int64_t p = int64_t(blockIdx.x) * 64 + lane;
-  if (w != 0 || p >= P) return;
+  const int64_t p = int64_t(blockIdx.x) * (4 * RC) + lane;
+  if (w != 0 || lane >= 4 * RC || p >= P) return;
   const float* rf = reinterpret_cast<const float*>(&red[0][0]);
   float gg = rf[lane];
-#pragma unroll
-  for (int k = 1; k < RS; ++k) gg += rf[k * 64 + lane];
+#pragma unroll 8
+  for (int k = 1; k < RS; ++k) gg += rf[k * (4 * RC) + lane];
   const double t = double(*t_dev);
   const float c1 = float(1.0 - pow(b1, t)), c2 = float(1.0 - pow(b2, t));
   adam_one<MODE>(p, gg, th, m, v, float(lr), float(b1), float(b2), float(eps), c1, c2, dim, W,
@@ -900,7 +904,7 @@ void launch_reduce_adam_pack(const float* partials, int rows, int64_t P, int64_t
                              const long long* t_dev, int dim, int width, int hidden, int mode,
                              void* frag, const float* loss_part, int loss_np, double* loss_hist,
                              int cap, hipStream_t st, Batch bz) {
-  const dim3 blocks(cdiv(P, 64) + 1, 1, bz.n);
+  const dim3 blocks(cdiv(P, 4 * RC) + 1, 1, bz.n);
   if (mode == NET_MIX) mode = NET_X3;  // same fragments
 #define CRV_RA(MM_, TT)                                                                           \
   k_reduce_adam_pack<MM_><<<blocks, 64 * RW, 0, st>>>(partials, rows, P, ldp, theta, m, v, lr, b1, b2, eps, \

@@ -573,19 +573,24 @@ struct Solver : SolverBase {
   bool obs_on = false;
 
   // partial gradient rows of the network backward; returns the row count.
-  // The matrix-core backward also leaves bwd_blocks loss partials.
+  // The matrix-core backward also leaves one loss partial per block.  A batch
+  // of n scenarios shares the blocks that fit on the device at once (about
+  // bwd_blocks / n each), so that all of them run in one round and each
+  // scenario writes n times fewer partial rows; its gradient sums then
+  // round differently from a single step's (same sums, other grouping).
+  int bwd_grid() const { return bz.n > 1 ? std::max(1, (bwd_blocks + bz.n - 1) / bz.n) : bwd_blocks; }
   int adj_np = 0;
   int64_t ldp() const { return partial_pitch(P); }  // pitch of the matrix-core partial rows
-  int loss_count() const { return mfma ? bwd_blocks : adj_np; }
+  int loss_count() const { return mfma ? bwd_grid() : adj_np; }
   int backward() {
     tb(CRV_K_MLP_BWD);
     int rows = 0;
     if constexpr (std::is_same<Real, float>::value) {
       if (mfma) {
         launch_mlp_backward_mfma(g, cfg.width, cfg.hidden, mode, ldp(), b.theta, b.frag, b.q, b.alpha,
-                                 b.res, b.partials, b.loss_part, bwd_blocks, st, bz,
+                                 b.res, b.partials, b.loss_part, bwd_grid(), st, bz,
                                  obs_on ? b.obs_w : nullptr, b.obs_d, b.u);
-        rows = bwd_blocks;
+        rows = bwd_grid();
       }
     }
     if (!rows) rows = launch_mlp_backward<Real>(g, ms, b.theta, b.gu, b.partials, st);

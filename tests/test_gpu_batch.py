@@ -2,12 +2,24 @@
 workspaces lie at a fixed stride in one allocation (crv.Bucket) advance with
 one launch per kernel of the coupled step, blockIdx.z selecting the scenario
 (the unit batched is the coupled step of the IGA-ADS-CRVPINN algorithm,
-steps 4-7).  Every kernel reduces in a fixed order that does not depend on
-the batch, so the results must equal single-scenario steps bitwise."""
+steps 4-7).  Every kernel but the network backward computes exactly what it
+computes for one scenario; the backward spreads the device's resident blocks
+over the batch, so each scenario's parameter gradient is the same sum grouped
+into fewer partial rows.  Bucket steps therefore match single steps to
+rounding, which Adam's normalised steps carry into the parameters and the
+network's output (a small difference of large terms) amplifies: after 2
+coupled steps the fields, parameters and loss history agree within each
+form's parity bound against the oracle, FP32 tighter (measured worst cases:
+pressure 3e-5 FP32, 4e-4 split bf16, 2e-3 mixed; the saturation and
+parameters 1e-5 or less).  Plain bf16 is compared on its parameters,
+saturation and loss history only, to 1e-2: its bf16-rounded forward makes the
+pressure swing by tens of percent under parameter changes of 3e-5 (the
+same ill-conditioning that puts it 10% off the oracle).  A batch of one is bitwise a single
+step, and scenarios on their own streams (the serving path) stay bitwise."""
 import numpy as np
 import pytest
 
-from helpers import say
+from helpers import check, say
 from paper_2604_20731_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +45,19 @@ def _same(a, b):
             and sa == sb and np.array_equal(a.loss_history(), b.loss_history()))
 
 
+def _close(a, b, tol=1e-4, pressure=True):
+    pa, ca, _ = a.fields()
+    pb, cb, _ = b.fields()
+    ta, _, _, sa = a.get_state()
+    tb, _, _, sb = b.get_state()
+    if pressure:
+        check("p", pa, pb, tol)
+    check("S", ca, cb, tol)
+    check("theta", ta, tb, tol)
+    check("loss history", a.loss_history(), b.loss_history(), tol)
+    assert sa == sb
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,ne,width,n", [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2),
                                              ("bf16x3f", 128, 128, 2), ("bf16", 64, 64, 3),
@@ -51,19 +76,37 @@ def test_bucket_step_equals_single_steps(prec, ne, width, n):
         bucket.step(dts)
         for sc, dt in zip(singles, dts):
             sc.step(dt)
+    tol = {"fp32": 1e-4, "bf16x3": 1e-3, "bf16x3f": 5e-3, "bf16": 1e-2}[prec]
+    with_p = prec != "bf16"
     for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
-        assert _same(a, b), (prec, ne, width, k)
+        say(f"  scenario {k}")
+        _close(a, b, tol, with_p)
     # a run of consecutive scenarios of the bucket is itself a batch
     crv.step_batch(bucket.scenarios[1:], dts[1:])
     for sc, dt in zip(singles[1:], dts[1:]):
         sc.step(dt)
-    for a, b in zip(bucket.scenarios, singles):
-        if a is not bucket.scenarios[0]:
-            assert _same(a, b)
+    for a, b in zip(bucket.scenarios[1:], singles[1:]):
+        _close(a, b, tol, with_p)
     bucket.close()
     for sc in singles:
         sc.close()
-    say(f"  {n} scenarios bitwise equal to single steps")
+    say(f"  {n} scenarios within rounding of single steps")
+
+
+def test_batch_of_one_is_a_single_step_bitwise():
+    from paper_2604_20731_amd import crv
+    probs = _problems(2, 64, 64)
+    cfg = crv.config(dim=2, n_elem=64, degree=2, width=64, hidden=4, precision="bf16x3f")
+    bucket = crv.Bucket(cfg, probs)
+    single = crv.Scenario(cfg, probs[0].log_perm, probs[0].porosity, probs[0].wells,
+                          probs[0].theta0)
+    for sc in (bucket.scenarios[0], single):
+        sc.pretrain_pressure(20)
+    dt = _dt(single, probs[0])
+    for _ in range(2):
+        crv.step_batch(bucket.scenarios[:1], [dt])
+        single.step(dt)
+    assert _same(bucket.scenarios[0], single)
 
 
 def test_unordered_or_mixed_batches_fall_back_to_streams():
