@@ -342,71 +342,91 @@ __device__ inline float layer1_operand(const float* z, int q, int dim) {
   return q == dim ? 1.f : v;
 }
 
-// Forward of one 16-node tile held by this wave.  The operands that hidden
-// layer l (0-based, l < L-1) feeds into the next product go to sink(l, bop)
-// as soon as they are built; on return h holds the last hidden layer.
-template <int W, int L, int MODE, int DIM, bool PIPE, typename Sink>
-__device__ inline void forward_tile(const float* sp, const typename MM<MODE>::felem* __restrict__ frag,
-                                    const Layer1<W, L, DIM>& l1, const float* z, int q, int lane,
-                                    float (&h)[W / 4], const Sink& sink) {
+// Forward of TPW 16-node tiles held by this wave (the tiles share every
+// weight-fragment load and give the wave independent chains of products and
+// activations).  The operands that hidden layer l (0-based, l < L-1) feeds
+// into the next product go to sink(l, bop) as soon as they are built; on
+// return h holds the last hidden layer of every tile.
+template <int W, int L, int MODE, int DIM, bool PIPE, int TPW, typename Sink>
+__device__ inline void forward_tiles(const float* sp,
+                                     const typename MM<MODE>::felem* __restrict__ frag,
+                                     const Layer1<W, L, DIM>& l1, const float (&z)[TPW][DIM],
+                                     int q, int lane, float (&h)[TPW][W / 4], const Sink& sink) {
   using T = MM<MODE>;
   using SM = Small<W, L, DIM>;
   constexpr int NKS = W / T::KS, NMB = W / 16;
   {
-    const float zb = layer1_operand(z, q, DIM);
     const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int mb = 0; mb < NMB; ++mb) {
-      const f32x4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(l1.a[mb], zb, zero, 0, 0, 0);
+    for (int t = 0; t < TPW; ++t) {
+      const float zb = layer1_operand(z[t], q, DIM);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[4 * mb + i] = tanh_of_scaled(a[i]);
+      for (int mb = 0; mb < NMB; ++mb) {
+        const f32x4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(l1.a[mb], zb, zero, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[t][4 * mb + i] = tanh_of_scaled(a[i]);
+      }
     }
   }
 #pragma unroll
   for (int l = 1; l < L; ++l) {
     const float* bl = sp + SM::BH + (l - 1) * W;
-    typename T::op bop[NKS];
+    typename T::op bop[TPW][NKS];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) bop[ks] = T::from(&h[ks * T::S]);
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) bop[t][ks] = T::from(&h[t][ks * T::S]);
     sink(l - 1, bop);
-    // one 16-row output block at a time: its activations replace h[4mb..4mb+3]
+    // one 16-row output block at a time: its activations replace h[.][4mb..4mb+3]
     // (the operands of this layer are already in bop).  With PIPE the
     // products of block mb+1 are issued before the tanh of block mb, so the
     // activation work covers the matrix-core latency (two accumulator tiles
-    // live); without it one tile is live, for register-bound callers
-    auto products = [&](int mb) {
-      f32x4_t acc;
+    // live per node tile); without it one, for register-bound callers
+    auto products = [&](int mb, f32x4_t (&acc)[TPW]) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = bl[cfeat(mb * 4 + i, q)];
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks)
-        acc = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc);
-      return acc;
+        for (int i = 0; i < 4; ++i) acc[t][i] = bl[cfeat(mb * 4 + i, q)];
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const auto f = T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W));
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = T::mma_w(f, bop[t][ks], acc[t]);
+      }
     };
     if constexpr (PIPE) {
-      f32x4_t cur = products(0);
+      f32x4_t cur[TPW], nxt[TPW];
+      products(0, cur);
 #pragma unroll
       for (int mb = 0; mb < NMB; ++mb) {
-        f32x4_t nxt = cur;
-        if (mb + 1 < NMB) nxt = products(mb + 1);
+        if (mb + 1 < NMB) products(mb + 1, nxt);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(cur[i]);
-        cur = nxt;
+        for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[t][mb * 4 + i] = tanh_of_scaled(cur[t][i]);
+          cur[t] = nxt[t];
+        }
       }
     } else {
 #pragma unroll
       for (int mb = 0; mb < NMB; ++mb) {
-        f32x4_t acc;
+        f32x4_t acc[TPW];
+        products(mb, acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = bl[cfeat(mb * 4 + i, q)];
+        for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks)
-          acc = T::mma_w(T::frag(frag + frag_index<MODE>(l - 1, 0, mb, ks, lane, 0, W)), bop[ks], acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h[mb * 4 + i] = tanh_of_scaled(acc[i]);
+          for (int i = 0; i < 4; ++i) h[t][mb * 4 + i] = tanh_of_scaled(acc[t][i]);
       }
     }
   }
+}
+
+// 16-node tiles per wave of the forward: two (shared fragment loads, two
+// independent chains) where the registers of two tiles keep four waves per
+// SIMD, that is up to width 64
+template <int W>
+constexpr int fwd_tpw() {
+  return W <= 64 ? 2 : 1;
 }
 
 template <int W, int L, int MODE, int DIM>
@@ -421,31 +441,42 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
   __shared__ float sp[SM::SIZE];
   SM::stage(th, sp, threadIdx.x, blockDim.x);
   __syncthreads();
+  constexpr int TPW = fwd_tpw<W>();
   const int lane = threadIdx.x & 63, q = lane >> 4, n = lane & 15;
   const int64_t total = ipow(geo.n, DIM);
-  const int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const int64_t p = tile * 16 + n;
-  if (tile * 16 >= total) return;  // whole wave leaves together
-  float z[DIM];
-  bool interior = false;
-  if (p < total) node_z<DIM>(p, geo.n, geo.ne, z, &interior);
-  else
-    for (int c = 0; c < DIM; ++c) z[c] = 0.f;
+  // tile t of wave w in this block: tile (blockIdx.x * TPW + t) * 4 + w
+  const int64_t tile0 = int64_t(blockIdx.x) * 4 * TPW + (threadIdx.x >> 6);
+  if (tile0 * 16 >= total) return;  // whole wave leaves together
+  float z[TPW][DIM];
+  bool interior[TPW];
+  int64_t p[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    p[t] = (tile0 + 4 * t) * 16 + n;
+    interior[t] = false;
+    if (p[t] < total) node_z<DIM>(p[t], geo.n, geo.ne, z[t], &interior[t]);
+    else
+      for (int c = 0; c < DIM; ++c) z[t][c] = 0.f;
+  }
   Layer1<W, L, DIM> l1;
   l1.load(sp, lane);
-  float h[NR];
-  forward_tile<W, L, MODE, DIM, true>(sp, frag, l1, z, q, lane, h, NoSink());
+  float h[TPW][NR];
+  forward_tiles<W, L, MODE, DIM, true, TPW>(sp, frag, l1, z, q, lane, h, NoSink());
   const float* wo = sp + SM::WO;
-  float s = 0.f;
 #pragma unroll
-  for (int t = 0; t < NR; ++t) s += wo[cfeat(t, q)] * h[t];
-  s += __shfl_xor(s, 16, 64);
-  s += __shfl_xor(s, 32, 64);
-  if (q == 0 && p < total) u[p] = interior ? s + wo[W] : 0.f;
+  for (int t = 0; t < TPW; ++t) {
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s += wo[cfeat(r, q)] * h[t][r];
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (q == 0 && p[t] < total) u[p[t]] = interior[t] ? s + wo[W] : 0.f;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Backward.  Block = NW waves, a block step covers NB = 16*NW nodes.  The
+// Backward.  Block = NW waves of TPW 16-node tiles each, a block step covers
+// NB = 16*NW*TPW nodes (tile t of wave w: nodes 16 (t NW + w) .. + 15).  The
 // adjoint field g_u = 2 A^T q is evaluated per node from q and alpha (no g_u
 // array), and each block also sums its share of LOSS = RES . q into
 // loss_part[block].
@@ -461,17 +492,18 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 // node data (g_u, coordinates) alternate by block step for the same reason.
 // ---------------------------------------------------------------------------
 // waves per SIMD the register allocation must leave room for: plain-bf16
-// operands at width <= 64 fit three, everything else two
-template <int W, int MODE>
+// operands at width <= 64 fit three with one tile per wave, everything else
+// two
+template <int W, int MODE, int TPW>
 constexpr int bwd_min_waves() {
-  return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64) ? 3 : 2;
+  return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64 && TPW == 1) ? 3 : 2;
 }
 
-template <int W, int L, int MODE, int DIM, int NW>
+template <int W, int L, int MODE, int DIM, int NW, int TPW>
 struct BwdShape {
   using T = MM<MODE>;
   using E = typename T::lelem;
-  static constexpr int NB = 16 * NW;           // nodes per block step
+  static constexpr int NB = 16 * NW * TPW;     // nodes per block step
   static constexpr int LD = NB + T::PAD;       // row pitch of the transposed buffers
   static constexpr int NTH = 64 * NW;
   // LDS of one block with nd copies of the delta tile and the node data
@@ -483,7 +515,7 @@ struct BwdShape {
   // register budget (bwd_min_waves per SIMD) allow (0: does not fit)
   static constexpr int blocks_per_cu(int nd) {
     const int by_lds = int((160u * 1024u) / bytes(nd));
-    const int by_regs = bwd_min_waves<W, MODE>() * 4 / NW;
+    const int by_regs = bwd_min_waves<W, MODE, TPW>() * 4 / NW;
     const int b = by_lds < by_regs ? by_lds : (by_regs < 1 ? 1 : by_regs);
     return b > 4 ? 4 : b;
   }
@@ -494,8 +526,8 @@ struct BwdShape {
   static constexpr size_t lds_bytes() { return bytes(ND); }
 };
 
-template <int W, int L, int MODE, int DIM, int NW>
-__global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd_mfma(Geom geo, int64_t ldp,
+template <int W, int L, int MODE, int DIM, int NW, int TPW>
+__global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_mlp_bwd_mfma(Geom geo, int64_t ldp,
                                                              const float* __restrict__ th,
                                                              const typename MM<MODE>::felem* __restrict__ frag,
                                                              const float* __restrict__ qg,
@@ -511,7 +543,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   res = zofs(res, zb); partials = zofs(partials, zb); loss_part = zofs(loss_part, zb);
   obs_w = zofs(obs_w, zb); obs_d = zofs(obs_d, zb); u = zofs(u, zb);
   using T = MM<MODE>;
-  using BS = BwdShape<W, L, MODE, DIM, NW>;
+  using BS = BwdShape<W, L, MODE, DIM, NW, TPW>;
   using E = typename BS::E;
   using SM = Small<W, L, DIM>;
   constexpr int NR = W / 4, NKS = W / T::KS, NMB = W / 16;
@@ -538,7 +570,9 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
   const int tid = threadIdx.x;
   const int w = (OWN % NMB != 0) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6);
   const int lane = tid & 63, q = lane >> 4, n = lane & 15;
-  const int col = w * 16 + n;  // this lane's node column in the block step
+  int col[TPW];  // this lane's node column of each of its tiles in the block step
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) col[t] = (t * NW + w) * 16 + n;
   const int q4 = tid & 3;
   SM::stage(th, sp, tid, NTH);
   __syncthreads();
@@ -568,12 +602,14 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
 #pragma unroll
     for (int c = 0; c < DIM; ++c) s_w1[c][f] = 0.f;
   }
-  auto sink = [&](int l, const typename T::op(&bo)[NKS]) {
+  auto sink = [&](int l, const typename T::op(&bo)[TPW][NKS]) {
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
-      for (int v = 0; v < T::S; ++v)
-        T::lds_put_elem(Hall + (l * W + cfeat(ks * T::S + v, q)) * LD + col, HPL, bo[ks], v);
+      for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+        for (int v = 0; v < T::S; ++v)
+          T::lds_put_elem(Hall + (l * W + cfeat(ks * T::S + v, q)) * LD + col[t], HPL, bo[t][ks], v);
   };
 
   int ub = 0, gb = 0;  // copy of Dt for the next use; copy of the node data
@@ -597,37 +633,45 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
     } else {
       asm volatile("" : "+s"(fr));
     }
-    const int64_t p = step * NB + col;
-    float z[DIM];
-    bool interior = false;
-    const bool valid = p < total;
-    if (valid) node_z<DIM>(p, geo.n, geo.ne, z, &interior);
-    else
-      for (int c = 0; c < DIM; ++c) z[c] = 0.f;
-    // the adjoint's loads first: their latency hides behind the recompute
-    int64_t iq = -1;
-    float gv = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
-    if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
-    if (obs_w && iq >= 0) {
-      // data misfit w (u - d)^2 of the inverse problem (interior nodes)
-      const float wo = obs_w[p], r = u[p] - obs_d[p];
-      gv += 2.f * wo * r;
-      if (q == 0) lacc += wo * r * r;
-    }
-    float d[NR];
-    forward_tile<W, L, MODE, DIM, (W <= 64)>(sp, fr, l1, z, q, lane, d, sink);
-    if (q == 0) {
-      Gs[col] = gv;
+    float z[TPW][DIM], gv[TPW];
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) Zs[c][col] = z[c];
+    for (int t = 0; t < TPW; ++t) {
+      const int64_t p = step * NB + col[t];
+      bool interior = false;
+      const bool valid = p < total;
+      if (valid) node_z<DIM>(p, geo.n, geo.ne, z[t], &interior);
+      else
+        for (int c = 0; c < DIM; ++c) z[t][c] = 0.f;
+      // the adjoint's loads first: their latency hides behind the recompute
+      int64_t iq = -1;
+      gv[t] = valid ? adjoint_at<float, DIM>(geo, qg, alpha, p, &iq) : 0.f;
+      if (q == 0 && iq >= 0) lacc += res[iq] * qg[iq];
+      if (obs_w && iq >= 0) {
+        // data misfit w (u - d)^2 of the inverse problem (interior nodes)
+        const float ow = obs_w[p], r = u[p] - obs_d[p];
+        gv[t] += 2.f * ow * r;
+        if (q == 0) lacc += ow * r * r;
+      }
+    }
+    float d[TPW][NR];
+    forward_tiles<W, L, MODE, DIM, (W <= 64), TPW>(sp, fr, l1, z, q, lane, d, sink);
+    if (q == 0) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        Gs[col[t]] = gv[t];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Zs[c][col[t]] = z[t][c];
+      }
     }
     // h_L through Dt for the output layer; then delta_L = g w_out (1 - h_L^2)
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-      const int f = cfeat(t, q);
-      T::lds_put(Dt + f * LD + col, DPL, d[t]);
-      d[t] = gv * wo[f] * (1.f - d[t] * d[t]);
-    }
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int f = cfeat(r, q);
+        T::lds_put(Dt + f * LD + col[t], DPL, d[t][r]);
+        d[t][r] = gv[t] * wo[f] * (1.f - d[t][r] * d[t][r]);
+      }
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < FPT; ++f) {
@@ -652,18 +696,21 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
         Dt = Dts[ub];
       }
       // delta_l into Dt; for l >= 2 as the split operands the chain below uses
-      typename T::op bop[NKS];
-      if (l >= 2) {
+      typename T::op bop[TPW][NKS];
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          bop[ks] = T::from(&d[ks * T::S]);
+      for (int t = 0; t < TPW; ++t) {
+        if (l >= 2) {
 #pragma unroll
-          for (int v = 0; v < T::S; ++v)
-            T::lds_put_elem(Dt + cfeat(ks * T::S + v, q) * LD + col, DPL, bop[ks], v);
+          for (int ks = 0; ks < NKS; ++ks) {
+            bop[t][ks] = T::from(&d[t][ks * T::S]);
+#pragma unroll
+            for (int v = 0; v < T::S; ++v)
+              T::lds_put_elem(Dt + cfeat(ks * T::S + v, q) * LD + col[t], DPL, bop[t][ks], v);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) T::lds_put(Dt + cfeat(r, q) * LD + col[t], DPL, d[t][r]);
         }
-      } else {
-#pragma unroll
-        for (int t = 0; t < NR; ++t) T::lds_put(Dt + cfeat(t, q) * LD + col, DPL, d[t]);
       }
       __syncthreads();
       if (l >= 2) {
@@ -698,9 +745,8 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
           for (int k = 0; k < QN; ++k) {
             const float dv = T::lds_get(dr + k, DPL);
             sb += dv;
-            if (l == 1)
 #pragma unroll
-              for (int c = 0; c < DIM; ++c) sw[c] += dv * Zs[c][q4 * QN + k];
+            for (int c = 0; c < DIM; ++c) sw[c] += dv * Zs[c][q4 * QN + k];
           }
           s_b[0][f] += sb;
 #pragma unroll
@@ -708,20 +754,28 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
         }
       }
       if (l >= 2) {
-        // delta_{l-1} = (W_l^T delta_l) (1 - h_{l-1}^2)
+        // delta_{l-1} = (W_l^T delta_l) (1 - h_{l-1}^2), one fragment load for all tiles
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
-          f32x4_t c2;
+          f32x4_t c2[TPW];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) c2[i] = 0.f;
+          for (int t = 0; t < TPW; ++t)
 #pragma unroll
-          for (int ks = 0; ks < NKS; ++ks)
-            c2 = T::mma_w(T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W)), bop[ks], c2);
+            for (int i = 0; i < 4; ++i) c2[t][i] = 0.f;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float hv = T::lds_get(Hall + ((l - 2) * W + cfeat(mb * 4 + i, q)) * LD + col, HPL);
-            d[mb * 4 + i] = c2[i] * (1.f - hv * hv);
+          for (int ks = 0; ks < NKS; ++ks) {
+            const auto f = T::frag(fr + frag_index<MODE>(l - 2, 1, mb, ks, lane, 0, W));
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) c2[t] = T::mma_w(f, bop[t][ks], c2[t]);
           }
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float hv =
+                  T::lds_get(Hall + ((l - 2) * W + cfeat(mb * 4 + i, q)) * LD + col[t], HPL);
+              d[t][mb * 4 + i] = c2[t][i] * (1.f - hv * hv);
+            }
         }
       }
       if constexpr (ND == 1) __syncthreads();  // Dt (and Hall in the next step) are rewritten
@@ -731,7 +785,6 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE>())) void k_mlp_bwd
       gb ^= 1;
     }
   }
-
   // ---- this block's partial gradient row ----
   float* row = partials + int64_t(blockIdx.x) * ldp;
 #pragma unroll
@@ -922,7 +975,7 @@ static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u,
   const int64_t total = ipow(g.n, g.dim);
   const int64_t tiles = (total + 15) / 16;
   const auto* fr = static_cast<const typename MM<MODE>::felem*>(frag);
-  const dim3 grid(cdiv(tiles, 4), 1, bz.n);
+  const dim3 grid(cdiv(tiles, 4 * fwd_tpw<W>()), 1, bz.n);
   if constexpr (L == 4) {
     if (g.dim == 3) {
       k_mlp_fwd_mfma<W, L, MODE, 3><<<grid, 256, 0, st>>>(g, th, fr, u, tb, bz.zb);
@@ -964,10 +1017,18 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 // slower than 4 waves at three blocks per CU)
 constexpr int bwd_nw(int width, int) { return width >= 128 ? 8 : 4; }
 
+// 16-node tiles per wave: two for the plain-bf16 and mixed backward at width
+// 64 in 2D (two blocks per CU of two waves per SIMD, each wave with two
+// independent chains and one fragment load per two products), one otherwise
+constexpr int bwd_tpw(int width, int mode, int dim) {
+  return (width == 64 && dim == 2 && (mode == NET_BF16 || mode == NET_MIX)) ? 2 : 1;
+}
+
 // resident blocks per CU that the LDS of one block allows (160 KB per CU)
 template <int W, int L, int MODE, int DIM>
 static int bwd_lds_blocks() {
-  const size_t lds = BwdShape<W, L, MODE, DIM, bwd_nw(W, MODE)>::lds_bytes();
+  const size_t lds =
+      BwdShape<W, L, MODE, DIM, bwd_nw(W, MODE), bwd_tpw(W, MODE, DIM)>::lds_bytes();
   return int(std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / lds)));
 }
 
@@ -982,12 +1043,14 @@ static int bwd_per_cu(int dim, bool query) {
     if constexpr (L == 4) {
       lds_blocks = bwd_lds_blocks<W, L, MODE, 3>();
       if (query)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_mlp_bwd_mfma<W, L, MODE, 3, NW>, 64 * NW, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, k_mlp_bwd_mfma<W, L, MODE, 3, NW, bwd_tpw(W, MODE, 3)>, 64 * NW, 0);
     }
   } else {
     lds_blocks = bwd_lds_blocks<W, L, MODE, 2>();
     if (query)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_mlp_bwd_mfma<W, L, MODE, 2, NW>, 64 * NW, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, k_mlp_bwd_mfma<W, L, MODE, 2, NW, bwd_tpw(W, MODE, 2)>, 64 * NW, 0);
   }
   if (!query) return lds_blocks;
   if (e != hipSuccess) {
@@ -1006,7 +1069,7 @@ int mlp_bwd_mfma_blocks(const Geom& g, int width, int hidden, int mode, int cu_c
   CRV_BWD_SHAPES(CRV_BB)
 #undef CRV_BB
   const int64_t total = ipow(g.n, g.dim);
-  const int nb = 16 * nw;
+  const int nb = 16 * nw * bwd_tpw(width, mode, g.dim);
   const int64_t steps = (total + nb - 1) / nb;
   return int(std::max<int64_t>(1, std::min<int64_t>(steps, int64_t(cu_count) * per_cu)));
 }
@@ -1021,12 +1084,12 @@ static void bwd_inst(const Geom& g, int64_t ldp, const float* th, const void* fr
   const dim3 grid(blocks, 1, bz.n);
   if constexpr (L == 4) {
     if (g.dim == 3) {
-      k_mlp_bwd_mfma<W, L, MODE, 3, NW><<<grid, 64 * NW, 0, st>>>(
+      k_mlp_bwd_mfma<W, L, MODE, 3, NW, bwd_tpw(W, MODE, 3)><<<grid, 64 * NW, 0, st>>>(
           g, ldp, th, fr, q, alpha, res, partials, loss_part, bz.zb, ow, od, u);
       return;
     }
   }
-  k_mlp_bwd_mfma<W, L, MODE, 2, NW><<<grid, 64 * NW, 0, st>>>(
+  k_mlp_bwd_mfma<W, L, MODE, 2, NW, bwd_tpw(W, MODE, 2)><<<grid, 64 * NW, 0, st>>>(
       g, ldp, th, fr, q, alpha, res, partials, loss_part, bz.zb, ow, od, u);
 }
 
