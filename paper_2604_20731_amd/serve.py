@@ -164,6 +164,13 @@ class Server:
                 time.sleep(0.0002)
         span = max(last_done - first_arrival, 1e-9)
         lat_a = np.array(lat) if lat else np.array([np.nan])
+        # the same percentiles per scenario shape: what the tail is made of
+        by_shape = {}
+        for r in results.values():
+            by_shape.setdefault(f"{r['n_elem']}^2 w{r['width']}", []).extend(r["latencies_ms"])
+        shapes = {k: {"steps": len(v), "p50_step_ms": float(np.percentile(v, 50)),
+                      "p99_step_ms": float(np.percentile(v, 99))}
+                  for k, v in sorted(by_shape.items()) if v}
         return {
             "scenarios": len(results),
             "scenarios_per_s": len(results) / span,
@@ -173,6 +180,7 @@ class Server:
             "mean_queue_wait_s": float(np.mean(waits)) if waits else 0.0,
             "max_queue_wait_s": float(np.max(waits)) if waits else 0.0,
             "span_s": span,
+            "by_shape": shapes,
             "max_active_seen": most_active,
             "peak_workspace_bytes": peak_bytes,
             "refused": refused,
