@@ -276,14 +276,16 @@ def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
     return out
 
 
-def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="bucket",
+def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="shared",
                 profile=False):
     """Aggregate coupled steps/s of several 512^2 scenarios stepped together by
     crv_step_batch.  mode "bucket": the scenarios' workspaces lie at one
     stride in one allocation and every kernel of the step runs once for all of
-    them (the scenario index selects the workspace); "streams": each scenario
-    on its own stream, their captured steps overlapping on the device.  With
-    profile, one more batched step runs event-timed (bucket mode)."""
+    them (the scenario index selects the workspace), bitwise single steps;
+    "shared": the same with the network backward sharing the device's blocks
+    among the scenarios (crv_step_batch_shared); "streams": each scenario on
+    its own stream, their captured steps overlapping on the device.  With
+    profile, one more batched step runs event-timed (bucket modes)."""
     import torch
     from paper_2604_20731_amd import crv, inputs
     probs = [inputs.make_problem("b512", seed=sd, n_elem=n_elem) for sd in seeds]
@@ -291,7 +293,8 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="buc
     cfg = crv.config(dim=2, n_elem=p0.n_elem, degree=p0.degree, width=p0.width,
                      hidden=p0.hidden, precision=precision)
     bucket = None
-    if mode == "bucket":
+    shared = mode == "shared"
+    if mode in ("bucket", "shared"):
         bucket = crv.Bucket(cfg, probs)
         ctxs = bucket.scenarios
     else:
@@ -303,17 +306,17 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="buc
         p, _, _ = sc.fields()
         dts.append(cfl_dt_from_pressure(p, np.exp(pr.log_perm), pr.porosity, pr.n_elem))
     for _ in range(warmup):
-        crv.step_batch(ctxs, dts)
+        crv.step_batch(ctxs, dts, shared)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        crv.step_batch(ctxs, dts)
+        crv.step_batch(ctxs, dts, shared)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernels = {}
     if profile and bucket is not None:
         ctxs[0].profile_enable(True)
-        crv.step_batch(ctxs, dts)
+        crv.step_batch(ctxs, dts, shared)
         prof = ctxs[0].profile_read()
         ctxs[0].profile_enable(False)
         kernels = {name: {"ms_per_step": ms, "launches_per_step": n,
@@ -385,13 +388,18 @@ def main():
     log(f"{args.precision} single scenario, {args.steps} steps (+ event-timed kernels)")
     single, kernels = run_single(prob, args.precision, args.steps, args.warmup, args.pretrain,
                                  not args.no_profile)
-    log(f"{args.precision} batched, one launch per kernel: {args.batch} scenarios x {args.steps} steps")
+    log(f"{args.precision} batched, one launch per kernel, backward blocks shared: {args.batch} "
+        f"scenarios x {args.steps} steps")
     batched, bkern = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
                                  args.pretrain, profile=True)
     kernel_rooflines(bkern, prob, args.precision, scenarios=args.batch)
     log(f"{args.precision} {args.batch} scenarios on their own streams, {args.steps} steps")
     streams = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
                           args.pretrain, mode="streams")
+    log(f"{args.precision} batched, each scenario with its own backward grid (bitwise single "
+        f"steps): {args.batch} scenarios x {args.steps} steps")
+    bitwise = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
+                          args.pretrain, mode="bucket")
     alt = None
     if args.alt_precision:
         log(f"{args.alt_precision}: single scenario and {args.batch} batched, {args.steps} steps")
@@ -425,6 +433,11 @@ def main():
                      pretrain_iters=200, steps=20)
         out = srv.run(inputs.serving_mix(args.serve))
         serving = {k: v for k, v in out.items() if k != "results"}
+        log("serving, every scenario on its own stream (no batching)")
+        srv = Server(hbm_budget_bytes=16 << 30, max_active=16, precision=args.precision,
+                     pretrain_iters=200, steps=20, batch=False)
+        out = srv.run(inputs.serving_mix(args.serve))
+        serving["streams"] = {k: v for k, v in out.items() if k not in ("results", "by_shape")}
     kernel_rooflines(kernels, prob, args.precision)
     big = None
     if args.big_kernels:
@@ -490,6 +503,7 @@ def main():
         "batched": batched,
         "batched_kernels": bkern,
         "streams_batched": streams,
+        "bitwise_batched": bitwise,
         "vs_plain": batched["value"] / plain["value"],
         "vs_single": batched["value"] / single["value"],
         "alt_precision": alt,

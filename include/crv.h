@@ -188,18 +188,22 @@ crv_status crv_step(crv_ctx* ctx, double dt);
 /* Serving form of crv_step (IGA-ADS-CRVPINN algorithm, steps 4-7, for n
  * scenarios): one coupled step of length dts[i] for each of the n contexts
  * (all validated first: CRV_EINVAL for a NULL context or a bad dt,
- * CRV_ESTATE for a context not pretrained; nothing is enqueued then).
- * Contexts of one configuration (2D, matrix-core network) whose workspaces
- * lie at one stride, in order and without overlap, advance together: every
- * kernel of the step runs once for all of them (the scenario selects the
- * workspace), on the first context's stream, ordered after the work queued
- * on the others' streams and before their later work.  The network backward
- * then shares the blocks that fit on the device among the scenarios, so
- * their gradients round differently from crv_step's (the same sums grouped
- * otherwise).  Any other set of contexts steps each on its own stream with
- * no host wait, with exactly the results of n crv_step calls.  Asynchronous
- * like crv_step. */
+ * CRV_ESTATE for a context not pretrained; nothing is enqueued then), with
+ * exactly the results of n crv_step calls.  Contexts of one configuration
+ * (2D, matrix-core network) whose workspaces lie at one stride, in order and
+ * without overlap, advance together: every kernel of the step runs once for
+ * all of them (the scenario selects the workspace), on the first context's
+ * stream, ordered after the work queued on the others' streams and before
+ * their later work.  Any other set of contexts steps each on its own stream
+ * with no host wait.  Asynchronous like crv_step.
+ * crv_step_batch_shared: the same, except that a batched network backward
+ * shares the blocks that fit on the device among the scenarios (each
+ * scenario's gradient is the same sum grouped into fewer partial rows), which
+ * is faster for large grids; results then match crv_step to rounding, which
+ * Adam's normalised steps carry on (within each precision form's parity
+ * bound), not bitwise. */
 crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n);
+crv_status crv_step_batch_shared(crv_ctx* const* ctxs, const double* dts, int n);
 
 /* Outputs (any may be NULL): p_nodal (N+1)^d network pressure m*NN,
  * s_coefs nb^d, s_nodal (N+1)^d saturation at the nodes. Synchronises. */

@@ -128,6 +128,7 @@ int main() {
   const double dts[2] = {1e-3, 1e-3};
   expect("step_batch NULL context", crv_step_batch(none, dts, 2), CRV_EINVAL);
   expect("step_batch empty", crv_step_batch(nullptr, nullptr, 0), CRV_OK);
+  expect("step_batch_shared NULL context", crv_step_batch_shared(none, dts, 2), CRV_EINVAL);
 
   // the allocation-free Gram solve: sizes beyond its array, missing arrays
   float f = 0.f;

@@ -297,8 +297,9 @@ struct SolverBase {
   // scenario batching (2D float32 matrix-core contexts of one configuration)
   virtual bool batchable() const { return false; }
   virtual int64_t batch_tag() const { return 0; }
-  virtual crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb) {
-    (void)all, (void)dts, (void)n, (void)zb;
+  virtual crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb,
+                                  bool share) {
+    (void)all, (void)dts, (void)n, (void)zb, (void)share;
     return fail(CRV_EINVAL, "this context cannot run a batched step");
   }
 };
@@ -573,12 +574,16 @@ struct Solver : SolverBase {
   bool obs_on = false;
 
   // partial gradient rows of the network backward; returns the row count.
-  // The matrix-core backward also leaves one loss partial per block.  A batch
-  // of n scenarios shares the blocks that fit on the device at once (about
-  // bwd_blocks / n each), so that all of them run in one round and each
-  // scenario writes n times fewer partial rows; its gradient sums then
-  // round differently from a single step's (same sums, other grouping).
-  int bwd_grid() const { return bz.n > 1 ? std::max(1, (bwd_blocks + bz.n - 1) / bz.n) : bwd_blocks; }
+  // The matrix-core backward also leaves one loss partial per block.  A
+  // batch keeps each scenario's own grid (bitwise a single step), unless it
+  // shares the blocks that fit on the device at once among its n scenarios
+  // (about bwd_blocks / n each): then all of them run in one round and each
+  // writes n times fewer partial rows, its gradient sums rounding differently
+  // from a single step's (the same sums, grouped otherwise).
+  bool share_bwd = false;
+  int bwd_grid() const {
+    return (bz.n > 1 && share_bwd) ? std::max(1, (bwd_blocks + bz.n - 1) / bz.n) : bwd_blocks;
+  }
   int adj_np = 0;
   int64_t ldp() const { return partial_pitch(P); }  // pitch of the matrix-core partial rows
   int loss_count() const { return mfma ? bwd_grid() : adj_np; }
@@ -885,12 +890,14 @@ struct Solver : SolverBase {
   // Scenarios of this context's configuration whose workspaces lie zb bytes
   // apart, starting with this one, advance together: every kernel of the step
   // runs once for all of them (blockIdx.z selects the scenario), replayed
-  // from a graph captured per (count, stride) on this context's stream.  The
-  // kernels reduce in an order that does not depend on the batch, so each
-  // scenario's result is bitwise the one of its own crv_step.
+  // from a graph captured per (count, stride, sharing) on this context's
+  // stream.  Without sharing every kernel reduces in an order that does not
+  // depend on the batch, so each scenario's result is bitwise the one of its
+  // own crv_step; with sharing the backward's grouping differs (above).
   struct BatchGraph {
     int n;
     int64_t zb;
+    bool share;
     hipGraphExec_t exec;
   };
   std::vector<BatchGraph> g_batch;
@@ -910,7 +917,8 @@ struct Solver : SolverBase {
     return join_ev[k];
   }
 
-  crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb) override {
+  crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb,
+                          bool share) override {
     // order after the work already queued on the other scenarios' streams
     size_t ev = 0;
     for (int k = 1; k < n; ++k) {
@@ -929,19 +937,23 @@ struct Solver : SolverBase {
     if (use_graphs()) {
       hipGraphExec_t exec = nullptr;
       for (const BatchGraph& bg : g_batch)
-        if (bg.n == n && bg.zb == zb) exec = bg.exec;
+        if (bg.n == n && bg.zb == zb && bg.share == share) exec = bg.exec;
       if (!exec) {
         bz = Batch{n, zb};
+        share_bwd = share;
         s = capture(&exec, [&] { step_body(); });
         bz = one;
+        share_bwd = false;
         if (s) return s;
-        g_batch.push_back(BatchGraph{n, zb, exec});
+        g_batch.push_back(BatchGraph{n, zb, share, exec});
       }
       CRV_HIP(hipGraphLaunch(exec, st));
     } else {
       bz = Batch{n, zb};
+      share_bwd = share;
       step_body();
       bz = one;
+      share_bwd = false;
     }
     if ((s = check_launch())) return s;
     // and the other streams' later work after the batch
@@ -1329,7 +1341,7 @@ crv_status crv_step(crv_ctx* c, double dt) {
   return sv.step(dt);
 }
 
-crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
+static crv_status step_batch(crv_ctx* const* ctxs, const double* dts, int n, bool share) {
   if (n < 0 || (n > 0 && (!ctxs || !dts))) return fail(CRV_EINVAL, "bad batch arrays");
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !ctxs[i]->impl) return fail(CRV_EINVAL, "context is NULL");
@@ -1354,7 +1366,7 @@ crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
     if (ok) {
       std::vector<SolverBase*> all(static_cast<size_t>(n));
       for (int i = 0; i < n; ++i) all[size_t(i)] = ctxs[i]->impl.get();
-      return s0.step_batched(all.data(), dts, n, zb);
+      return s0.step_batched(all.data(), dts, n, zb, share);
     }
   }
   for (int i = 0; i < n; ++i) {
@@ -1362,6 +1374,14 @@ crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
     if (s) return s;
   }
   return CRV_OK;
+}
+
+crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
+  return step_batch(ctxs, dts, n, false);
+}
+
+crv_status crv_step_batch_shared(crv_ctx* const* ctxs, const double* dts, int n) {
+  return step_batch(ctxs, dts, n, true);
 }
 
 crv_status crv_get_fields(crv_ctx* c, double* p_nodal, double* s_coefs, double* s_nodal) {

@@ -2,20 +2,23 @@
 workspaces lie at a fixed stride in one allocation (crv.Bucket) advance with
 one launch per kernel of the coupled step, blockIdx.z selecting the scenario
 (the unit batched is the coupled step of the IGA-ADS-CRVPINN algorithm,
-steps 4-7).  Every kernel but the network backward computes exactly what it
-computes for one scenario; the backward spreads the device's resident blocks
-over the batch, so each scenario's parameter gradient is the same sum grouped
-into fewer partial rows.  Bucket steps therefore match single steps to
-rounding, which Adam's normalised steps carry into the parameters and the
-network's output (a small difference of large terms) amplifies: after 2
-coupled steps the fields, parameters and loss history agree within each
-form's parity bound against the oracle, FP32 tighter (measured worst cases:
-pressure 3e-5 FP32, 4e-4 split bf16, 2e-3 mixed; the saturation and
-parameters 1e-5 or less).  Plain bf16 is compared on its parameters,
-saturation and loss history only, to 1e-2: its bf16-rounded forward makes the
-pressure swing by tens of percent under parameter changes of 3e-5 (the
-same ill-conditioning that puts it 10% off the oracle).  A batch of one is bitwise a single
-step, and scenarios on their own streams (the serving path) stay bitwise."""
+steps 4-7).
+
+crv_step_batch: every kernel reduces in an order that does not depend on the
+batch, so bucket steps equal single steps bitwise.
+
+crv_step_batch_shared: the network backward spreads the device's resident
+blocks over the batch, so each scenario's parameter gradient is the same sum
+grouped into fewer partial rows; Adam's normalised steps carry the rounding
+into the parameters and the network's output (a small difference of large
+terms) amplifies it: after 2 coupled steps the fields, parameters and loss
+history agree within each form's parity bound against the oracle, FP32
+tighter (measured worst cases: pressure 3e-5 FP32, 4e-4 split bf16, 2e-3
+mixed; the saturation and parameters 1e-5 or less).  Plain bf16 is compared
+on its parameters, saturation and loss history only, to 1e-2: its
+bf16-rounded forward makes the pressure swing by tens of percent under
+parameter changes of 3e-5 (the same ill-conditioning that puts it 10% off
+the oracle).  A batch of one is bitwise a single step either way."""
 import numpy as np
 import pytest
 
@@ -58,13 +61,12 @@ def _close(a, b, tol=1e-4, pressure=True):
     assert sa == sb
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec,ne,width,n", [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2),
-                                             ("bf16x3f", 128, 128, 2), ("bf16", 64, 64, 3),
-                                             ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3)])
-def test_bucket_step_equals_single_steps(prec, ne, width, n):
+CASES = [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2), ("bf16x3f", 128, 128, 2), ("bf16", 64, 64, 3),
+         ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3)]
+
+
+def _run(prec, ne, width, n, shared):
     from paper_2604_20731_amd import crv
-    say("bucket", prec, ne, width, n)
     probs = _problems(n, ne, width)
     cfg = crv.config(dim=2, n_elem=ne, degree=2, width=width, hidden=4, precision=prec)
     bucket = crv.Bucket(cfg, probs)
@@ -73,24 +75,44 @@ def test_bucket_step_equals_single_steps(prec, ne, width, n):
         sc.pretrain_pressure(20)
     dts = [_dt(sc, p) for sc, p in zip(singles, probs)]
     for _ in range(2):
-        bucket.step(dts)
+        bucket.step(dts, shared)
         for sc, dt in zip(singles, dts):
             sc.step(dt)
-    tol = {"fp32": 1e-4, "bf16x3": 1e-3, "bf16x3f": 5e-3, "bf16": 1e-2}[prec]
-    with_p = prec != "bf16"
+    return crv, bucket, singles, dts
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,ne,width,n", CASES)
+def test_bucket_step_equals_single_steps(prec, ne, width, n):
+    say("bucket", prec, ne, width, n)
+    crv, bucket, singles, dts = _run(prec, ne, width, n, False)
     for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
-        say(f"  scenario {k}")
-        _close(a, b, tol, with_p)
+        assert _same(a, b), (prec, ne, width, k)
     # a run of consecutive scenarios of the bucket is itself a batch
     crv.step_batch(bucket.scenarios[1:], dts[1:])
     for sc, dt in zip(singles[1:], dts[1:]):
         sc.step(dt)
     for a, b in zip(bucket.scenarios[1:], singles[1:]):
+        assert _same(a, b)
+    bucket.close()
+    for sc in singles:
+        sc.close()
+    say(f"  {n} scenarios bitwise equal to single steps")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,ne,width,n", CASES)
+def test_shared_bucket_step_matches_single_steps(prec, ne, width, n):
+    say("shared bucket", prec, ne, width, n)
+    crv, bucket, singles, dts = _run(prec, ne, width, n, True)
+    tol = {"fp32": 1e-4, "bf16x3": 1e-3, "bf16x3f": 5e-3, "bf16": 1e-2}[prec]
+    with_p = prec != "bf16"
+    for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
+        say(f"  scenario {k}")
         _close(a, b, tol, with_p)
     bucket.close()
     for sc in singles:
         sc.close()
-    say(f"  {n} scenarios within rounding of single steps")
 
 
 def test_batch_of_one_is_a_single_step_bitwise():
@@ -104,7 +126,7 @@ def test_batch_of_one_is_a_single_step_bitwise():
         sc.pretrain_pressure(20)
     dt = _dt(single, probs[0])
     for _ in range(2):
-        crv.step_batch(bucket.scenarios[:1], [dt])
+        crv.step_batch(bucket.scenarios[:1], [dt], shared=True)
         single.step(dt)
     assert _same(bucket.scenarios[0], single)
 

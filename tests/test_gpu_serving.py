@@ -28,13 +28,14 @@ def _mix(big=False):
 @pytest.mark.parametrize("prec,big", [("bf16x3f", False), ("bf16x3f", True), ("bf16x3", False),
                                       ("fp32", False)])
 def test_alone_equals_mix(prec, big):
-    """The default served form (the mixed network) included, with a 256^2
-    scenario and a width-128 one in the mix; the mix must actually overlap
-    (two or more scenarios active at once)."""
+    """Scenarios on their own streams: the default served form (the mixed
+    network) included, with a 256^2 scenario and a width-128 one in the mix;
+    the mix must actually overlap (two or more scenarios active at once) and
+    every result is bitwise the one of the scenario alone."""
     from paper_2604_20731_amd.serve import Server
     arrivals = _mix(big)
     srv = Server(hbm_budget_bytes=4 << 30, max_active=4, precision=prec, pretrain_iters=30,
-                 steps=3, keep_fields=True)
+                 steps=3, keep_fields=True, batch=False)
     mix = srv.run(arrivals)
     say(f"mix {prec} big={big}: {mix['scenarios']} scenarios, {mix['scenarios_per_s']:.1f}/s, "
         f"p50 {mix['p50_step_ms']:.2f} ms p99 {mix['p99_step_ms']:.2f} ms, "
@@ -43,7 +44,35 @@ def test_alone_equals_mix(prec, big):
     assert mix["max_active_seen"] >= 2
     for a in arrivals:
         alone = Server(hbm_budget_bytes=4 << 30, max_active=1, precision=prec, pretrain_iters=30,
-                       steps=3, keep_fields=True).run([a])
+                       steps=3, keep_fields=True, batch=False).run([a])
+        pm, sm, _ = mix["results"][a.seed]["fields"]
+        pa, sa, _ = alone["results"][a.seed]["fields"]
+        assert np.array_equal(pm, pa) and np.array_equal(sm, sa), a
+        assert len(mix["results"][a.seed]["latencies_ms"]) == 3
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["bf16x3f", "fp32"])
+def test_batched_serving_alone_equals_mix(prec):
+    """The batched server (slot pools; each pool advances in rounds, every run
+    of consecutive ready slots as one crv_step_batch): arrivals of three
+    shapes, several of each, so that batches form (the largest holds two or
+    more scenarios); every scenario's pressure and saturation are bitwise
+    those of its run alone."""
+    from paper_2604_20731_amd.serve import Server
+    shapes = [(64, 64), (64, 64), (48, 32), (64, 64), (48, 32), (96, 128), (96, 128), (64, 64)]
+    arrivals = [inputs.Arrival(t=0.0005 * k, n_elem=ne, width=w, seed=300 + k, n_wells=1 + k % 5)
+                for k, (ne, w) in enumerate(shapes)]
+    srv = Server(hbm_budget_bytes=4 << 30, max_active=8, precision=prec, pretrain_iters=30,
+                 steps=3, keep_fields=True, batch=True, pool_slots=4)
+    mix = srv.run(arrivals)
+    say(f"batched mix {prec}: {mix['scenarios']} scenarios, largest batch {mix['largest_batch']}, "
+        f"p50 {mix['p50_step_ms']:.2f} ms p99 {mix['p99_step_ms']:.2f} ms")
+    assert mix["scenarios"] == len(arrivals)
+    assert mix["largest_batch"] >= 2
+    for a in arrivals:
+        alone = Server(hbm_budget_bytes=4 << 30, max_active=1, precision=prec, pretrain_iters=30,
+                       steps=3, keep_fields=True, batch=True).run([a])
         pm, sm, _ = mix["results"][a.seed]["fields"]
         pa, sa, _ = alone["results"][a.seed]["fields"]
         assert np.array_equal(pm, pa) and np.array_equal(sm, sa), a
@@ -56,7 +85,7 @@ def test_budget_limits_concurrency():
     arrivals = _mix()
     one = crv.workspace_size(crv.config(n_elem=64, width=64, hidden=4, precision="bf16x3"))
     srv = Server(hbm_budget_bytes=int(1.5 * one), max_active=8, precision="bf16x3",
-                 pretrain_iters=10, steps=2)
+                 pretrain_iters=10, steps=2, batch=False)
     out = srv.run(arrivals)
     assert out["scenarios"] == len(arrivals)
     assert out["max_queue_wait_s"] >= 0.0
