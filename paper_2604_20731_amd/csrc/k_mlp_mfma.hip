@@ -40,7 +40,39 @@
 namespace crv {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// Two floats rounded to bf16 (nearest even) by one conversion into one
+// register, v0 in the low half and v1 in the high half.  The empty asm makes
+// the pair opaque, so every later use of a half (its float value, a 16-bit
+// store) is taken from this register by a shift, a mask or a high-half store,
+// instead of the compiler converting that float a second time on its own.
+__device__ inline unsigned int bf16_pair(float v0, float v1) {
+  unsigned int w = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2_t{v0, v1}, bf16x2_t));
+  asm("" : "+v"(w));
+  return w;
+}
+// the float values of the two halves (exact)
+__device__ inline float bf16_lo_float(unsigned int w) { return __builtin_bit_cast(float, w << 16); }
+__device__ inline float bf16_hi_float(unsigned int w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
+__device__ inline void put_bits(__bf16* p, unsigned int bits16) {
+  *reinterpret_cast<unsigned short*>(p) = (unsigned short)bits16;
+}
+// bf16 element v of a packed eight-value operand
+__device__ inline void put_elem(__bf16* p, const bf16x8_t& o, int v) {
+  const unsigned int w = __builtin_bit_cast(u32x4_t, o)[v >> 1];
+  put_bits(p, (v & 1) ? (w >> 16) : w);
+}
+// eight floats rounded to bf16 as one operand (four paired conversions)
+__device__ inline bf16x8_t bf16x8_from(const float* v) {
+  u32x4_t w;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = bf16_pair(v[2 * k], v[2 * k + 1]);
+  return __builtin_bit_cast(bf16x8_t, w);
+}
 
 template <int M>
 struct MM;
@@ -65,6 +97,10 @@ struct MM<NET_F32> {
   __device__ static inline op lds_op(const lelem* p, int) { return *p; }
   __device__ static inline float lds_get(const lelem* p, int) { return *p; }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = v; }
+  __device__ static inline void lds_put2(lelem* p0, lelem* p1, int, float v0, float v1) {
+    *p0 = v0;
+    *p1 = v1;
+  }
   __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int) { *p = o; }
 };
 
@@ -82,12 +118,7 @@ struct MM<NET_BF16> {
   __device__ static inline f32x4_t mma_w(wop a, op b, f32x4_t c) { return mma(a, b, c); }
   static constexpr int NPL = 1;
   __device__ static inline op frag(const felem* p) { return *reinterpret_cast<const op*>(p); }
-  __device__ static inline op from(const float* v) {
-    op o;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (__bf16)v[k];
-    return o;
-  }
+  __device__ static inline op from(const float* v) { return bf16x8_from(v); }
   __device__ static inline void put(felem* p, float w) { p[0] = (__bf16)w; }
   __device__ static inline f32x4_t row_sum(op a, f32x4_t c) {
     op one;
@@ -98,7 +129,12 @@ struct MM<NET_BF16> {
   __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
-  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { *p = o[v]; }
+  __device__ static inline void lds_put2(lelem* p0, lelem* p1, int, float v0, float v1) {
+    const unsigned int w = bf16_pair(v0, v1);
+    put_bits(p0, w);
+    put_bits(p1, w >> 16);
+  }
+  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { put_elem(p, o, v); }
 };
 
 struct SplitOp {
@@ -128,14 +164,14 @@ struct MM<NET_X3> {
     return op{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + 64 * S)};
   }
   __device__ static inline op from(const float* v) {
-    op o;
+    u32x4_t wh, wl;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const __bf16 h = (__bf16)v[k];
-      o.h[k] = h;
-      o.l[k] = (__bf16)(v[k] - float(h));
+    for (int k = 0; k < 4; ++k) {
+      const unsigned int h = bf16_pair(v[2 * k], v[2 * k + 1]);
+      wh[k] = h;
+      wl[k] = bf16_pair(v[2 * k] - bf16_lo_float(h), v[2 * k + 1] - bf16_hi_float(h));
     }
-    return o;
+    return op{__builtin_bit_cast(bf16x8_t, wh), __builtin_bit_cast(bf16x8_t, wl)};
   }
   // the subtraction is kept apart from whatever produced w (no fused
   // multiply-add with a caller's product), so the Adam kernel's in-place
@@ -164,9 +200,17 @@ struct MM<NET_X3> {
     p[0] = h;
     p[plane] = (__bf16)(v - float(h));
   }
+  __device__ static inline void lds_put2(lelem* p0, lelem* p1, int plane, float v0, float v1) {
+    const unsigned int h = bf16_pair(v0, v1);
+    const unsigned int l = bf16_pair(v0 - bf16_lo_float(h), v1 - bf16_hi_float(h));
+    put_bits(p0, h);
+    put_bits(p1, h >> 16);
+    put_bits(p0 + plane, l);
+    put_bits(p1 + plane, l >> 16);
+  }
   __device__ static inline void lds_put_elem(lelem* p, int plane, const op& o, int v) {
-    p[0] = o.h[v];
-    p[plane] = o.l[v];
+    put_elem(p, o.h, v);
+    put_elem(p + plane, o.l, v);
   }
 };
 
@@ -195,12 +239,7 @@ struct MM<NET_MIX> {
   __device__ static inline wop frag(const felem* p) {
     return wop{*reinterpret_cast<const bf16x8_t*>(p), *reinterpret_cast<const bf16x8_t*>(p + 64 * S)};
   }
-  __device__ static inline op from(const float* v) {
-    op o;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (__bf16)v[k];
-    return o;
-  }
+  __device__ static inline op from(const float* v) { return bf16x8_from(v); }
   __device__ static inline void put(felem* p, float w) { MM<NET_X3>::put(p, w); }
   __device__ static inline f32x4_t row_sum(op a, f32x4_t c) {
     op one;
@@ -212,7 +251,10 @@ struct MM<NET_MIX> {
   __device__ static inline op lds_op(const lelem* p, int) { return *reinterpret_cast<const op*>(p); }
   __device__ static inline float lds_get(const lelem* p, int) { return float(*p); }
   __device__ static inline void lds_put(lelem* p, int, float v) { *p = (__bf16)v; }
-  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { *p = o[v]; }
+  __device__ static inline void lds_put2(lelem* p0, lelem* p1, int plane, float v0, float v1) {
+    MM<NET_BF16>::lds_put2(p0, p1, plane, v0, v1);
+  }
+  __device__ static inline void lds_put_elem(lelem* p, int, const op& o, int v) { put_elem(p, o, v); }
 };
 
 // tanh(a) = 1 - 2 / (2^(K a) + 1) with K = 2 / ln 2.  Every weight and bias
@@ -667,10 +709,11 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int f = cfeat(r, q);
-        T::lds_put(Dt + f * LD + col[t], DPL, d[t][r]);
-        d[t][r] = gv[t] * wo[f] * (1.f - d[t][r] * d[t][r]);
+      for (int r = 0; r < NR; r += 2) {
+        const int f0 = cfeat(r, q), f1 = cfeat(r + 1, q);
+        T::lds_put2(Dt + f0 * LD + col[t], Dt + f1 * LD + col[t], DPL, d[t][r], d[t][r + 1]);
+        d[t][r] = gv[t] * wo[f0] * (1.f - d[t][r] * d[t][r]);
+        d[t][r + 1] = gv[t] * wo[f1] * (1.f - d[t][r + 1] * d[t][r + 1]);
       }
     __syncthreads();
 #pragma unroll
@@ -709,7 +752,9 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
           }
         } else {
 #pragma unroll
-          for (int r = 0; r < NR; ++r) T::lds_put(Dt + cfeat(r, q) * LD + col[t], DPL, d[t][r]);
+          for (int r = 0; r < NR; r += 2)
+            T::lds_put2(Dt + cfeat(r, q) * LD + col[t], Dt + cfeat(r + 1, q) * LD + col[t], DPL, d[t][r],
+                        d[t][r + 1]);
         }
       }
       __syncthreads();
