@@ -321,8 +321,28 @@ __global__ __launch_bounds__(256) void k_tridiag_rows(const Real* __restrict__ b
     if (j0 + e < n) {
       const Real le = (e == P - 1) ? lnext : l[e + 1];
       xv = v[e] - le * xv;
-      xl[j0 + e] = xv;
+      v[e] = xv;
     }
+  // the lane's P results leave as 16-byte stores when the loads could be
+  // vectorised (then the whole span lies inside the line's pitch, and the
+  // entries past n are the zeros the padded line holds)
+  constexpr int V = 16 / sizeof(Real);
+  if constexpr (P % V == 0) {
+    if (vec) {
+      typedef Real vec_t __attribute__((ext_vector_type(V)));
+#pragma unroll
+      for (int e = 0; e < P; e += V) {
+        vec_t w;
+#pragma unroll
+        for (int k = 0; k < V; ++k) w[k] = v[e + k];
+        *reinterpret_cast<vec_t*>(xl + j0 + e) = w;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < P; ++e)
+    if (j0 + e < n) xl[j0 + e] = v[e];
 }
 
 template <typename Real>
