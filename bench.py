@@ -415,8 +415,14 @@ def main():
         sweep[str(nb_)] = {"value": r_["value"], "ms_per_round": r_["ms_per_round"]}
     # the gravity variant of the same workload (pressure right-hand side and
     # gas flux with buoyancy; gravity 2, densities 1.2 and 0.4)
-    grav = galerkin = None
+    grav = galerkin = plain128 = None
     if args.variants:
+        # the plain path with the wider network: 2 -> 4x128 -> 1 in float32 on
+        # the matrix cores (one step after one warm-up; each takes ~0.1-0.3 s)
+        log("plain fp32 single scenario, width 128, 2 steps")
+        p128 = inputs.make_problem(args.workload, seed=0, width=128)
+        plain128, _ = run_single(p128, "fp32", 2, 1, args.pretrain, False)
+        plain128["config"] = {"width": 128, "hidden": 4, "precision": "fp32"}
         log(f"bf16x3 single scenario with gravity, {args.steps} steps")
         # gravity scenarios run the split-bf16 network: the mixed form's
         # trajectory drifts past the bf16 bound with gravity
@@ -499,6 +505,7 @@ def main():
                                "iterations per coupled step",
                    "precision": args.precision, "batch": args.batch, "dt": single["dt"]},
         "plain_fp32_single": plain,
+        "plain_fp32_width128": plain128,
         "single": single,
         "batched": batched,
         "batched_kernels": bkern,

@@ -538,6 +538,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
 // two
 template <int W, int MODE, int TPW>
 constexpr int bwd_min_waves() {
+  if (MODE == NET_F32 && W >= 128) return 1;  // float32 weight-gradient tiles: one wave per SIMD
   return ((MODE == NET_BF16 || MODE == NET_MIX) && W <= 64 && TPW == 1) ? 3 : 2;
 }
 
@@ -625,8 +626,13 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
   const float* wo = sp + SM::WO;
   float lacc = 0.f;  // this lane's share of RES . q (lane group 0 only)
 
+  // a wave's dW tiles cover whole 16-row blocks (OWN a multiple of NMB) or
+  // lie inside one; slot o then belongs to row block o / NMB of the wave's
+  // (a compile-time index), and each owned row block has its own db tile
+  static_assert(OWN % NMB == 0 || NMB % OWN == 0, "dW tiles per wave");
+  constexpr int RBW = OWN >= NMB ? OWN / NMB : 1;  // row blocks per wave
   f32x4_t acc[L - 1][OWN];
-  f32x4_t bacc[L - 1];  // db_2..db_L of the wave's output rows (tile column ib = 0 only)
+  f32x4_t bacc[L - 1][RBW];  // db_2..db_L of the wave's row blocks (tile column ib = 0 only)
 #pragma unroll
   for (int a = 0; a < L - 1; ++a) {
 #pragma unroll
@@ -634,7 +640,9 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[a][o][i] = 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bacc[a][i] = 0.f;
+    for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bacc[a][rb][i] = 0.f;
   }
   float s_wout[FPT], s_b[1][FPT], s_w1[DIM][FPT], s_bout = 0.f;
 #pragma unroll
@@ -772,7 +780,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
               const typename T::op av = T::lds_op(arow + ks * T::KS, DPL);
               acc[l - 2][o] = T::mma(av, T::lds_op(brow + ks * T::KS, HPL), acc[l - 2][o]);
               // db_l = delta_l times a ones column, once per output row block
-              if (ib == 0) bacc[l - 2] = T::row_sum(av, bacc[l - 2]);
+              if (ib == 0) bacc[l - 2][o / NMB] = T::row_sum(av, bacc[l - 2][o / NMB]);
             }
           }
         }
@@ -844,7 +852,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
         for (int i = 0; i < 4; ++i) {
           const int orow = ob * 16 + 4 * q + i;
           row[off + int64_t(orow) * W + ib * 16 + n] = acc[l - 2][o][i];
-          if (ib == 0 && n == 0) row[off + int64_t(W) * W + orow] = bacc[l - 2][i];
+          if (ib == 0 && n == 0) row[off + int64_t(W) * W + orow] = bacc[l - 2][o / NMB][i];
         }
       }
     }
@@ -975,7 +983,8 @@ __global__ __launch_bounds__(64 * RW) void k_reduce_adam_pack(
 // ---------------------------------------------------------------------------
 bool mlp_mfma_supported(int dim, int width, int hidden, int mode) {
   if (dim == 3 ? hidden != 4 : (dim != 2 || !(hidden == 3 || hidden == 4))) return false;
-  if (mode == NET_BF16 || mode == NET_MIX) return width == 32 || width == 64 || width == 128;
+  if (mode == NET_BF16 || mode == NET_MIX || mode == NET_F32)
+    return width == 32 || width == 64 || width == 128;
   return width == 32 || width == 64;
 }
 
@@ -1033,13 +1042,15 @@ static void fwd_inst(const Geom& g, const float* th, const void* frag, float* u,
 // instantiated shapes: the forward of the mixed form is the split-bf16 one;
 // the split-bf16 backward keeps two LDS planes and stops at width 64
 #define CRV_FWD_SHAPES(X)                                                                    \
-  X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
+  X(32, 3, NET_F32) X(64, 3, NET_F32) X(128, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)  \
+  X(128, 4, NET_F32)                                                                         \
   X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
   X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
   X(32, 3, NET_X3) X(64, 3, NET_X3) X(128, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)       \
   X(128, 4, NET_X3)
 #define CRV_BWD_SHAPES(X)                                                                    \
-  X(32, 3, NET_F32) X(64, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)                    \
+  X(32, 3, NET_F32) X(64, 3, NET_F32) X(128, 3, NET_F32) X(32, 4, NET_F32) X(64, 4, NET_F32)  \
+  X(128, 4, NET_F32)                                                                         \
   X(32, 3, NET_BF16) X(64, 3, NET_BF16) X(128, 3, NET_BF16) X(32, 4, NET_BF16)                \
   X(64, 4, NET_BF16) X(128, 4, NET_BF16)                                                     \
   X(32, 3, NET_X3) X(64, 3, NET_X3) X(32, 4, NET_X3) X(64, 4, NET_X3)                        \
@@ -1060,7 +1071,9 @@ void launch_mlp_forward_mfma(const Geom& g, int width, int hidden, int mode, con
 // so that its weight-gradient tiles spread over more waves
 // (6 waves for the mixed form at width 64, two blocks per CU, measured 1.6x
 // slower than 4 waves at three blocks per CU)
-constexpr int bwd_nw(int width, int) { return width >= 128 ? 8 : 4; }
+// (float32 at width 128: 4 waves, the LDS of its activations, 139 KB, allows
+// one block per CU)
+constexpr int bwd_nw(int width, int mode) { return (width >= 128 && mode != NET_F32) ? 8 : 4; }
 
 // 16-node tiles per wave: two for the plain-bf16 and mixed backward at width
 // 64 in 2D (two blocks per CU of two waves per SIMD, each wave with two

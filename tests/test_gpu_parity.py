@@ -164,3 +164,28 @@ def test_coupled_trajectory_c1_full(prec, tol):
         for lab, a, b in (("p", p, pr), ("S", s, sr), ("S nodal", sn, snr)):
             worst = max(worst, *check(lab, a, b, tol))
     say(f"  worst {worst:.3e}")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16x3f", 5e-3)])
+def test_coupled_trajectory_width128(prec, tol):
+    """The wider network, 2 -> 4x128 -> 1, on the matrix cores (float32:
+    one wave per SIMD, four waves per block; mixed form: eight) through
+    pretraining and coupled steps on a 40^2-element grid against the oracle."""
+    say("coupled width 128", prec)
+    prob = problem("c1", n_elem=40, width=128, hidden=4)
+    sc = scenario_for(prob, prec)
+    orc = oracle_for(prob, lr=1e-4)
+    n_pre, n_steps = 300, 2
+    l_gpu = sc.pretrain_pressure(n_pre)
+    orc.pretrain(n_pre)
+    assert abs(l_gpu - orc.loss_history[-1]) <= tol * abs(orc.loss_history[-1])
+    dt = cfl_dt(orc)
+    for k in range(n_steps):
+        sc.step(dt)
+        orc.step(dt)
+        p, s, sn = sc.fields()
+        pr, sr, snr = orc.fields()
+        check(f"step {k}, p", p, pr, tol)
+        check(f"step {k}, S", s, sr, tol)
+    check("loss history", sc.loss_history(), np.array(orc.loss_history), tol)
+    sc.close()
