@@ -137,21 +137,56 @@ void launch_gravity_rhs(const Geom& g, const Real* flux, const Real* qi, const R
 // a3: RES_p = sum_dir [alpha_{p-e}(u_p - u_{p-e}) - alpha_p (u_{p+e} - u_p)] - h^2 q_p
 // (eq. 24-25 with Kronecker-delta tests at interior nodes)
 // ---------------------------------------------------------------------------
+// 2D: 64 x 16 tiles of interior nodes.  The block stages u over the tile and
+// its one-node halo, and alpha over the tile and its lower/left neighbours, in
+// LDS with coalesced row loads (each value read from memory once per tile),
+// then each thread forms four outputs of its column from LDS.
+constexpr int RTX = 64, RTY = 16;
 template <typename Real>
 __global__ __launch_bounds__(256) void k_residual2(Geom g, const Real* __restrict__ u,
                                                    const Real* __restrict__ alpha,
                                                    const Real* __restrict__ hq,
                                                    Real* __restrict__ res, int64_t zb) {
   u = zofs(u, zb); alpha = zofs(alpha, zb); hq = zofs(hq, zb); res = zofs(res, zb);
-  const int ii = blockIdx.x * 64 + (threadIdx.x & 63);  // interior column 0..m-1
-  const int jj = blockIdx.y * 4 + (threadIdx.x >> 6);   // interior row
-  if (ii >= g.m || jj >= g.m) return;
+  __shared__ Real su[RTY + 2][RTX + 2];  // node rows j0 .. j0 + RTY + 1, cols i0 .. i0 + RTX + 1
+  __shared__ Real sa[RTY + 1][RTX + 1];  // node rows j0 .. j0 + RTY, cols i0 .. i0 + RTX
   const int n = g.n;
-  const int64_t p = int64_t(jj + 1) * n + (ii + 1);
-  const Real up = u[p], ap = alpha[p];
-  const Real r = alpha[p - 1] * (up - u[p - 1]) - ap * (u[p + 1] - up) +
-                 alpha[p - n] * (up - u[p - n]) - ap * (u[p + n] - up) - hq[p];
-  res[int64_t(jj) * g.mp + ii] = r;
+  const int i0 = blockIdx.x * RTX, j0 = blockIdx.y * RTY;  // first interior column / row (node - 1)
+  const int lx = threadIdx.x & 63, ii = i0 + lx;
+  // every load of the thread is issued before the first wait: h^2 q of its
+  // outputs, then its share of the two tiles
+  Real hv[RTY / 4];
+#pragma unroll
+  for (int k = 0; k < RTY / 4; ++k) {
+    const int jj = j0 + (threadIdx.x >> 6) + 4 * k;
+    hv[k] = (ii < g.m && jj < g.m) ? hq[int64_t(jj + 1) * n + (ii + 1)] : Real(0);
+  }
+  constexpr int NU = (RTY + 2) * (RTX + 2), NA = (RTY + 1) * (RTX + 1);
+#pragma unroll
+  for (int it = 0; it < (NU + 255) / 256; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    const int r = k / (RTX + 2), c = k - r * (RTX + 2);
+    const int nr = j0 + r, nc = i0 + c;
+    if (k < NU) su[r][c] = (nr < n && nc < n) ? u[int64_t(nr) * n + nc] : Real(0);
+  }
+#pragma unroll
+  for (int it = 0; it < (NA + 255) / 256; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    const int r = k / (RTX + 1), c = k - r * (RTX + 1);
+    const int nr = j0 + r, nc = i0 + c;
+    if (k < NA) sa[r][c] = (nr < n && nc < n) ? alpha[int64_t(nr) * n + nc] : Real(0);
+  }
+  __syncthreads();
+  if (ii >= g.m) return;
+#pragma unroll
+  for (int k = 0; k < RTY / 4; ++k) {
+    const int ly = (threadIdx.x >> 6) + 4 * k, jj = j0 + ly;
+    if (jj >= g.m) break;
+    const Real up = su[ly + 1][lx + 1], ap = sa[ly + 1][lx + 1];
+    const Real r = sa[ly + 1][lx] * (up - su[ly + 1][lx]) - ap * (su[ly + 1][lx + 2] - up) +
+                   sa[ly][lx + 1] * (up - su[ly][lx + 1]) - ap * (su[ly + 2][lx + 1] - up) - hv[k];
+    res[int64_t(jj) * g.mp + ii] = r;
+  }
 }
 
 // 3D: RES_p = h sum_dir [...] - h^3 q_p (the alpha terms carry h^(d-2));
@@ -182,7 +217,7 @@ void launch_residual(const Geom& g, const Real* u, const Real* alpha, const Real
     k_residual3<Real><<<grid3, 256, 0, st>>>(g, u, alpha, hq, Real(1.0 / g.ne), res);
     return;
   }
-  dim3 grid(cdiv(g.m, 64), cdiv(g.m, 4), bz.n);
+  dim3 grid(cdiv(g.m, RTX), cdiv(g.m, RTY), bz.n);
   k_residual2<Real><<<grid, 256, 0, st>>>(g, u, alpha, hq, res, bz.zb);
 }
 
