@@ -16,8 +16,13 @@ Two ways to run the steps:
   consecutive slots and advances each run with one crv_step_batch: one
   captured graph in which every kernel of the coupled step runs once for the
   whole run.  The HBM budget counts pools; a pool is freed when it empties.
-  Every kernel reduces in an order that does not depend on the batch, so
-  the results are bitwise those of the scenario alone.
+  A pool has at most `pool_slots` slots and at most as many as keep its
+  batched step's network work (elements x width^2 per scenario) within
+  `batch_cost_cap`: a round of a pool is one step of all its scenarios, so
+  the cap bounds the step latency of the heavy shapes (the default admits
+  two 512^2 width-128 scenarios per pool, and eight of every shape at most
+  a quarter of that).  Every kernel reduces in an order that does not depend
+  on the batch, so the results are bitwise those of the scenario alone.
 * streams: every scenario has its own workspace and stream; each step is one
   replay of its own captured graph, and the steps of different scenarios
   overlap on the device.  Scenarios share no device state and every kernel
@@ -113,7 +118,8 @@ class Pool:
 class Server:
     def __init__(self, hbm_budget_bytes: int, max_active: int = 16, precision: str = "bf16x3f",
                  pretrain_iters: int = 200, steps: int = 20, device: str = "cuda:0",
-                 keep_fields: bool = False, batch: bool = True, pool_slots: int = 8):
+                 keep_fields: bool = False, batch: bool = True, pool_slots: int = 8,
+                 batch_cost_cap: float = 2.0 * 512 ** 2 * 128 ** 2):
         self.budget = int(hbm_budget_bytes)
         self.max_active = max_active
         self.precision = precision
@@ -123,6 +129,15 @@ class Server:
         self.keep_fields = keep_fields
         self.batch = batch
         self.pool_slots = pool_slots
+        self.batch_cost_cap = batch_cost_cap
+
+    def slots_for(self, prob: inputs.Problem) -> int:
+        """Slots of a new pool for this shape: pool_slots, fewer where one
+        scenario's network work (elements x width^2, in proportion to its
+        nodes x width^2) would make a full round exceed batch_cost_cap (at
+        least one)."""
+        cost = float(prob.n_elem ** prob.dim) * prob.width ** 2
+        return max(1, min(self.pool_slots, int(self.batch_cost_cap // cost)))
 
     def precision_for(self, width: int) -> str:
         """The requested form where it exists (split bf16 stops at width 64;
@@ -180,7 +195,7 @@ class Server:
                     if pool is None:
                         # a new pool: as many slots as the budget allows, at most pool_slots
                         stride = (ws + 255) // 256 * 256
-                        n_slots = min(self.pool_slots, (self.budget - 256) // stride)
+                        n_slots = min(self.slots_for(prob), (self.budget - 256) // stride)
                         need = stride * n_slots + 256
                 if (self.batch and pool is None and n_slots < 1) or ws > self.budget:
                     # can never fit: refuse it rather than wait for memory
