@@ -421,8 +421,9 @@ def main():
         # the matrix cores (one step after one warm-up; each takes ~0.1-0.3 s)
         log("plain fp32 single scenario, width 128, 2 steps")
         p128 = inputs.make_problem(args.workload, seed=0, width=128)
-        plain128, _ = run_single(p128, "fp32", 2, 1, args.pretrain, False)
+        plain128, k128 = run_single(p128, "fp32", 2, 1, args.pretrain, True)
         plain128["config"] = {"width": 128, "hidden": 4, "precision": "fp32"}
+        plain128["kernels_us_per_launch"] = {k: v["us_per_launch"] for k, v in k128.items()}
         log(f"bf16x3 single scenario with gravity, {args.steps} steps")
         # gravity scenarios run the split-bf16 network: the mixed form's
         # trajectory drifts past the bf16 bound with gravity
