@@ -67,9 +67,11 @@ def algorithmic_work(name, prob, n_launch_units):
 
 NET_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x3f": 3}
 
-# tanh = 1 - 2 / (2^(Ka) + 1): one exp2 and one reciprocal, both quarter-rate
-# transcendental instructions: 256 CUs x 4 SIMDs x 16 lanes / 4 x 2.4 GHz
-TRANS_PEAK_PER_S = 256 * 4 * 16 / 4 * 2.4e9
+# tanh = 1 - 2 / (2^(Ka) + 1): one exp2 and one reciprocal, both transcendental
+# instructions, which a SIMD retires for 8 lanes per clock: 256 CUs x 4 SIMDs x
+# 8 lanes x 2.4 GHz = 19.7 T/s (a throughput probe of independent exp2 and
+# reciprocal chains on the MI355X reached 17.2 and 16.7 T/s)
+TRANS_PEAK_PER_S = 256 * 4 * 8 * 2.4e9
 
 
 def transcendental_floor(name, prob, us_per_launch, scenarios=1):
@@ -89,12 +91,12 @@ def transcendental_floor(name, prob, us_per_launch, scenarios=1):
 
 def kernel_symbol(name, prob, precision):
     """Device symbol of the launch the event timer calls `name` (matrix-core
-    network kernels only; 4 waves per backward block up to width 64, two
-    16-node tiles per wave for the plain-bf16 and mixed backward at width 64
-    in 2D)."""
+    network kernels only; 4 waves per backward block up to width 64 and for
+    float32 at 128, 8 for the bf16 forms at 128, two 16-node tiles per wave
+    for the plain-bf16 and mixed backward at width 64 in 2D)."""
     if name == "mlp_bwd" and precision in NET_MODE:
         mode = NET_MODE[precision]
-        nw = 8 if prob.width >= 128 else 4
+        nw = 8 if (prob.width >= 128 and mode != 0) else 4   # float32 at width 128: 4
         tpw = 2 if (prob.width == 64 and prob.dim == 2 and mode in (1, 3)) else 1
         return f"crv::k_mlp_bwd_mfma<{prob.width}, {prob.hidden}, {mode}, {prob.dim}, {nw}, {tpw}>"
     if name == "mlp_fwd" and precision in NET_MODE:
