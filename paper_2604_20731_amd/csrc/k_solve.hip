@@ -646,45 +646,63 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
 // consecutive floats, so every A load of a wave is one contiguous 2 KB read.
 // One 32x32 output tile per block; its NW waves split K into NW contiguous
 // ranges and the partial tiles are summed in a fixed order through LDS.
-template <int EPI>
-__global__ __launch_bounds__(512) void k_gemm_pa_f32(int M, int N, int K,
-                                                     const float* __restrict__ Af,
-                                                     const float* __restrict__ B, int ldb,
-                                                     int64_t sb, float* __restrict__ C, int ldc,
-                                                     int64_t sc, const float* __restrict__ sym,
-                                                     const double* __restrict__ skip) {
+template <int EPI, int NW, int RPW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_pa_f32(int M, int N, int K,
+                                                         const float* __restrict__ Af,
+                                                         const float* __restrict__ B, int ldb,
+                                                         int64_t sb, float* __restrict__ C, int ldc,
+                                                         int64_t sc, const float* __restrict__ sym,
+                                                         const double* __restrict__ skip) {
   if (skip && skip[0] <= skip[3]) return;
   B += int64_t(blockIdx.z) * sb;
   C += int64_t(blockIdx.z) * sc;
-  __shared__ float part[8][32 * 33];
-  const int nw = blockDim.x >> 6;
+  // K ranges: wave w sums ranges RPW w .. RPW w + RPW - 1 (RPW = 1 or 2).  The
+  // range sums combine as: adjacent pairs first (0+1, 2+3, ...), then the
+  // pair sums in order (an odd range count: all ranges in order), the same
+  // sum whether a pair is added in a wave's registers or from LDS
+  constexpr int R = NW * RPW;
+  __shared__ float part[NW][32 * 33];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, g = lane >> 5;
   const int mb = blockIdx.y, n0 = blockIdx.x * 32;
-  const int kq = K / nw;  // multiple of 16
-  const float* a = Af + ((int64_t(mb) * (K / 16) + (w * kq) / 16) * 64 + lane) * 8;
-  const float* b = B + int64_t(w * kq + g) * ldb + n0 + r;
-  gemm_f32x16_t acc;
+  const int kq = K / R;  // multiple of 16
+  gemm_f32x16_t tot;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int kc = 0; kc < kq / 16; ++kc) {
-    const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(a + kc * 512);
-    const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(a + kc * 512 + 4);
-    float bv[8];
+  for (int j = 0; j < RPW; ++j) {
+    const int q = w * RPW + j;
+    const float* a = Af + ((int64_t(mb) * (K / 16) + (q * kq) / 16) * 64 + lane) * 8;
+    const float* b = B + int64_t(q * kq + g) * ldb + n0 + r;
+    gemm_f32x16_t acc;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) bv[u] = b[int64_t(kc * 16 + 2 * u) * ldb];
-    const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    for (int kc = 0; kc < kq / 16; ++kc) {
+      const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(a + kc * 512);
+      const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(a + kc * 512 + 4);
+      float bv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+      for (int u = 0; u < 8; ++u) bv[u] = b[int64_t(kc * 16 + 2 * u) * ldb];
+      const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+    }
+    if (j == 0) tot = acc;
+    else tot += acc;  // the pair sum of ranges 2w, 2w + 1
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) part[w][(8 * (i >> 2) + 4 * g + (i & 3)) * 33 + r] = acc[i];
+  for (int i = 0; i < 16; ++i) part[w][(8 * (i >> 2) + 4 * g + (i & 3)) * 33 + r] = tot[i];
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+  for (int e = threadIdx.x; e < 32 * 32; e += 64 * NW) {
     // the transposed store walks the tile by columns, so both stores are
     // contiguous along the lanes
     const int row = EPI == 1 ? (e & 31) : (e >> 5), col = EPI == 1 ? (e >> 5) : (e & 31);
-    float v = part[0][row * 33 + col];
-    for (int k = 1; k < nw; ++k) v += part[k][row * 33 + col];
+    const int at = row * 33 + col;
+    float v;
+    if constexpr (RPW == 1 && R % 2 == 0) {
+      v = part[0][at] + part[1][at];
+      for (int k = 1; k < R / 2; ++k) v += part[2 * k][at] + part[2 * k + 1][at];
+    } else {
+      v = part[0][at];
+      for (int k = 1; k < NW; ++k) v += part[k][at];
+    }
     const int gi = mb * 32 + row, gj = n0 + col;
     if constexpr (EPI == 1) {
       C[int64_t(gj) * ldc + gi] = v;
@@ -703,18 +721,42 @@ static void gemm_dispatch(int M, int N, int K, const Real* A, int lda, const Rea
   if (batch <= 0) return;
   if constexpr (sizeof(Real) == 4) {
     if (EPI != 0 || a_packed) {  // epilogues: callers always pass the packed operand
-      // K split over nw waves (the largest divisor of K/64 up to 8), so that
-      // every wave's range is a multiple of 16
+      // K split into nr ranges (the largest divisor of K/64 up to 8), so that
+      // every range is a multiple of 16.  One wave per range, or two ranges
+      // per wave once the grid has 512 or more tiles (as in batched launches:
+      // blocks of half the waves and half the LDS run beside the other
+      // streams' kernels better); the sums are the same either way
       const int units = K / 64;
-      int nw = 1;
+      int nr = 1;
       for (int d = 8; d >= 1; --d)
         if (units % d == 0) {
-          nw = d;
+          nr = d;
           break;
         }
+      const bool pairs = nr % 2 == 0 && int64_t(N / 32) * (M / 32) * batch >= 512;
       dim3 grid(N / 32, M / 32, batch);
-      k_gemm_pa_f32<EPI><<<grid, 64 * nw, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc, sym,
-                                                   skip);
+#define CRV_PA(NWV, RPWV) \
+  k_gemm_pa_f32<EPI, NWV, RPWV><<<grid, 64 * NWV, 0, st>>>(M, N, K, a_packed, B, ldb, sb, C, ldc, sc, sym, skip)
+      if (pairs) {
+        switch (nr / 2) {
+          case 1: CRV_PA(1, 2); break;
+          case 2: CRV_PA(2, 2); break;
+          case 3: CRV_PA(3, 2); break;
+          default: CRV_PA(4, 2); break;
+        }
+      } else {
+        switch (nr) {
+          case 1: CRV_PA(1, 1); break;
+          case 2: CRV_PA(2, 1); break;
+          case 3: CRV_PA(3, 1); break;
+          case 4: CRV_PA(4, 1); break;
+          case 5: CRV_PA(5, 1); break;
+          case 6: CRV_PA(6, 1); break;
+          case 7: CRV_PA(7, 1); break;
+          default: CRV_PA(8, 1); break;
+        }
+      }
+#undef CRV_PA
       return;
     }
     // dims are multiples of 64, so K/4 is a multiple of 16
