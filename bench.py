@@ -279,7 +279,7 @@ def run_galerkin(prob, precision, steps, dt, rtol=1e-6):
 
 
 def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="shared",
-                profile=False, groups=4):
+                profile=False, groups=4, part=1):
     """Aggregate coupled steps/s of several 512^2 scenarios stepped together by
     crv_step_batch.  mode "bucket": the scenarios' workspaces lie at one
     stride in one allocation and every kernel of the step runs once for all of
@@ -287,7 +287,8 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="sha
     "shared": the same with the network backward sharing the device's blocks
     among the scenarios (crv_step_batch_shared); "split": `groups` shared
     buckets, each on its own stream, so that one bucket's forward and small
-    kernels overlap another's backward on the device; "streams": each
+    kernels overlap another's backward on the device, each bucket's backward
+    on 1/part of the device's blocks (crv_step_batch_shared_part); "streams": each
     scenario on its own stream, their captured steps overlapping on the
     device.  With profile, one more batched step runs event-timed (one-bucket
     modes)."""
@@ -320,7 +321,7 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="sha
         if mode == "split":
             k = 0
             for b in buckets:   # every bucket's step is enqueued on its own stream
-                b.step(dts[k:k + len(b.scenarios)], True)
+                b.step(dts[k:k + len(b.scenarios)], True, part)
                 k += len(b.scenarios)
         else:
             crv.step_batch(ctxs, dts, shared)
@@ -356,6 +357,7 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="sha
            "ms_per_round": 1e3 * elapsed / steps}
     if mode == "split":
         out["buckets"] = sizes
+        out["backward_part"] = part
     return (out, kernels) if profile else out
 
 
@@ -369,6 +371,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="concurrent 512^2 scenarios")
     ap.add_argument("--groups", type=int, default=4,
                     help="batched buckets (one stream each) the headline batch is split into")
+    ap.add_argument("--bwd-part", type=int, default=2,
+                    help="each split bucket's backward takes 1/part of the device's blocks")
     ap.add_argument("--batch-sweep", default="32,64",
                     help="further batch sizes timed for the aggregate rate ('' to skip)")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
@@ -420,11 +424,11 @@ def main():
     log(f"{args.precision} batched: first run of {args.batch} scenarios as {args.groups} buckets "
         "on as many streams (untimed for the headline), 2 steps")
     first = run_batched(list(range(args.batch)), args.precision, 2, 1, 2, mode="split",
-                        groups=args.groups)
+                        groups=args.groups, part=args.bwd_part)
     log(f"{args.precision} batched: {args.batch} scenarios as {args.groups} shared buckets on "
         f"{args.groups} streams, {args.steps} steps")
     batched = run_batched(list(range(args.batch)), args.precision, args.steps, args.warmup,
-                          args.pretrain, mode="split", groups=args.groups)
+                          args.pretrain, mode="split", groups=args.groups, part=args.bwd_part)
     batched["first_run_of_process"] = first["value"]
     log(f"{args.precision} batched, one launch per kernel, backward blocks shared: {args.batch} "
         f"scenarios in one bucket x {args.steps} steps")
@@ -444,13 +448,14 @@ def main():
         alt_single, _ = run_single(prob, args.alt_precision, args.steps, args.warmup, args.pretrain,
                                    False)
         alt_batched = run_batched(list(range(args.batch)), args.alt_precision, args.steps,
-                                  args.warmup, args.pretrain, mode="split", groups=args.groups)
+                                  args.warmup, args.pretrain, mode="split", groups=args.groups,
+                                  part=args.bwd_part)
         alt = {"precision": args.alt_precision, "single": alt_single, "batched": alt_batched}
     sweep = {}
     for nb_ in [int(x) for x in args.batch_sweep.split(",") if x.strip()]:
         log(f"{args.precision} batched: {nb_} scenarios x 3 steps")
         r_ = run_batched(list(range(nb_)), args.precision, 3, 1, args.pretrain, mode="split",
-                         groups=args.groups)
+                         groups=args.groups, part=args.bwd_part)
         sweep[str(nb_)] = {"value": r_["value"], "ms_per_round": r_["ms_per_round"]}
     # the gravity variant of the same workload (pressure right-hand side and
     # gas flux with buoyancy; gravity 2, densities 1.2 and 0.4)

@@ -201,9 +201,15 @@ crv_status crv_step(crv_ctx* ctx, double dt);
  * scenario's gradient is the same sum grouped into fewer partial rows), which
  * is faster for large grids; results then match crv_step to rounding, which
  * Adam's normalised steps carry on (within each precision form's parity
- * bound), not bitwise. */
+ * bound), not bitwise.
+ * crv_step_batch_shared_part: crv_step_batch_shared whose batched backward
+ * takes 1/part of the device's resident blocks (part in [1, 16], else
+ * CRV_EINVAL; part = 1 is crv_step_batch_shared), for batches stepped on
+ * several streams at once: each leaves room for the others' kernels.  The
+ * grouping of the gradient sums depends on part (same bound as above). */
 crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n);
 crv_status crv_step_batch_shared(crv_ctx* const* ctxs, const double* dts, int n);
+crv_status crv_step_batch_shared_part(crv_ctx* const* ctxs, const double* dts, int n, int part);
 
 /* Outputs (any may be NULL): p_nodal (N+1)^d network pressure m*NN,
  * s_coefs nb^d, s_nodal (N+1)^d saturation at the nodes. Synchronises. */

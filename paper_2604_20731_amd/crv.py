@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "CRV_OK", -1: "CRV_EINVAL", -2: "CRV_ENOMEM", -3: "CRV_EHIP",
 EXPORTED = [
     "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
     "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_step_batch",
-    "crv_step_batch_shared",
+    "crv_step_batch_shared", "crv_step_batch_shared_part",
     "crv_get_fields", "crv_loss_grad",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
     "crv_set_observations", "crv_invert", "crv_get_log_perm",
@@ -76,6 +76,7 @@ def _load() -> C.CDLL:
         "crv_step": [vp, C.c_double],
         "crv_step_batch": [C.POINTER(vp), dp, C.c_int],
         "crv_step_batch_shared": [C.POINTER(vp), dp, C.c_int],
+        "crv_step_batch_shared_part": [C.POINTER(vp), dp, C.c_int, C.c_int],
         "crv_train_async": [vp, C.c_int],
         "crv_sync": [vp],
         "crv_get_fields": [vp, dp, dp, dp],
@@ -367,19 +368,24 @@ def gram_solve_noalloc(n_elem: int, res, q, loss=None, stream=None):
                                       C.c_void_p(st.cuda_stream)))
 
 
-def step_batch(scenarios, dts, shared: bool = False):
+def step_batch(scenarios, dts, shared: bool = False, part: int = 1):
     """crv_step_batch: one coupled step for each scenario, bitwise the results
     of one crv_step each.  Scenarios of one configuration whose workspaces lie
     at one stride (a Bucket, or a run of consecutive scenarios of one) step
     with one launch per kernel; others each on their own stream, with no
     host wait between them.  shared: crv_step_batch_shared (the batched
     backward shares the device's blocks among the scenarios: faster, equal to
-    rounding)."""
+    rounding); part > 1: crv_step_batch_shared_part (the batch's backward
+    takes 1/part of the device's blocks, for batches stepped on several
+    streams at once)."""
     n = len(scenarios)
     if len(dts) != n:
         raise ValueError("one dt per scenario")
     ctxs = (C.c_void_p * n)(*[sc.ctx for sc in scenarios])
     d = _f64(dts)
+    if shared and part != 1:
+        _check(LIB.crv_step_batch_shared_part(ctxs, _dp(d), n, int(part)))
+        return
     fn = LIB.crv_step_batch_shared if shared else LIB.crv_step_batch
     _check(fn(ctxs, _dp(d), n))
 
@@ -404,8 +410,8 @@ class Bucket:
                                                     lead + (k + 1) * self.stride])
             for k, p in enumerate(problems)]
 
-    def step(self, dts, shared: bool = False):
-        step_batch(self.scenarios, dts, shared)
+    def step(self, dts, shared: bool = False, part: int = 1):
+        step_batch(self.scenarios, dts, shared, part)
 
     def close(self):
         for sc in self.scenarios:

@@ -129,6 +129,9 @@ int main() {
   expect("step_batch NULL context", crv_step_batch(none, dts, 2), CRV_EINVAL);
   expect("step_batch empty", crv_step_batch(nullptr, nullptr, 0), CRV_OK);
   expect("step_batch_shared NULL context", crv_step_batch_shared(none, dts, 2), CRV_EINVAL);
+  expect("step_batch_shared_part NULL context", crv_step_batch_shared_part(none, dts, 2, 2), CRV_EINVAL);
+  expect("step_batch_shared_part part 0", crv_step_batch_shared_part(none, dts, 2, 0), CRV_EINVAL);
+  expect("step_batch_shared_part part 17", crv_step_batch_shared_part(none, dts, 2, 17), CRV_EINVAL);
 
   // the allocation-free Gram solve: sizes beyond its array, missing arrays
   float f = 0.f;

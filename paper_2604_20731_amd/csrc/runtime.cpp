@@ -297,9 +297,11 @@ struct SolverBase {
   // scenario batching (2D float32 matrix-core contexts of one configuration)
   virtual bool batchable() const { return false; }
   virtual int64_t batch_tag() const { return 0; }
+  // part: 0 = every scenario keeps its own backward grid (bitwise single
+  // steps); p >= 1 = the batch's backward shares 1/p of the device's blocks
   virtual crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb,
-                                  bool share) {
-    (void)all, (void)dts, (void)n, (void)zb, (void)share;
+                                  int part) {
+    (void)all, (void)dts, (void)n, (void)zb, (void)part;
     return fail(CRV_EINVAL, "this context cannot run a batched step");
   }
 };
@@ -577,12 +579,16 @@ struct Solver : SolverBase {
   // The matrix-core backward also leaves one loss partial per block.  A
   // batch keeps each scenario's own grid (bitwise a single step), unless it
   // shares the blocks that fit on the device at once among its n scenarios
-  // (about bwd_blocks / n each): then all of them run in one round and each
-  // writes n times fewer partial rows, its gradient sums rounding differently
-  // from a single step's (the same sums, grouped otherwise).
-  bool share_bwd = false;
+  // (about bwd_blocks / n each; / (n p) when the batch is to take 1/p of the
+  // device, leaving room for other streams' batches): then all of them run
+  // in one round and each writes that many times fewer partial rows, its
+  // gradient sums rounding differently from a single step's (the same sums,
+  // grouped otherwise).
+  int share_part = 0;  // 0: own grid per scenario; p: the batch shares 1/p of the device's blocks
   int bwd_grid() const {
-    return (bz.n > 1 && share_bwd) ? std::max(1, (bwd_blocks + bz.n - 1) / bz.n) : bwd_blocks;
+    if (bz.n <= 1 || share_part <= 0) return bwd_blocks;
+    const int per = bz.n * share_part;
+    return std::max(1, (bwd_blocks + per - 1) / per);
   }
   int adj_np = 0;
   int64_t ldp() const { return partial_pitch(P); }  // pitch of the matrix-core partial rows
@@ -897,7 +903,7 @@ struct Solver : SolverBase {
   struct BatchGraph {
     int n;
     int64_t zb;
-    bool share;
+    int part;
     hipGraphExec_t exec;
   };
   std::vector<BatchGraph> g_batch;
@@ -918,7 +924,7 @@ struct Solver : SolverBase {
   }
 
   crv_status step_batched(SolverBase* const* all, const double* dts, int n, int64_t zb,
-                          bool share) override {
+                          int part) override {
     // order after the work already queued on the other scenarios' streams
     size_t ev = 0;
     for (int k = 1; k < n; ++k) {
@@ -937,23 +943,23 @@ struct Solver : SolverBase {
     if (use_graphs()) {
       hipGraphExec_t exec = nullptr;
       for (const BatchGraph& bg : g_batch)
-        if (bg.n == n && bg.zb == zb && bg.share == share) exec = bg.exec;
+        if (bg.n == n && bg.zb == zb && bg.part == part) exec = bg.exec;
       if (!exec) {
         bz = Batch{n, zb};
-        share_bwd = share;
+        share_part = part;
         s = capture(&exec, [&] { step_body(); });
         bz = one;
-        share_bwd = false;
+        share_part = 0;
         if (s) return s;
-        g_batch.push_back(BatchGraph{n, zb, share, exec});
+        g_batch.push_back(BatchGraph{n, zb, part, exec});
       }
       CRV_HIP(hipGraphLaunch(exec, st));
     } else {
       bz = Batch{n, zb};
-      share_bwd = share;
+      share_part = part;
       step_body();
       bz = one;
-      share_bwd = false;
+      share_part = 0;
     }
     if ((s = check_launch())) return s;
     // and the other streams' later work after the batch
@@ -1341,7 +1347,7 @@ crv_status crv_step(crv_ctx* c, double dt) {
   return sv.step(dt);
 }
 
-static crv_status step_batch(crv_ctx* const* ctxs, const double* dts, int n, bool share) {
+static crv_status step_batch(crv_ctx* const* ctxs, const double* dts, int n, int part) {
   if (n < 0 || (n > 0 && (!ctxs || !dts))) return fail(CRV_EINVAL, "bad batch arrays");
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !ctxs[i]->impl) return fail(CRV_EINVAL, "context is NULL");
@@ -1366,7 +1372,7 @@ static crv_status step_batch(crv_ctx* const* ctxs, const double* dts, int n, boo
     if (ok) {
       std::vector<SolverBase*> all(static_cast<size_t>(n));
       for (int i = 0; i < n; ++i) all[size_t(i)] = ctxs[i]->impl.get();
-      return s0.step_batched(all.data(), dts, n, zb, share);
+      return s0.step_batched(all.data(), dts, n, zb, part);
     }
   }
   for (int i = 0; i < n; ++i) {
@@ -1377,11 +1383,16 @@ static crv_status step_batch(crv_ctx* const* ctxs, const double* dts, int n, boo
 }
 
 crv_status crv_step_batch(crv_ctx* const* ctxs, const double* dts, int n) {
-  return step_batch(ctxs, dts, n, false);
+  return step_batch(ctxs, dts, n, 0);
 }
 
 crv_status crv_step_batch_shared(crv_ctx* const* ctxs, const double* dts, int n) {
-  return step_batch(ctxs, dts, n, true);
+  return step_batch(ctxs, dts, n, 1);
+}
+
+crv_status crv_step_batch_shared_part(crv_ctx* const* ctxs, const double* dts, int n, int part) {
+  if (part < 1 || part > 16) return fail(CRV_EINVAL, "part must be in [1, 16]");
+  return step_batch(ctxs, dts, n, part);
 }
 
 crv_status crv_get_fields(crv_ctx* c, double* p_nodal, double* s_coefs, double* s_nodal) {

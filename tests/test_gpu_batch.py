@@ -66,7 +66,7 @@ CASES = [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2), ("bf16x3f", 128, 128, 2), 
          ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3), ("fp32", 64, 128, 2)]
 
 
-def _run(prec, ne, width, n, shared):
+def _run(prec, ne, width, n, shared, part=1):
     from paper_2604_20731_amd import crv
     probs = _problems(n, ne, width)
     cfg = crv.config(dim=2, n_elem=ne, degree=2, width=width, hidden=4, precision=prec)
@@ -76,7 +76,7 @@ def _run(prec, ne, width, n, shared):
         sc.pretrain_pressure(20)
     dts = [_dt(sc, p) for sc, p in zip(singles, probs)]
     for _ in range(2):
-        bucket.step(dts, shared)
+        bucket.step(dts, shared, part)
         for sc, dt in zip(singles, dts):
             sc.step(dt)
     return crv, bucket, singles, dts
@@ -111,6 +111,23 @@ def test_shared_bucket_step_matches_single_steps(prec, ne, width, n):
     for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
         say(f"  scenario {k}")
         _close(a, b, tol, with_p)
+    bucket.close()
+    for sc in singles:
+        sc.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,ne,width,n,part", [("bf16x3f", 512, 64, 2, 2), ("fp32", 64, 64, 3, 4)])
+def test_shared_part_bucket_step_matches_single_steps(prec, ne, width, n, part):
+    """crv_step_batch_shared_part: the batch's backward on 1/part of the
+    device's blocks (the grouping of the gradient sums changes again), within
+    the same bounds as the shared form."""
+    say("shared part bucket", prec, ne, width, n, part)
+    crv, bucket, singles, dts = _run(prec, ne, width, n, True, part)
+    tol = {"fp32": 1e-3, "bf16x3f": 5e-3}[prec]
+    for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
+        say(f"  scenario {k}")
+        _close(a, b, tol, True)
     bucket.close()
     for sc in singles:
         sc.close()
