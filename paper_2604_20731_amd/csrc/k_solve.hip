@@ -644,8 +644,9 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_f32(int M, int N, int K,
 // constant operand, packed once): chunk kc of row block mb holds, for lane
 // (r = lane%32, g = lane/32), A[32 mb + r][16 kc + 2u + g], u = 0..7, as 8
 // consecutive floats, so every A load of a wave is one contiguous 2 KB read.
-// One 32x32 output tile per block; its NW waves split K into NW contiguous
-// ranges and the partial tiles are summed in a fixed order through LDS.
+// One 32x32 output tile per block; K is split into NW * RPW contiguous
+// ranges, RPW per wave, and the range sums are combined in a fixed order
+// (through registers within a wave, through LDS across waves).
 template <int EPI, int NW, int RPW>
 __global__ __launch_bounds__(64 * NW) void k_gemm_pa_f32(int M, int N, int K,
                                                          const float* __restrict__ Af,
