@@ -299,13 +299,13 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="sha
     cfg = crv.config(dim=2, n_elem=p0.n_elem, degree=p0.degree, width=p0.width,
                      hidden=p0.hidden, precision=precision)
     buckets = []
+    group = None
     shared = mode in ("shared", "split")
     if mode in ("bucket", "shared"):
         buckets = [crv.Bucket(cfg, probs)]
     elif mode == "split":
-        per = (len(probs) + groups - 1) // groups
-        buckets = [crv.Bucket(cfg, probs[k:k + per], stream=torch.cuda.Stream())
-                   for k in range(0, len(probs), per)]
+        group = crv.BucketGroup(cfg, probs, groups=groups)
+        buckets = group.buckets
     if buckets:
         ctxs = [sc for b in buckets for sc in b.scenarios]
     else:
@@ -318,11 +318,8 @@ def run_batched(seeds, precision, steps, warmup, pretrain, n_elem=512, mode="sha
         dts.append(cfl_dt_from_pressure(p, np.exp(pr.log_perm), pr.porosity, pr.n_elem))
 
     def round_():
-        if mode == "split":
-            k = 0
-            for b in buckets:   # every bucket's step is enqueued on its own stream
-                b.step(dts[k:k + len(b.scenarios)], True, part)
-                k += len(b.scenarios)
+        if group is not None:
+            group.step(dts, True, part)   # every bucket's step enqueued on its own stream
         else:
             crv.step_batch(ctxs, dts, shared)
 

@@ -420,6 +420,40 @@ class Bucket:
         self._mem = None
 
 
+class BucketGroup:
+    """Scenarios of one configuration split into `groups` Buckets, each on its
+    own stream, stepped together: every bucket's batched step is enqueued on
+    its stream with no host wait, so one bucket's forward and small kernels
+    run beside another's backward.  With shared=True each bucket's backward
+    takes 1/part of the device's blocks (crv_step_batch_shared_part), leaving
+    room for the others; part = 1 gives each the whole device."""
+
+    def __init__(self, cfg: CrvConfig, problems, groups: int = 4, device: str = "cuda:0"):
+        import torch  # device memory and streams only
+        problems = list(problems)
+        if groups < 1:
+            raise ValueError("groups must be >= 1")
+        per = (len(problems) + groups - 1) // groups
+        self.buckets = [Bucket(cfg, problems[k:k + per], device=device,
+                               stream=torch.cuda.Stream(device=device))
+                        for k in range(0, len(problems), per)]
+        self.scenarios = [sc for b in self.buckets for sc in b.scenarios]
+
+    def step(self, dts, shared: bool = True, part: int = 2):
+        if len(dts) != len(self.scenarios):
+            raise ValueError("one dt per scenario")
+        k = 0
+        for b in self.buckets:
+            n = len(b.scenarios)
+            b.step(list(dts[k:k + n]), shared, part)
+            k += n
+
+    def close(self):
+        for b in self.buckets:
+            b.close()
+        self.buckets, self.scenarios = [], []
+
+
 def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:
     """Build a Scenario from an inputs.Problem."""
     cfg = config(dim=prob.dim, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
