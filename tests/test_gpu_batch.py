@@ -171,3 +171,32 @@ def test_unordered_or_mixed_batches_fall_back_to_streams():
     singles[0].step(dts[0])
     for a, b in zip(bucket.scenarios, singles):
         assert _same(a, b)
+
+
+@pytest.mark.timeout(600)
+def test_bucket_group_concurrent_equals_sequential():
+    """crv.BucketGroup steps its buckets on their own streams at once (the
+    bench's headline form); the result must not depend on that concurrency:
+    bitwise the same buckets stepped one after another with a device
+    synchronisation in between."""
+    import torch
+    from paper_2604_20731_amd import crv
+    probs = _problems(4, 64, 64)
+    cfg = crv.config(dim=2, n_elem=64, degree=2, width=64, hidden=4, precision="bf16x3f")
+    conc = crv.BucketGroup(cfg, probs, groups=2)
+    seq = crv.BucketGroup(cfg, probs, groups=2)
+    for sc in conc.scenarios + seq.scenarios:
+        sc.pretrain_pressure(20)
+    dts = [_dt(sc, p) for sc, p in zip(seq.scenarios, probs)]
+    for _ in range(2):
+        conc.step(dts, True, 2)
+        k = 0
+        for b in seq.buckets:
+            b.step(dts[k:k + len(b.scenarios)], True, 2)
+            k += len(b.scenarios)
+            torch.cuda.synchronize()
+    for a, b in zip(conc.scenarios, seq.scenarios):
+        assert _same(a, b)
+    say("  concurrent bucket group bitwise equal to sequential buckets")
+    conc.close()
+    seq.close()
