@@ -237,6 +237,23 @@ crv_status crv_set_saturation(crv_ctx* ctx, const double* s_coefs);
  * to evaluate the loss at a new log K. */
 crv_status crv_set_log_perm(crv_ctx* ctx, const double* log_perm);
 
+/* Differentiation form on device arrays (float32 contexts; a float64
+ * context gives CRV_EINVAL).  Every pointer is device memory of the
+ * context's GPU, owned by the caller; a host pointer is CRV_EINVAL.
+ * crv_set_params_device: theta (n_params float32, nullable) replaces the
+ *   network parameters as crv_set_state(theta, NULL, NULL, -1) does;
+ *   log_perm ((N+1)^d float32, nullable) replaces the nodal log K as
+ *   crv_set_log_perm does (K = exp(log K) in float64, rounded once).  A
+ *   non-finite log K is CRV_EINVAL and changes nothing: the check waits for
+ *   the context's stream once.  The copies read the arrays in stream order.
+ * crv_loss_grad_device: crv_loss_grad's loss (one float64, eq. 21-28),
+ *   dtheta (n_params float32) and dlogperm ((N+1)^d float32), each nullable,
+ *   written in stream order on the context's stream without waiting for
+ *   it: a caller on another stream orders itself after the context's
+ *   stream before reading them.  Does not change the training state. */
+crv_status crv_set_params_device(crv_ctx* ctx, const float* theta, const float* log_perm);
+crv_status crv_loss_grad_device(crv_ctx* ctx, double* loss, float* dtheta, float* dlogperm);
+
 /* Inverse problem (the paper's conclusions name recovering reservoir
  * parameters as future work), read as a joint Adam on the network parameters
  * and the nodal log K.

@@ -26,7 +26,7 @@ EXPORTED = [
     "crv_config_default", "crv_param_count", "crv_workspace_size", "crv_init",
     "crv_pretrain_pressure", "crv_train_async", "crv_sync", "crv_step", "crv_step_batch",
     "crv_step_batch_shared", "crv_step_batch_shared_part",
-    "crv_get_fields", "crv_loss_grad",
+    "crv_get_fields", "crv_loss_grad", "crv_loss_grad_device", "crv_set_params_device",
     "crv_get_state", "crv_set_state", "crv_set_saturation", "crv_set_log_perm", "crv_loss_history",
     "crv_set_observations", "crv_invert", "crv_get_log_perm",
     "crv_gram_solve", "crv_gram_solve_noalloc", "crv_mass_solve", "crv_project_pressure",
@@ -81,6 +81,8 @@ def _load() -> C.CDLL:
         "crv_sync": [vp],
         "crv_get_fields": [vp, dp, dp, dp],
         "crv_loss_grad": [vp, dp, dp, dp],
+        "crv_loss_grad_device": [vp, vp, vp, vp],
+        "crv_set_params_device": [vp, vp, vp],
         "crv_get_state": [vp, dp, dp, dp, C.POINTER(C.c_int64)],
         "crv_set_state": [vp, dp, dp, dp, C.c_int64],
         "crv_set_saturation": [vp, dp],
@@ -237,6 +239,51 @@ class Scenario:
         gl = np.empty((self.ne + 1,) * self.dim) if with_logperm else None
         _check(LIB.crv_loss_grad(self.ctx, C.byref(loss), _dp(g), _dp(gl)))
         return (loss.value, g, gl) if with_logperm else (loss.value, g)
+
+    @staticmethod
+    def _device_f32(t, n: int, name: str):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+        return C.c_void_p(t.data_ptr())
+
+    def set_params_device(self, theta=None, log_perm=None):
+        """crv_set_params_device: theta and/or the nodal log K from float32
+        CUDA tensors, read in order on this scenario's stream after the
+        work already queued on the current stream."""
+        import torch
+        cur = torch.cuda.current_stream(self._ws.device)
+        self._stream.wait_stream(cur)
+        th = None if theta is None else self._device_f32(theta, self.P, "theta")
+        lk = None if log_perm is None else self._device_f32(log_perm, self.nn, "log_perm")
+        for t in (theta, log_perm):
+            if t is not None and self._stream != cur:
+                t.record_stream(self._stream)
+        _check(LIB.crv_set_params_device(self.ctx, th, lk))
+
+    def loss_grad_device(self, with_logperm: bool = False):
+        """crv_loss_grad_device: the loss (float64) and gradients (float32)
+        as CUDA tensors, ready for work on the current stream; no host
+        transfer and no wait."""
+        import torch
+        dev = self._ws.device
+        cur = torch.cuda.current_stream(dev)
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+        g = torch.empty(self.P, dtype=torch.float32, device=dev)
+        gl = (torch.empty((self.ne + 1,) * self.dim, dtype=torch.float32, device=dev)
+              if with_logperm else None)
+        self._stream.wait_stream(cur)
+        _check(LIB.crv_loss_grad_device(self.ctx, C.c_void_p(loss.data_ptr()),
+                                        C.c_void_p(g.data_ptr()),
+                                        None if gl is None else C.c_void_p(gl.data_ptr())))
+        if self._stream != cur:
+            for t in (loss, g, gl):
+                if t is not None:
+                    t.record_stream(self._stream)
+            cur.wait_stream(self._stream)
+        return (loss, g, gl) if with_logperm else (loss, g)
 
     def get_state(self):
         th, m, v = np.empty(self.P), np.empty(self.P), np.empty(self.P)
@@ -454,8 +501,11 @@ class BucketGroup:
         self.buckets, self.scenarios = [], []
 
 
-def scenario_from_problem(prob, precision: Optional[str] = None, **cfg_over) -> Scenario:
-    """Build a Scenario from an inputs.Problem."""
+def scenario_from_problem(prob, precision: Optional[str] = None, stream=None,
+                          **cfg_over) -> Scenario:
+    """Build a Scenario from an inputs.Problem (on the given torch stream,
+    default the current one)."""
     cfg = config(dim=prob.dim, n_elem=prob.n_elem, degree=prob.degree, width=prob.width,
                  hidden=prob.hidden, precision=precision or prob.precision, **cfg_over)
-    return Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0, prob.s0_coefs)
+    return Scenario(cfg, prob.log_perm, prob.porosity, prob.wells, prob.theta0, prob.s0_coefs,
+                    stream=stream)

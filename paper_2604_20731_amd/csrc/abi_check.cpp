@@ -106,6 +106,9 @@ int main() {
   expect("set_state NULL", crv_set_state(nullptr, &d, &d, &d, 0), CRV_EINVAL);
   expect("set_saturation NULL", crv_set_saturation(nullptr, &d), CRV_EINVAL);
   expect("set_log_perm NULL", crv_set_log_perm(nullptr, &d), CRV_EINVAL);
+  float fd = 0;
+  expect("loss_grad_device NULL", crv_loss_grad_device(nullptr, &d, &fd, &fd), CRV_EINVAL);
+  expect("set_params_device NULL", crv_set_params_device(nullptr, &fd, &fd), CRV_EINVAL);
   expect("loss_history NULL", crv_loss_history(nullptr, &d, 1, &it), CRV_EINVAL);
   expect("gram_solve NULL", crv_gram_solve(nullptr, &d, &d), CRV_EINVAL);
   expect("mass_solve NULL", crv_mass_solve(nullptr, &d, &d), CRV_EINVAL);

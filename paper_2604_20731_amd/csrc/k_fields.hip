@@ -309,6 +309,23 @@ void launch_adam_logk(int64_t n, Real* logk, Real* m, Real* v, const Real* g, Re
   k_adam_logk<Real><<<cdiv(n, 256), 256, 0, st>>>(n, logk, m, v, g, perm, lr, b1, b2, eps, t);
 }
 
+// log K taken from a device array: log K copied, K = exp(log K) evaluated in
+// float64 and rounded once, as the host path does
+__global__ __launch_bounds__(256) void k_set_logk(int64_t n, const float* __restrict__ src,
+                                                  float* __restrict__ logk,
+                                                  float* __restrict__ perm) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float lk = src[p];
+  logk[p] = lk;
+  perm[p] = float(exp(double(lk)));
+}
+
+void launch_set_logk(int64_t n, const float* src, float* logk, float* perm, hipStream_t st) {
+  if (n == 0) return;
+  k_set_logk<<<cdiv(n, 256), 256, 0, st>>>(n, src, logk, perm);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(256) void k_loss_finalize(const Real* __restrict__ part, int np,
                                                        double* __restrict__ hist, int cap,

@@ -125,6 +125,8 @@ template <typename Real>
 void launch_fill(Real* p, size_t n, Real v, hipStream_t st);
 template <typename Src, typename Dst>
 void launch_convert(const Src* in, Dst* out, size_t n, hipStream_t st);
+// logk[i] = src[i], perm[i] = exp(src[i]) (float32 contexts, src on the device)
+void launch_set_logk(int64_t n, const float* src, float* logk, float* perm, hipStream_t st);
 // non-finite check: sets *flag = 1 if any entry is NaN/Inf
 template <typename Real>
 void launch_check_finite(const Real* p, size_t n, int* flag, hipStream_t st, Batch bz = Batch{});

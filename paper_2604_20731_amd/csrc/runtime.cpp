@@ -183,7 +183,7 @@ static size_t carve(Carve& cv, const crv_config& c, Buffers<Real>& b) {
   b.t_dev = cv.take<long long>(1);
   b.t_zero = cv.take<long long>(1);
   b.tau = cv.take<double>(1);
-  b.flag = cv.take<int>(1);
+  b.flag = cv.take<int>(2);  // [0] numeric failure (sticky), [1] input check
   b.obs_w = cv.take<Real>(nn);
   b.obs_d = cv.take<Real>(nn);
   b.logk = cv.take<Real>(nn);
@@ -281,6 +281,8 @@ struct SolverBase {
   virtual crv_status set_state(const double*, const double*, const double*, int64_t) = 0;
   virtual crv_status set_saturation(const double*) = 0;
   virtual crv_status set_log_perm(const double*) = 0;
+  virtual crv_status loss_grad_device(double*, float*, float*) = 0;
+  virtual crv_status set_params_device(const float*, const float*) = 0;
   virtual crv_status set_observations(const double*, const double*) = 0;
   virtual crv_status invert(int iters, double lr_logk) = 0;
   virtual crv_status get_log_perm(double*) = 0;
@@ -1062,6 +1064,77 @@ struct Solver : SolverBase {
     return check_launch();
   }
 
+  // ---- differentiation form on device arrays (float32 contexts) ----
+  // p must be device memory: a host pointer handed to a kernel or a
+  // device-to-device copy would fault instead of failing
+  crv_status check_device_ptr(const void* p, const char* what) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+      (void)hipGetLastError();  // the query's failure is not a launch error
+      return fail(CRV_EINVAL, std::string(what) + " is not device memory");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+      return fail(CRV_EINVAL, std::string(what) + " is not device memory");
+    return CRV_OK;
+  }
+
+  crv_status loss_grad_device(double* d_loss, float* d_dtheta, float* d_dlogperm) override {
+    if constexpr (!std::is_same<Real, float>::value) {
+      return fail(CRV_EINVAL, "device-array differentiation needs a float32 context");
+    } else {
+      crv_status s;
+      if (d_loss && (s = check_device_ptr(d_loss, "loss"))) return s;
+      if (d_dtheta && (s = check_device_ptr(d_dtheta, "dtheta"))) return s;
+      if (d_dlogperm && (s = check_device_ptr(d_dlogperm, "dlogperm"))) return s;
+      loss_pass(nullptr);
+      grad_pass();
+      if (d_loss) {
+        launch_loss_finalize<Real>(b.loss_part, loss_count(), b.loss_scalar, 1, b.t_zero, 0, st);
+        CRV_HIP(hipMemcpyAsync(d_loss, b.loss_scalar, sizeof(double), hipMemcpyDeviceToDevice, st));
+      }
+      if (d_dtheta)
+        CRV_HIP(hipMemcpyAsync(d_dtheta, b.grad, size_t(P) * sizeof(float), hipMemcpyDeviceToDevice,
+                               st));
+      if (d_dlogperm) {
+        launch_grad_logperm<Real>(g, b.u, b.q, b.alpha, gravity() ? b.gflux : nullptr, cfg.gravity,
+                                  b.tmp_nodal, st);
+        CRV_HIP(hipMemcpyAsync(d_dlogperm, b.tmp_nodal, nn * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+      }
+      return check_launch();
+    }
+  }
+
+  crv_status set_params_device(const float* d_theta, const float* d_logperm) override {
+    if constexpr (!std::is_same<Real, float>::value) {
+      return fail(CRV_EINVAL, "device-array parameters need a float32 context");
+    } else {
+      crv_status s;
+      if (d_theta && (s = check_device_ptr(d_theta, "theta"))) return s;
+      if (d_logperm && (s = check_device_ptr(d_logperm, "log_perm"))) return s;
+      if (d_logperm) {
+        // reject non-finite log K before anything changes (one wait)
+        CRV_HIP(hipMemsetAsync(b.flag + 1, 0, sizeof(int), st));
+        launch_check_finite<float>(d_logperm, nn, b.flag + 1, st);
+        if ((s = check_launch())) return s;
+        int bad = 0;
+        CRV_HIP(hipMemcpyAsync(&bad, b.flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        CRV_HIP(hipStreamSynchronize(st));
+        if (bad) return fail(CRV_EINVAL, "log_perm has non-finite entries");
+      }
+      if (d_theta) {
+        CRV_HIP(hipMemcpyAsync(b.theta, d_theta, size_t(P) * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+        pack();
+      }
+      if (d_logperm) {
+        launch_set_logk(int64_t(nn), d_logperm, b.logk, b.perm, st);
+        refresh();
+      }
+      return check_launch();
+    }
+  }
+
   // ---- inverse problem ----
   void drop_graphs() {
     if (g_train) (void)hipGraphExecDestroy(g_train);
@@ -1403,6 +1476,16 @@ crv_status crv_get_fields(crv_ctx* c, double* p_nodal, double* s_coefs, double* 
 crv_status crv_loss_grad(crv_ctx* c, double* loss, double* dtheta, double* dlogperm) {
   CRV_CTX(c);
   return sv.loss_grad(loss, dtheta, dlogperm);
+}
+
+crv_status crv_loss_grad_device(crv_ctx* c, double* d_loss, float* d_dtheta, float* d_dlogperm) {
+  CRV_CTX(c);
+  return sv.loss_grad_device(d_loss, d_dtheta, d_dlogperm);
+}
+
+crv_status crv_set_params_device(crv_ctx* c, const float* d_theta, const float* d_log_perm) {
+  CRV_CTX(c);
+  return sv.set_params_device(d_theta, d_log_perm);
 }
 
 crv_status crv_get_state(crv_ctx* c, double* theta, double* m, double* v, int64_t* t) {

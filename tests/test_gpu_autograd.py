@@ -76,3 +76,84 @@ def test_autograd_c5_full_bf16(prec, tol, tol_dtheta):
     four layers: the documented 1e-1 bound of that form)."""
     say("autograd c5 129^3", prec)
     _check(problem("c5"), prec, tol, tol_dtheta=tol_dtheta)
+
+
+def _f32_inputs(prob, seed=11):
+    rng = np.random.default_rng(seed)
+    th = (prob.theta0 + 0.05 * rng.standard_normal(prob.theta0.size)).astype(np.float32)
+    lk = (prob.log_perm + 0.1 * rng.standard_normal(prob.log_perm.shape)).astype(np.float32)
+    return th, lk
+
+
+@pytest.mark.parametrize("name,prec,over", [
+    ("c1", "fp32", {}),
+    ("c2", "bf16x3f", {}),
+    ("c5", "fp32", dict(n_elem=16, width=32, hidden=4, wells=WELLS3)),
+])
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_device_arrays_match_host_arrays(name, prec, over, own_stream):
+    """crv_set_params_device + crv_loss_grad_device (the autograd path for
+    CUDA tensors) give what crv_set_state/crv_set_log_perm + crv_loss_grad
+    give on the same float32 values: the same kernels on the same inputs,
+    with K = exp(log K) rounded once from float64 on both sides.  With
+    own_stream the scenario runs on a stream of its own while the tensors
+    live on the current one."""
+    from paper_2604_20731_amd.autograd import crv_loss
+    say("device-array loss_grad", name, prec, "own stream" if own_stream else "current stream")
+    prob = problem(name, **over)
+    kw = dict(stream=torch.cuda.Stream()) if own_stream else {}
+    sc = scenario_for(prob, prec, **kw)
+    th, lk = _f32_inputs(prob)
+    t_before = sc.get_state()[3]
+    sc.set_theta(th.astype(np.float64))
+    sc.set_log_perm(lk.astype(np.float64))
+    l_h, g_h, gl_h = sc.loss_grad(with_logperm=True)
+    sc.set_theta(prob.theta0)           # the device call must replace both again
+    sc.set_log_perm(prob.log_perm)
+    theta = torch.tensor(th, device="cuda:0", requires_grad=True)
+    log_perm = torch.tensor(lk, device="cuda:0", requires_grad=True)
+    loss = crv_loss(theta, log_perm, sc)
+    loss.backward()
+    g = theta.grad.double().cpu().numpy()
+    gl = log_perm.grad.double().cpu().numpy()
+    e = dict(loss=abs(float(loss.detach()) - l_h) / abs(l_h), dtheta=rel(g, g_h), dlogK=rel(gl, gl_h),
+             dtheta_max=maxrel(g, g_h), dlogK_max=maxrel(gl, gl_h))
+    say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert all(v <= 1e-6 for v in e.values()), e
+    assert sc.get_state()[3] == t_before
+    # the host path reads back what the device call installed
+    assert np.array_equal(sc.get_state()[0], th.astype(np.float64))
+    assert np.array_equal(sc.log_perm(), lk.astype(np.float64))
+    sc.close()
+
+
+def test_device_array_errors():
+    """Non-finite log K is rejected before anything changes; host memory
+    and float64 contexts are rejected; wrong sizes are caught in Python."""
+    import ctypes as C
+    from paper_2604_20731_amd import crv
+    say("device-array error paths")
+    prob = problem("c1")
+    sc = scenario_for(prob, "fp32")
+    l0, g0 = sc.loss_grad()
+    bad = torch.tensor(prob.log_perm.ravel(), dtype=torch.float32, device="cuda:0")
+    bad[5] = float("nan")
+    with pytest.raises(crv.CrvError, match="non-finite"):
+        sc.set_params_device(log_perm=bad)
+    l1, g1 = sc.loss_grad()
+    assert l1 == l0 and np.array_equal(g1, g0)
+    host = torch.zeros(sc.P, dtype=torch.float32)
+    st = crv.LIB.crv_loss_grad_device(sc.ctx, None, C.c_void_p(host.data_ptr()), None)
+    assert st == -1 and b"device memory" in crv.LIB.crv_last_error()
+    st = crv.LIB.crv_set_params_device(sc.ctx, C.c_void_p(host.data_ptr()), None)
+    assert st == -1
+    with pytest.raises(ValueError):
+        sc.set_params_device(theta=torch.zeros(sc.P + 1, device="cuda:0"))
+    l2, _ = sc.loss_grad()
+    assert l2 == l0
+    sc.close()
+    sc64 = scenario_for(prob, "fp64")
+    d = torch.zeros(sc64.P, dtype=torch.float32, device="cuda:0")
+    st = crv.LIB.crv_loss_grad_device(sc64.ctx, None, C.c_void_p(d.data_ptr()), None)
+    assert st == -1 and b"float32 context" in crv.LIB.crv_last_error()
+    sc64.close()
