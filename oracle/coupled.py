@@ -14,7 +14,10 @@ Readings:
     the network has just been trained to;
   * one coupled step of length dt runs the ten substeps with tau = dt / 10;
   * the nodal saturation used for alpha is the spline evaluated at the nodes;
-  * Adam moments and step count persist across pretraining and all steps.
+  * Adam moments and step count persist across pretraining and all steps;
+  * the network output is multiplied by the interior indicator (default) or,
+    as an option, by the distance factor prod_a 4 x_a (1 - x_a): the paper
+    only asks that the trial functions vanish on the boundary.
 """
 from __future__ import annotations
 
@@ -27,7 +30,8 @@ class Oracle:
     def __init__(self, dim, n_elem, degree, width, hidden, log_perm, porosity, wells,
                  theta0, s0_coefs=None, mu_w=1.0, mu_g=0.1, relperm_exp=2.0,
                  lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, adam_iters=100,
-                 substeps=10, well_radius=0.06, gravity=0.0, rho_w=0.0, rho_g=0.0):
+                 substeps=10, well_radius=0.06, gravity=0.0, rho_w=0.0, rho_g=0.0,
+                 boundary_factor=0):
         self.dim, self.n_elem, self.r = dim, n_elem, degree
         self.dims = mlp.layer_dims(dim, width, hidden)
         self.mu_w, self.mu_g, self.n_exp = mu_w, mu_g, relperm_exp
@@ -45,7 +49,12 @@ class Oracle:
         self.theta = np.asarray(theta0, dtype=np.float64).copy()
         self.adam = mlp.Adam(self.theta.size, lr, beta1, beta2, eps)
         self.z = mlp.node_inputs(n_elem, dim)
-        self.mask = pressure.interior_mask(n_elem, dim)
+        # trial-function factor: u = factor * NN (interior indicator, or the
+        # distance form prod 4 x (1 - x) with boundary_factor = 1)
+        if boundary_factor not in (0, 1):
+            raise ValueError("boundary_factor must be 0 or 1")
+        self.mask = (pressure.interior_mask(n_elem, dim) if boundary_factor == 0
+                     else pressure.distance_factor(n_elem, dim))
         self.loss_history = []
         self.obs_d = self.obs_w = None
         self.refresh()

@@ -117,6 +117,19 @@ def interior_mask(n_elem: int, dim: int) -> np.ndarray:
     return m
 
 
+def distance_factor(n_elem: int, dim: int) -> np.ndarray:
+    """The distance form of the trial-function factor: prod over the axes of
+    4 x_a (1 - x_a) at the nodes, x_a = i_a / N.  It vanishes on every
+    boundary face (so the trial function meets the zero pressure condition,
+    as with the interior indicator) and equals one at the centre."""
+    x = np.arange(n_elem + 1) / n_elem
+    f1 = 4.0 * x * (1.0 - x)
+    out = f1
+    for _ in range(dim - 1):
+        out = np.multiply.outer(f1, out)
+    return out
+
+
 def stiffness_full(alpha: np.ndarray, n_elem: int) -> sp.csr_matrix:
     """Matrix of a_h on the full grid: a_h(u, v) = v^T A u with
     a_h(u,v) = h^d sum_a sum_edges alpha_lower (D_a u)(D_a v)."""

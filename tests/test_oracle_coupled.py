@@ -102,3 +102,40 @@ def test_gradients_3d_match_central_differences():
         assert abs(gl.ravel()[k] - fd) < 1e-7 * max(1.0, abs(fd)), k
     o.perm = base
     o.refresh()
+
+
+def _tiny_factor(dim=2):
+    p = (inputs.make_problem("tiny") if dim == 2 else
+         inputs.make_problem("c5", n_elem=4, width=8, hidden=2, wells=np.array([[0.5, 0.5, 1.0]])))
+    return p, Oracle(p.dim, p.n_elem, p.degree, p.width, p.hidden, p.log_perm,
+                     p.porosity, p.wells, p.theta0, boundary_factor=1)
+
+
+def test_distance_factor_trial_function_closed_form():
+    """With every weight zero the network is its output bias b, so the trial
+    function is b prod_a 4 x_a (1 - x_a), written out node by node here."""
+    p, o = _tiny_factor()
+    th = np.zeros_like(o.theta)
+    th[-1] = 0.7
+    u = o.u_nodal(th)
+    n = p.n_elem
+    for j in range(n + 1):
+        for i in range(n + 1):
+            x, y = i / n, j / n
+            assert abs(u[j, i] - 0.7 * 16 * x * (1 - x) * y * (1 - y)) < 1e-15
+    assert np.all(u[0] == 0) and np.all(u[-1] == 0) and np.all(u[:, 0] == 0)
+    assert np.all(u[:, -1] == 0)
+
+
+def test_distance_factor_gradients_match_central_differences():
+    """dLOSS/dtheta with the distance factor (the backward must carry the
+    factor, not the indicator), 2D and 3D, against central differences."""
+    for dim, seed in ((2, 6), (3, 8)):
+        p, o = _tiny_factor(dim)
+        th = o.theta + 0.05 * np.random.default_rng(seed).standard_normal(o.theta.size)
+        _, g = o.loss_and_grad(th)
+        eps = 1e-6
+        for k in np.random.default_rng(seed + 1).choice(th.size, size=12, replace=False):
+            e = np.zeros_like(th); e[k] = eps
+            fd = (o.loss_and_grad(th + e)[0] - o.loss_and_grad(th - e)[0]) / (2 * eps)
+            assert abs(g[k] - fd) < 1e-7 * max(1.0, abs(fd)), (dim, k)
