@@ -27,14 +27,15 @@
  *     s = clamp(S, 0, 1) (second eq. 23 with Brooks-Corey mobilities);
  *   - RES_k = a_h(u, delta_k) - (q, delta_k)_h at interior nodes (eq. 24-25),
  *     G = (delta, delta)_{nabla,h} (eq. 26, no h^-2 factor), LOSS = RES.G^-1 RES;
- *   - network u = m NN_theta(2x - 1), m = 0 on the boundary, tanh hidden
- *     layers, linear output.
+ *   - network u = f NN_theta(2x - 1), f the trial-function factor (zero on
+ *     the boundary; crv_config.boundary_factor), tanh hidden layers, linear
+ *     output.
  *
  * Array layouts (all host arrays are float64, C order, x fastest):
  *   nodal      (N+1)^d        index ((k*(N+1)) + j)*(N+1) + i
  *   interior   (N-1)^d        node (i,j[,k]) with 1 <= i,j,k <= N-1
  *   coefs      nb^d           index ((c*nb) + b)*nb + a
- *   wells      n_wells x 3    rows (x, y, rate); rate > 0 injects gas
+ *   wells      n_wells        crv_well records (x, y, rate); rate > 0 injects gas
  *   theta      n_params       per layer W (out x in, row-major) then b (out),
  *                             layers d -> width (x hidden, tanh) -> 1
  *
@@ -104,9 +105,22 @@ typedef struct {
    * q - div_+(g K (kr_w rho_w/mu_w + kr_g rho_g/mu_g)) (forward difference
    * along e_v), the gas flux lambda_g K (grad p - rho_g g).  0 = off. */
   double gravity, rho_w, rho_g;
+  /* Trial-function factor u = f NN (eq. 23: the trial functions vanish on
+   * the boundary): 0 = interior indicator (default), 1 = distance factor
+   * prod_a 4 x_a (1 - x_a) (also zero on the boundary, one at the centre);
+   * other values CRV_EINVAL. */
+  int boundary_factor;
 } crv_config;
 
 typedef struct crv_ctx crv_ctx;
+
+/* One well (IGA-ADS-CRVPINN algorithm, step 1: the sources q_w, q_g): a disc
+ * of radius crv_config.well_radius around (x, y) in 2D, a vertical cylinder
+ * over the interior z nodes in 3D; rate > 0 injects gas, rate < 0 produces.
+ * Three doubles, the same bytes as a row of an n x 3 float64 array. */
+typedef struct {
+  double x, y, rate;
+} crv_well;
 
 /* Defaults: 2D, Ne 32, r 2, width 32, 3 hidden layers, FP32, mu_w 1,
  * mu_g 0.1, n 2, Adam lr 1e-4 (the paper's value), beta (0.9, 0.999),
@@ -117,20 +131,26 @@ crv_status crv_config_default(crv_config* cfg);
 /* Number of network parameters for cfg. */
 crv_status crv_param_count(const crv_config* cfg, int64_t* n);
 
-/* Device bytes crv_init needs for cfg (workspace footprint). */
+/* Device bytes crv_init needs for cfg: every array of IGA-ADS-CRVPINN
+ * algorithm steps 1-7 (inputs, fields, network state, Adam moments, Gram and
+ * mass factors, scratch), 256-byte aligned; the serving admission budget. */
 crv_status crv_workspace_size(const crv_config* cfg, size_t* bytes);
 
 /* Algorithm step 1.  log_perm, porosity: nodal (N+1)^d; porosity > 0.
- * wells: n_wells x 3; every well disc (3D: vertical cylinder over the
+ * wells: n_wells records; every well disc (3D: vertical cylinder over the
  * interior z nodes) must cover at least one node and no boundary node.
  * s0_coefs: nb^d initial saturation coefficients, NULL for zero.
- * theta0: initial network parameters (crv_param_count values).
+ * theta0: initial network parameters (crv_param_count values), or NULL for
+ * the seeded default: Xavier-uniform weights a (2u - 1), a = sqrt(6 /
+ * (fan_in + fan_out)), u = (x_k >> 11) 2^-53 with x_k output k of SplitMix64
+ * started at seed (k counts the weights in the theta layout), zero biases.
+ * seed is read only when theta0 is NULL.
  * stream: a hipStream_t (NULL = default stream).  On success *out holds the
  * context.  Returns CRV_EINVAL for invalid input, CRV_ENOMEM when ws_bytes
  * is below crv_workspace_size. */
 crv_status crv_init(const crv_config* cfg, const double* log_perm, const double* porosity,
-                    const double* wells, int n_wells, const double* s0_coefs,
-                    const double* theta0, void* d_workspace, size_t ws_bytes,
+                    const crv_well* wells, int n_wells, const double* s0_coefs,
+                    const double* theta0, uint64_t seed, void* d_workspace, size_t ws_bytes,
                     void* stream, crv_ctx** out);
 
 /* Algorithm step 2 (and step 7): iters Adam iterations on the robust loss

@@ -46,6 +46,7 @@ class CrvConfig(C.Structure):
         ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
         ("adam_iters", C.c_int), ("substeps", C.c_int), ("well_radius", C.c_double),
         ("gravity", C.c_double), ("rho_w", C.c_double), ("rho_g", C.c_double),
+        ("boundary_factor", C.c_int),
     ]
 
 
@@ -71,7 +72,8 @@ def _load() -> C.CDLL:
         "crv_config_default": [cfgp],
         "crv_param_count": [cfgp, C.POINTER(C.c_int64)],
         "crv_workspace_size": [cfgp, C.POINTER(C.c_size_t)],
-        "crv_init": [cfgp, dp, dp, dp, C.c_int, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)],
+        "crv_init": [cfgp, dp, dp, dp, C.c_int, dp, dp, C.c_uint64, vp, C.c_size_t, vp,
+                     C.POINTER(vp)],
         "crv_pretrain_pressure": [vp, C.c_int, dp],
         "crv_step": [vp, C.c_double],
         "crv_step_batch": [C.POINTER(vp), dp, C.c_int],
@@ -156,10 +158,11 @@ def workspace_size(cfg: CrvConfig) -> int:
 class Scenario:
     """One reservoir scenario: a libcrv context on the current torch stream
     with a torch-allocated device workspace (or the given uint8 device tensor
-    of at least workspace_size(cfg) bytes, 256-byte aligned)."""
+    of at least workspace_size(cfg) bytes, 256-byte aligned).  theta0 None
+    takes the library's seeded default parameters (seed)."""
 
     def __init__(self, cfg: CrvConfig, log_perm, porosity, wells, theta0, s0_coefs=None,
-                 device: str = "cuda:0", stream=None, workspace=None):
+                 device: str = "cuda:0", stream=None, workspace=None, seed: int = 0):
         import torch  # device memory and streams only
         self.cfg = cfg
         self.dim, self.ne, self.r = cfg.dim, cfg.n_elem, cfg.degree
@@ -179,17 +182,17 @@ class Scenario:
         self._stream = st
         lp, po = _f64(log_perm).ravel(), _f64(porosity).ravel()
         w = _f64(wells).reshape(-1, 3)
-        th = _f64(theta0).ravel()
+        th = None if theta0 is None else _f64(theta0).ravel()
         s0 = None if s0_coefs is None else _f64(s0_coefs).ravel()
         if lp.size != self.nn or po.size != self.nn:
             raise ValueError("nodal arrays must have (N+1)^d entries")
-        if th.size != self.P:
+        if th is not None and th.size != self.P:
             raise ValueError(f"theta0 must have {self.P} entries")
         if s0 is not None and s0.size != self.nc:
             raise ValueError("s0_coefs must have nb^d entries")
         ctx = C.c_void_p()
         _check(LIB.crv_init(C.byref(cfg), _dp(lp), _dp(po), _dp(w), int(w.shape[0]), _dp(s0),
-                            _dp(th), C.c_void_p(self._ws.data_ptr()), self.ws_bytes,
+                            _dp(th), int(seed), C.c_void_p(self._ws.data_ptr()), self.ws_bytes,
                             C.c_void_p(st.cuda_stream), C.byref(ctx)))
         self.ctx = ctx
 

@@ -59,6 +59,7 @@ int main() {
       {"well_radius 0", [](crv_config* x) { x->well_radius = 0.0; }},
       {"gravity -1", [](crv_config* x) { x->gravity = -1.0; }},
       {"rho_g inf", [](crv_config* x) { x->rho_g = INFINITY; }},
+      {"boundary_factor 2", [](crv_config* x) { x->boundary_factor = 2; }},
   };
   for (const Bad& b : bad) {
     crv_config x;
@@ -70,7 +71,7 @@ int main() {
     std::snprintf(what, sizeof what, "init %s", b.name);
     crv_ctx* ctx = nullptr;
     std::vector<double> one(64, 0.0);
-    expect(what, crv_init(&x, one.data(), one.data(), nullptr, 0, nullptr, one.data(), nullptr, 0,
+    expect(what, crv_init(&x, one.data(), one.data(), nullptr, 0, nullptr, one.data(), 0, nullptr, 0,
                           nullptr, &ctx),
            CRV_EINVAL);
   }
@@ -80,15 +81,15 @@ int main() {
   const size_t nn = size_t(c.n_elem + 1) * (c.n_elem + 1);
   std::vector<double> lp(nn, 0.0), po(nn, 0.2), th(size_t(np), 0.0);
   expect("init NULL log_perm", crv_init(&c, nullptr, po.data(), nullptr, 0, nullptr, th.data(),
-                                        nullptr, 0, nullptr, &ctx), CRV_EINVAL);
+                                        0, nullptr, 0, nullptr, &ctx), CRV_EINVAL);
   expect("init NULL out", crv_init(&c, lp.data(), po.data(), nullptr, 0, nullptr, th.data(),
-                                   nullptr, 0, nullptr, nullptr), CRV_EINVAL);
+                                   0, nullptr, 0, nullptr, nullptr), CRV_EINVAL);
   alignas(256) static char small[512];
   expect("init workspace too small", crv_init(&c, lp.data(), po.data(), nullptr, 0, nullptr,
-                                              th.data(), small, sizeof small, nullptr, &ctx),
+                                              th.data(), 0, small, sizeof small, nullptr, &ctx),
          CRV_ENOMEM);
   expect("init workspace misaligned", crv_init(&c, lp.data(), po.data(), nullptr, 0, nullptr,
-                                               th.data(), small + 8, size_t(1) << 40, nullptr,
+                                               th.data(), 0, small + 8, size_t(1) << 40, nullptr,
                                                &ctx),
          CRV_EINVAL);
 

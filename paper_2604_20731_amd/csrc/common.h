@@ -18,6 +18,7 @@ struct Geom {
   int nb;   // coefficients per axis (ne + r)
   int m;    // interior nodes per axis (ne - 1)
   int mp;   // padded pitch of interior arrays (multiple of 64)
+  int bfac = 0;  // trial-function factor: 0 interior indicator, 1 prod 4 x (1 - x)
 };
 
 // Scenario batching.  Scenarios of one configuration whose workspaces lie zb
@@ -153,6 +154,22 @@ __device__ inline void node_ijk(int64_t p, int n, int* i, int* j, int* k) {
     *j = int(q1);
     *k = 0;
   }
+}
+
+// trial-function factor at an interior node (i, j[, k]) (eq. 23 asks only
+// that the trial functions vanish on the boundary): 1 for the interior
+// indicator, prod_a 4 x_a (1 - x_a), x_a = i_a / ne, for the distance form
+// (float64, the axes multiplied in the order i, j, k)
+template <int DIM>
+__device__ inline double trial_factor(int bfac, int ne, int i, int j, int k) {
+  if (!bfac) return 1.0;
+  const double xi = double(i) / double(ne), xj = double(j) / double(ne);
+  double f = (4.0 * xi * (1.0 - xi)) * (4.0 * xj * (1.0 - xj));
+  if (DIM == 3) {
+    const double xk = double(k) / double(ne);
+    f *= 4.0 * xk * (1.0 - xk);
+  }
+  return f;
 }
 
 }  // namespace crv

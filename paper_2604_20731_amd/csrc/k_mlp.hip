@@ -20,7 +20,7 @@ int64_t mlp_param_count(int dim, int width, int hidden) {
 }
 
 template <typename Real, int DIM>
-__device__ inline void node_input(const Geom& g, int64_t p, Real* z, bool* interior) {
+__device__ inline void node_input(const Geom& g, int64_t p, Real* z, bool* interior, Real* fac) {
   const int n = g.n;
   const int i = int(p % n);
   const int j = int((p / n) % n);
@@ -32,6 +32,7 @@ __device__ inline void node_input(const Geom& g, int64_t p, Real* z, bool* inter
   bool in = i > 0 && i < g.ne && j > 0 && j < g.ne;
   if (DIM == 3) in = in && k > 0 && k < g.ne;
   *interior = in;
+  *fac = in ? Real(trial_factor<DIM>(g.bfac, g.ne, i, j, k)) : Real(0);
 }
 
 // exact i/N as the oracle computes it (double division, then scaling)
@@ -42,9 +43,9 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(Geom g, int hidden, const Real*
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t_bump && p == 0) *t_bump = *t_bump + 1;  // first kernel of an Adam iteration
   if (p >= total) return;
-  Real z[DIM];
+  Real z[DIM], fac;
   bool interior;
-  node_input<Real, DIM>(g, p, z, &interior);
+  node_input<Real, DIM>(g, p, z, &interior, &fac);
   Real h[W], hn[W];
   const Real* w = th;
 #pragma unroll
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(Geom g, int hidden, const Real*
   Real y = w[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) y += w[i] * h[i];
-  u[p] = interior ? y : Real(0);
+  u[p] = interior ? fac * y : Real(0);
 }
 
 // Backward: a block of NT threads handles NT nodes per tile and loops over
@@ -98,9 +99,9 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(Geom g, int hidden, int64_t P,
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t p = tile * NT + tid;
     const bool valid = p < total;
-    Real z[DIM];
+    Real z[DIM], fac = 0;
     bool interior = false;
-    if (valid) node_input<Real, DIM>(g, p, z, &interior);
+    if (valid) node_input<Real, DIM>(g, p, z, &interior, &fac);
     else
       for (int c = 0; c < DIM; ++c) z[c] = 0;
     for (int c = 0; c < DIM; ++c) Zs[c * NT + tid] = z[c];
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(Geom g, int hidden, int64_t P,
         w += W * W + W;
       }
     }
-    const Real gv = (valid && interior) ? gu[p] : Real(0);
+    const Real gv = (valid && interior) ? fac * gu[p] : Real(0);  // dLOSS/dNN = f dLOSS/du
     Gs[tid] = gv;
     // delta of the last hidden layer: g * w_out * (1 - h^2)
     {

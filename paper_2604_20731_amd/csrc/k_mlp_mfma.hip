@@ -319,8 +319,10 @@ __global__ void k_pack_fragments(const float* __restrict__ th, int dim, int W, i
   T::put(frag + frag_index<MODE>(hl, dir, mb, ks, lane, v, W), w);
 }
 
+// network input of node p and its trial-function factor (0 on the boundary)
 template <int DIM>
-__device__ inline void node_z(int64_t p, int n, int ne, float* z, bool* interior) {
+__device__ inline void node_z(int64_t p, int n, int ne, int bfac, float* z, bool* interior,
+                              float* fac) {
   int i, j, k;
   node_ijk<DIM>(p, n, &i, &j, &k);
   const double inv = 1.0 / double(ne);
@@ -332,6 +334,7 @@ __device__ inline void node_z(int64_t p, int n, int ne, float* z, bool* interior
     in = in && k > 0 && k < ne;
   }
   *interior = in;
+  *fac = in ? float(trial_factor<DIM>(bfac, ne, i, j, k)) : 0.f;
 }
 
 // Small parameters staged in LDS per block: W1 (W x DIM), b1, the hidden
@@ -491,12 +494,14 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
   if (tile0 * 16 >= total) return;  // whole wave leaves together
   float z[TPW][DIM];
   bool interior[TPW];
+  float fac[TPW];
   int64_t p[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     p[t] = (tile0 + 4 * t) * 16 + n;
     interior[t] = false;
-    if (p[t] < total) node_z<DIM>(p[t], geo.n, geo.ne, z[t], &interior[t]);
+    fac[t] = 0.f;
+    if (p[t] < total) node_z<DIM>(p[t], geo.n, geo.ne, geo.bfac, z[t], &interior[t], &fac[t]);
     else
       for (int c = 0; c < DIM; ++c) z[t][c] = 0.f;
   }
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
     for (int r = 0; r < NR; ++r) s += wo[cfeat(r, q)] * h[t][r];
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
-    if (q == 0 && p[t] < total) u[p[t]] = interior[t] ? s + wo[W] : 0.f;
+    if (q == 0 && p[t] < total) u[p[t]] = interior[t] ? fac[t] * (s + wo[W]) : 0.f;
   }
 }
 
@@ -688,8 +693,9 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
     for (int t = 0; t < TPW; ++t) {
       const int64_t p = step * NB + col[t];
       bool interior = false;
+      float fac = 0.f;
       const bool valid = p < total;
-      if (valid) node_z<DIM>(p, geo.n, geo.ne, z[t], &interior);
+      if (valid) node_z<DIM>(p, geo.n, geo.ne, geo.bfac, z[t], &interior, &fac);
       else
         for (int c = 0; c < DIM; ++c) z[t][c] = 0.f;
       // the adjoint's loads first: their latency hides behind the recompute
@@ -702,6 +708,7 @@ __global__ __launch_bounds__(64 * NW, (bwd_min_waves<W, MODE, TPW>())) void k_ml
         gv[t] += 2.f * ow * r;
         if (q == 0) lacc += ow * r * r;
       }
+      if (geo.bfac) gv[t] *= fac;  // dLOSS/dNN = f dLOSS/du
     }
     float d[TPW][NR];
     forward_tiles<W, L, MODE, DIM, (W <= 64), TPW>(sp, fr, l1, z, q, lane, d, sink);

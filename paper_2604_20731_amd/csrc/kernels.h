@@ -175,7 +175,7 @@ struct MlpShape {
   int64_t nparams;
 };
 int64_t mlp_param_count(int dim, int width, int hidden);
-// u = mask * NN(2x-1) on all nodes; t_bump (nullable) is incremented once.
+// u = f * NN(2x-1) on all nodes (f the trial-function factor); t_bump (nullable) is incremented once.
 template <typename Real>
 void launch_mlp_forward(const Geom& g, const MlpShape& s, const Real* theta, Real* u,
                         long long* t_bump, hipStream_t st);

@@ -75,6 +75,7 @@ static Geom make_geom(const crv_config& c) {
   g.nb = c.n_elem + c.degree;
   g.m = c.n_elem - 1;
   g.mp = (g.m + 63) / 64 * 64;
+  g.bfac = c.boundary_factor;
   return g;
 }
 
@@ -219,6 +220,8 @@ static crv_status validate_config(const crv_config* c) {
   if (!(c->gravity >= 0 && std::isfinite(c->gravity)) || !(c->rho_w >= 0 && std::isfinite(c->rho_w)) ||
       !(c->rho_g >= 0 && std::isfinite(c->rho_g)))
     return fail(CRV_EINVAL, "gravity and densities must be finite and >= 0");
+  if (c->boundary_factor != 0 && c->boundary_factor != 1)
+    return fail(CRV_EINVAL, "boundary_factor must be 0 (indicator) or 1 (distance factor)");
   return CRV_OK;
 }
 
@@ -316,7 +319,7 @@ static bool same_config(const crv_config& a, const crv_config& b) {
          a.beta1 == b.beta1 && a.beta2 == b.beta2 && a.eps == b.eps &&
          a.adam_iters == b.adam_iters && a.substeps == b.substeps &&
          a.well_radius == b.well_radius && a.gravity == b.gravity && a.rho_w == b.rho_w &&
-         a.rho_g == b.rho_g;
+         a.rho_g == b.rho_g && a.boundary_factor == b.boundary_factor;
 }
 
 template <typename Real>
@@ -1329,14 +1332,50 @@ crv_status crv_workspace_size(const crv_config* c, size_t* bytes) {
   return CRV_OK;
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014), as a counter-based stream: output k of the
+// generator started at state seed
+static uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// seeded default parameters: Xavier-uniform weights a (2 u_k - 1),
+// a = sqrt(6 / (fan_in + fan_out)), u_k = (output k >> 11) 2^-53 with k
+// counting the weights in layout order; zero biases
+static std::vector<double> default_theta(const crv_config& c, uint64_t seed) {
+  std::vector<double> th;
+  std::vector<int> d{c.dim};
+  for (int l = 0; l < c.hidden; ++l) d.push_back(c.width);
+  d.push_back(1);
+  uint64_t k = 0;
+  for (size_t l = 0; l + 1 < d.size(); ++l) {
+    const double a = std::sqrt(6.0 / double(d[l] + d[l + 1]));
+    for (int e = 0; e < d[l] * d[l + 1]; ++e) {
+      const double u = double(splitmix64(seed, k++) >> 11) * 0x1.0p-53;
+      th.push_back(a * (2.0 * u - 1.0));
+    }
+    th.insert(th.end(), size_t(d[l + 1]), 0.0);
+  }
+  return th;
+}
+
 crv_status crv_init(const crv_config* c, const double* log_perm, const double* porosity,
-                    const double* wells, int n_wells, const double* s0_coefs,
-                    const double* theta0, void* d_workspace, size_t ws_bytes, void* stream,
-                    crv_ctx** out) {
+                    const crv_well* wells, int n_wells, const double* s0_coefs,
+                    const double* theta0, uint64_t seed, void* d_workspace, size_t ws_bytes,
+                    void* stream, crv_ctx** out) {
+  static_assert(sizeof(crv_well) == 3 * sizeof(double), "crv_well is three doubles");
   crv_status s = validate_config(c);
   if (s) return s;
-  if (!out || !log_perm || !porosity || !theta0)
-    return fail(CRV_EINVAL, "log_perm, porosity, theta0 and out are required");
+  if (!out || !log_perm || !porosity)
+    return fail(CRV_EINVAL, "log_perm, porosity and out are required");
+  std::vector<double> theta_default;
+  if (!theta0) {
+    theta_default = default_theta(*c, seed);
+    theta0 = theta_default.data();
+  }
   *out = nullptr;
   size_t need = 0;
   crv_workspace_size(c, &need);
@@ -1363,7 +1402,8 @@ crv_status crv_init(const crv_config* c, const double* log_perm, const double* p
   sv.P = mlp_param_count(c->dim, c->width, c->hidden);
   sv.ws = d_workspace;
   sv.owns_ws = owns;
-  s = sv.init(log_perm, porosity, wells, n_wells, s0_coefs, theta0);
+  s = sv.init(log_perm, porosity, reinterpret_cast<const double*>(wells), n_wells, s0_coefs,
+              theta0);
   if (s) return s;
   *out = ctx.release();
   return CRV_OK;

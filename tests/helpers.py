@@ -1,5 +1,7 @@
 """Shared builders for the GPU parity tests: the same seeded Problem feeds the
 HIP scenario and the FP64 oracle (which share no code)."""
+import math
+
 import numpy as np
 
 from paper_2604_20731_amd import inputs
@@ -53,3 +55,28 @@ def scenario_for(prob, precision, **kw):
 
 def say(*a):
     print(*a, flush=True)
+
+
+def splitmix64(seed, k):
+    """Output k of SplitMix64 started at state seed (Steele, Lea and Flood,
+    OOPSLA 2014), written out from its definition."""
+    m = (1 << 64) - 1
+    z = (seed + (k + 1) * 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def default_theta(dim, width, hidden, seed):
+    """The library's seeded default parameters: Xavier-uniform weights from
+    splitmix64 outputs in layout order (top 53 bits), zero biases."""
+    d = [dim] + [width] * hidden + [1]
+    out, k = [], 0
+    for i in range(len(d) - 1):
+        a = math.sqrt(6.0 / (d[i] + d[i + 1]))
+        for _ in range(d[i] * d[i + 1]):
+            u = (splitmix64(seed, k) >> 11) * 2.0 ** -53
+            out.append(a * (2.0 * u - 1.0))
+            k += 1
+        out += [0.0] * d[i + 1]
+    return np.array(out)

@@ -98,7 +98,7 @@ def test_gravity_config_and_galerkin_argument_errors():
     cfg = crv.config()
     assert cfg.gravity == 0.0 and cfg.rho_w == 0.0 and cfg.rho_g == 0.0
     names = [f for f, _ in crv.CrvConfig._fields_]
-    assert names[-3:] == ["gravity", "rho_w", "rho_g"]
+    assert names[-4:] == ["gravity", "rho_w", "rho_g", "boundary_factor"]
     assert crv.workspace_size(crv.config(gravity=9.81, rho_w=1.0, rho_g=0.5)) > 0
     for bad in (dict(gravity=-1.0), dict(rho_w=-0.1), dict(rho_g=float("nan"))):
         n = C.c_size_t()
@@ -119,3 +119,36 @@ def test_precond_constants_match_the_header():
     found = {m.group(1).lower(): int(m.group(2))
              for m in re.finditer(r"#define CRV_PRECOND_(\w+) (\d+)", text)}
     assert found == crv.PRECOND
+
+
+def test_config_struct_matches_header():
+    """The binding's crv_config has the header's fields, in order, with the
+    header's C types (read from the struct declaration in include/crv.h)."""
+    import ctypes as C
+    import re
+    from pathlib import Path
+    text = (Path(__file__).resolve().parents[1] / "include" / "crv.h").read_text()
+    body = re.search(r"typedef struct \{(.*?)\} crv_config;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    header = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, rest = decl.split(None, 1)
+        header += [(n.strip(), ctype) for n in rest.split(",")]
+    ctypes_of = {"int": C.c_int, "double": C.c_double}
+    assert [(n, ctypes_of[t]) for n, t in header] == list(crv.CrvConfig._fields_)
+    assert crv.config().boundary_factor == 0
+    n = C.c_size_t()
+    assert crv.LIB.crv_workspace_size(C.byref(crv.config(boundary_factor=2)), C.byref(n)) == -1
+    assert crv.workspace_size(crv.config(boundary_factor=1)) > 0
+
+
+def test_splitmix64_published_vector():
+    """The tests' SplitMix64 (the generator of the library's seeded default
+    parameters) reproduces the published outputs for seed 1234567."""
+    from helpers import splitmix64
+    assert [splitmix64(1234567, k) for k in range(5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423,
+        4593380528125082431, 16408922859458223821]
