@@ -66,10 +66,10 @@ CASES = [("bf16x3f", 64, 64, 3), ("fp32", 48, 32, 2), ("bf16x3f", 128, 128, 2), 
          ("bf16x3", 40, 32, 4), ("bf16x3f", 512, 64, 3), ("fp32", 64, 128, 2)]
 
 
-def _run(prec, ne, width, n, shared, part=1):
+def _run(prec, ne, width, n, shared, part=1, **cfg_kw):
     from paper_2604_20731_amd import crv
     probs = _problems(n, ne, width)
-    cfg = crv.config(dim=2, n_elem=ne, degree=2, width=width, hidden=4, precision=prec)
+    cfg = crv.config(dim=2, n_elem=ne, degree=2, width=width, hidden=4, precision=prec, **cfg_kw)
     bucket = crv.Bucket(cfg, probs)
     singles = [crv.Scenario(cfg, p.log_perm, p.porosity, p.wells, p.theta0) for p in probs]
     for sc in bucket.scenarios + singles:
@@ -99,6 +99,21 @@ def test_bucket_step_equals_single_steps(prec, ne, width, n):
     for sc in singles:
         sc.close()
     say(f"  {n} scenarios bitwise equal to single steps")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,ne,width", [("bf16x3f", 64, 64), ("fp32", 48, 32)])
+def test_bucket_step_with_distance_factor_equals_single_steps(prec, ne, width):
+    """The distance trial factor rides in the batched kernels' geometry: a
+    bucket of such scenarios still steps bitwise as single steps."""
+    say("bucket, distance factor", prec, ne, width)
+    crv, bucket, singles, dts = _run(prec, ne, width, 2, False, boundary_factor=1)
+    for k, (a, b) in enumerate(zip(bucket.scenarios, singles)):
+        assert _same(a, b), (prec, ne, width, k)
+    assert bucket.scenarios[0].cfg.boundary_factor == 1
+    bucket.close()
+    for sc in singles:
+        sc.close()
 
 
 @pytest.mark.timeout(600)
