@@ -85,24 +85,26 @@ def _f32_inputs(prob, seed=11):
     return th, lk
 
 
-@pytest.mark.parametrize("name,prec,over", [
-    ("c1", "fp32", {}),
-    ("c2", "bf16x3f", {}),
-    ("c5", "fp32", dict(n_elem=16, width=32, hidden=4, wells=WELLS3)),
+@pytest.mark.parametrize("name,prec,over,cfg", [
+    ("c1", "fp32", {}, {}),
+    ("c2", "bf16x3f", {}, {}),
+    ("c5", "fp32", dict(n_elem=16, width=32, hidden=4, wells=WELLS3), {}),
+    ("c1", "bf16x3f", {}, dict(gravity=2.0, rho_w=1.2, rho_g=0.4, boundary_factor=1)),
 ])
 @pytest.mark.parametrize("own_stream", [False, True])
-def test_device_arrays_match_host_arrays(name, prec, over, own_stream):
+def test_device_arrays_match_host_arrays(name, prec, over, cfg, own_stream):
     """crv_set_params_device + crv_loss_grad_device (the autograd path for
     CUDA tensors) give what crv_set_state/crv_set_log_perm + crv_loss_grad
     give on the same float32 values: the same kernels on the same inputs,
     with K = exp(log K) rounded once from float64 on both sides.  With
     own_stream the scenario runs on a stream of its own while the tensors
-    live on the current one."""
+    live on the current one.  The last case adds gravity (the right-hand side
+    term of dLOSS/dlogK) and the distance trial factor."""
     from paper_2604_20731_amd.autograd import crv_loss
     say("device-array loss_grad", name, prec, "own stream" if own_stream else "current stream")
     prob = problem(name, **over)
     kw = dict(stream=torch.cuda.Stream()) if own_stream else {}
-    sc = scenario_for(prob, prec, **kw)
+    sc = scenario_for(prob, prec, **kw, **cfg)
     th, lk = _f32_inputs(prob)
     t_before = sc.get_state()[3]
     sc.set_theta(th.astype(np.float64))
