@@ -378,54 +378,72 @@ void launch_band_rows(const Real* b, Real* x, int n, int nlines, int64_t line_st
 
 // Strided lines (element j of line c at x[j*row_stride + c]), shared
 // coefficients.  A block owns 16 consecutive lines and splits their length
-// into 64 chunks: wave w, lane group s = lane/16 takes chunk 4w + s of line
-// lane%16 (so a row access reads 4 runs of 16 consecutive values).  Each
-// chunk composes its affine map (particular solution + r homogeneous ones),
-// 16 lanes of wave 0 chain the 64 chunk maps of their line through LDS in
-// order, and every chunk re-runs from its incoming state; the backward sweep
-// repeats this from the far end.
-template <typename Real, int R>
-__global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict__ b, Real* x, int n,
+// into 64 chunks of at most CH rows: wave w, lane group s = lane/16 takes
+// chunk 4w + s of line lane%16 (so a row access reads 4 runs of 16
+// consecutive values).  The chunk's right-hand side is loaded once into
+// registers (all of its rows in flight together) and stays there through
+// both sweeps; the shared factors are staged in LDS.  Each chunk composes its
+// affine map (particular solution + r homogeneous ones), 16 lanes of wave 0
+// chain the 64 chunk maps of their line through LDS in order, and every chunk
+// re-runs from its incoming state; the backward sweep repeats this from the
+// far end, and the solution is stored once.
+template <typename Real, int R, int CH>
+__global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* b, Real* x, int n,
                                                          int ncols, int64_t rs,
                                                          const Real* __restrict__ lt,
                                                          const Real* __restrict__ invd,
                                                          int64_t batch_stride) {
   constexpr int NCH = 64, CW = 16;  // chunks per line, lines per block
   constexpr int NM = R * R + R;      // one affine map
+  constexpr int NMAX = NCH * CH;     // longest line
   __shared__ Real maps[NCH][NM][CW];
   __shared__ Real instate[NCH][R][CW];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ Real slt[NMAX * R];
+  __shared__ Real sinv[NMAX];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < n * R; k += 1024) slt[k] = lt[k];
+  for (int k = tid; k < n; k += 1024) sinv[k] = invd[k];
+  const int lane = tid & 63, w = tid >> 6;
   const int cl = lane & (CW - 1), kc = w * 4 + (lane >> 4);  // line in block, chunk
   const int c = blockIdx.x * CW + cl;
   const bool colok = c < ncols;
-  const int ch = (n + NCH - 1) / NCH;        // rows per chunk
+  const int ch = (n + NCH - 1) / NCH;        // rows per chunk (<= CH)
   const int j0 = min(n, kc * ch), j1 = min(n, j0 + ch);
+  const int len = j1 - j0;
   const Real* bb = b + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
   Real* xx = x + int64_t(blockIdx.y) * batch_stride + (colok ? c : 0);
+  Real v[CH];  // right-hand side, then z = D^-1 L^-1 b, then the solution
+#pragma unroll
+  for (int e = 0; e < CH; ++e) v[e] = (colok && e < len) ? bb[int64_t(j0 + e) * rs] : Real(0);
+  __syncthreads();  // factors staged
 
-  // compose the chunk's affine map of the forward (dir 0) or backward (dir 1)
-  // recurrence; src is b (forward) or the scaled forward result (backward)
-  auto chunk_map = [&](int dir, const Real* src) {
+  auto put_map = [&](const Real (&a)[R][R], const Real (&cc)[R]) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      maps[kc][R * R + i][cl] = cc[i];
+#pragma unroll
+      for (int k = 0; k < R; ++k) maps[kc][i * R + k][cl] = a[i][k];
+    }
+  };
+  // the chunk's affine map of the forward recurrence y_j = v_j - sum_t l_jt y_(j-t)
+  auto forward_map = [&]() {
     Real a[R][R], cc[R];
 #pragma unroll
     for (int col = -1; col < R; ++col) {
       Real st[R];
 #pragma unroll
       for (int t = 0; t < R; ++t) st[t] = (t == col) ? Real(1) : Real(0);
-      for (int e = 0; e < j1 - j0; ++e) {
-        const int j = dir == 0 ? j0 + e : j1 - 1 - e;
-        Real y = (col < 0) ? src[int64_t(j) * rs] : Real(0);
-        if (dir == 0) {
 #pragma unroll
-          for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * st[t - 1];
-        } else {
+      for (int e = 0; e < CH; ++e) {
+        if (e < len) {
+          const int j = j0 + e;
+          Real y = (col < 0) ? v[e] : Real(0);
 #pragma unroll
-          for (int t = 1; t <= R; ++t)
-            if (j + t < n) y -= lt[int64_t(j + t) * R + (t - 1)] * st[t - 1];
+          for (int t = 1; t <= R; ++t) y -= slt[j * R + (t - 1)] * st[t - 1];
+#pragma unroll
+          for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+          st[0] = y;
         }
-#pragma unroll
-        for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
-        st[0] = y;
       }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
@@ -433,12 +451,37 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
         else a[t][col] = st[t];
       }
     }
+    put_map(a, cc);
+  };
+  // the same for the backward recurrence x_j = z_j - sum_t l_(j+t)t x_(j+t),
+  // taken from the chunk's last row to its first
+  auto backward_map = [&]() {
+    Real a[R][R], cc[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      maps[kc][R * R + i][cl] = cc[i];
+    for (int col = -1; col < R; ++col) {
+      Real st[R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) maps[kc][i * R + k][cl] = a[i][k];
+      for (int t = 0; t < R; ++t) st[t] = (t == col) ? Real(1) : Real(0);
+#pragma unroll
+      for (int e = CH - 1; e >= 0; --e) {
+        if (e < len) {
+          const int j = j0 + e;
+          Real y = (col < 0) ? v[e] : Real(0);
+#pragma unroll
+          for (int t = 1; t <= R; ++t)
+            if (j + t < n) y -= slt[(j + t) * R + (t - 1)] * st[t - 1];
+#pragma unroll
+          for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+          st[0] = y;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        if (col < 0) cc[t] = st[t];
+        else a[t][col] = st[t];
+      }
     }
+    put_map(a, cc);
   };
   // lanes 0..15 of wave 0 chain their line's chunk maps in order (dir 0:
   // first to last chunk)
@@ -464,7 +507,7 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
     }
   };
 
-  if (colok) chunk_map(0, bb);
+  if (colok) forward_map();
   __syncthreads();
   scan(0);
   __syncthreads();
@@ -472,18 +515,22 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
     Real st[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) st[t] = instate[kc][t][cl];
-    for (int j = j0; j < j1; ++j) {
-      Real y = bb[int64_t(j) * rs];
 #pragma unroll
-      for (int t = 1; t <= R; ++t) y -= lt[int64_t(j) * R + (t - 1)] * st[t - 1];
+    for (int e = 0; e < CH; ++e) {
+      if (e < len) {
+        const int j = j0 + e;
+        Real y = v[e];
 #pragma unroll
-      for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
-      st[0] = y;
-      xx[int64_t(j) * rs] = y * invd[j];  // z_j = y_j / D_j (b is not read again)
+        for (int t = 1; t <= R; ++t) y -= slt[j * R + (t - 1)] * st[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+        st[0] = y;
+        v[e] = y * sinv[j];  // z_j = y_j / D_j
+      }
     }
   }
-  __syncthreads();  // every chunk of z is written before the backward maps read it
-  if (colok) chunk_map(1, xx);
+  __syncthreads();  // the forward scan's maps and states are read before they are replaced
+  if (colok) backward_map();
   __syncthreads();
   scan(1);
   __syncthreads();
@@ -491,16 +538,23 @@ __global__ __launch_bounds__(1024) void k_band_cols_scan(const Real* __restrict_
     Real st[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) st[t] = instate[kc][t][cl];
-    for (int j = j1 - 1; j >= j0; --j) {
-      Real xv = xx[int64_t(j) * rs];
 #pragma unroll
-      for (int t = 1; t <= R; ++t)
-        if (j + t < n) xv -= lt[int64_t(j + t) * R + (t - 1)] * st[t - 1];
+    for (int e = CH - 1; e >= 0; --e) {
+      if (e < len) {
+        const int j = j0 + e;
+        Real xv = v[e];
 #pragma unroll
-      for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
-      st[0] = xv;
-      xx[int64_t(j) * rs] = xv;
+        for (int t = 1; t <= R; ++t)
+          if (j + t < n) xv -= slt[(j + t) * R + (t - 1)] * st[t - 1];
+#pragma unroll
+        for (int t = R - 1; t > 0; --t) st[t] = st[t - 1];
+        st[0] = xv;
+        v[e] = xv;
+      }
     }
+#pragma unroll
+    for (int e = 0; e < CH; ++e)
+      if (e < len) xx[int64_t(j0 + e) * rs] = v[e];
   }
 }
 
@@ -509,7 +563,14 @@ static void band_cols_dispatch(const Real* b, Real* x, int n, int nlines, int64_
                                const Real* lt, const Real* inv_d, int64_t batch,
                                int64_t batch_stride, hipStream_t st) {
   dim3 grid(cdiv(nlines, 16), unsigned(batch));
-  k_band_cols_scan<Real, R><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
+  const int ch = cdiv(n, 64);
+  // lines are n = n_elem + degree <= 1027 long (at most 17 rows per chunk)
+  if (ch <= 5)
+    k_band_cols_scan<Real, R, 5><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
+  else if (ch <= 9)
+    k_band_cols_scan<Real, R, 9><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
+  else if (ch <= 17)
+    k_band_cols_scan<Real, R, 17><<<grid, 1024, 0, st>>>(b, x, n, nlines, rs, lt, inv_d, batch_stride);
 }
 
 template <typename Real>
