@@ -93,6 +93,15 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
   Real v[P];
 #pragma unroll
   for (int e = 0; e < P; ++e) v[e] = (j0 + e < n) ? sb[lane * S + e] : Real(0);
+  // this lane's factor entries, all loaded before the recurrences use them
+  // (forward: rows j0..j0+P-1; backward: up to R rows further; D^-1: own rows)
+  Real lf[P + R][R], dd[P];
+#pragma unroll
+  for (int e = 0; e < P + R; ++e)
+#pragma unroll
+    for (int t = 0; t < R; ++t) lf[e][t] = (j0 + e < n) ? L[int64_t(j0 + e) * R + t] : Real(0);
+#pragma unroll
+  for (int e = 0; e < P; ++e) dd[e] = (j0 + e < n) ? D[j0 + e] : Real(0);
 
   // ---------------- forward: y_j = b_j - sum_t L(j,j-t) y_{j-t} --------------
   Affine<Real, R> f;
@@ -107,7 +116,7 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
       if (j < n) {
         Real y = (col < 0) ? v[e] : Real(0);
 #pragma unroll
-        for (int t = 1; t <= R; ++t) y -= L[int64_t(j) * R + (t - 1)] * s[t - 1];
+        for (int t = 1; t <= R; ++t) y -= lf[e][t - 1] * s[t - 1];
 #pragma unroll
         for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
         s[0] = y;
@@ -137,11 +146,11 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
       if (j < n) {
         Real y = v[e];
 #pragma unroll
-        for (int t = 1; t <= R; ++t) y -= L[int64_t(j) * R + (t - 1)] * s[t - 1];
+        for (int t = 1; t <= R; ++t) y -= lf[e][t - 1] * s[t - 1];
 #pragma unroll
         for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
         s[0] = y;
-        v[e] = y * D[j];  // z_j = y_j / D_j
+        v[e] = y * dd[e];  // z_j = y_j / D_j
       }
     }
   }
@@ -160,7 +169,7 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
         Real xv = (col < 0) ? v[e] : Real(0);
 #pragma unroll
         for (int t = 1; t <= R; ++t)
-          if (j + t < n) xv -= L[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+          if (j + t < n) xv -= lf[e + t][t - 1] * s[t - 1];
 #pragma unroll
         for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
         s[0] = xv;
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(256) void k_band_rows(const Real* __restrict__ b, R
         Real xv = v[e];
 #pragma unroll
         for (int t = 1; t <= R; ++t)
-          if (j + t < n) xv -= L[int64_t(j + t) * R + (t - 1)] * s[t - 1];
+          if (j + t < n) xv -= lf[e + t][t - 1] * s[t - 1];
 #pragma unroll
         for (int t = R - 1; t > 0; --t) s[t] = s[t - 1];
         s[0] = xv;
