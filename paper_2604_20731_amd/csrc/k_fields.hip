@@ -162,19 +162,35 @@ __global__ __launch_bounds__(256) void k_residual2(Geom g, const Real* __restric
     hv[k] = (ii < g.m && jj < g.m) ? hq[int64_t(jj + 1) * n + (ii + 1)] : Real(0);
   }
   constexpr int NU = (RTY + 2) * (RTX + 2), NA = (RTY + 1) * (RTX + 1);
+  constexpr int IU = (NU + 255) / 256, IA = (NA + 255) / 256;
+  // the tile values go to registers first and to LDS afterwards, so that no
+  // LDS store sits between two loads and waits for the earlier one
+  Real ru[IU], ra[IA];
 #pragma unroll
-  for (int it = 0; it < (NU + 255) / 256; ++it) {
+  for (int it = 0; it < IU; ++it) {
     const int k = threadIdx.x + 256 * it;
     const int r = k / (RTX + 2), c = k - r * (RTX + 2);
     const int nr = j0 + r, nc = i0 + c;
-    if (k < NU) su[r][c] = (nr < n && nc < n) ? u[int64_t(nr) * n + nc] : Real(0);
+    ru[it] = (k < NU && nr < n && nc < n) ? u[int64_t(nr) * n + nc] : Real(0);
   }
 #pragma unroll
-  for (int it = 0; it < (NA + 255) / 256; ++it) {
+  for (int it = 0; it < IA; ++it) {
     const int k = threadIdx.x + 256 * it;
     const int r = k / (RTX + 1), c = k - r * (RTX + 1);
     const int nr = j0 + r, nc = i0 + c;
-    if (k < NA) sa[r][c] = (nr < n && nc < n) ? alpha[int64_t(nr) * n + nc] : Real(0);
+    ra[it] = (k < NA && nr < n && nc < n) ? alpha[int64_t(nr) * n + nc] : Real(0);
+  }
+#pragma unroll
+  for (int it = 0; it < IU; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    const int r = k / (RTX + 2), c = k - r * (RTX + 2);
+    if (k < NU) su[r][c] = ru[it];
+  }
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    const int r = k / (RTX + 1), c = k - r * (RTX + 1);
+    if (k < NA) sa[r][c] = ra[it];
   }
   __syncthreads();
   if (ii >= g.m) return;
