@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include <type_traits>
 
 namespace crv {
 
@@ -745,15 +746,50 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_pa_f32(int M, int N, int K,
     gemm_f32x16_t acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-    for (int kc = 0; kc < kq / 16; ++kc) {
-      const f32x4_t a0 = *reinterpret_cast<const f32x4_t*>(a + kc * 512);
-      const f32x4_t a1 = *reinterpret_cast<const f32x4_t*>(a + kc * 512 + 4);
-      float bv[8];
+    // 16-deep K chunks.  For the common chunk counts of single launches the
+    // loop is unrolled and software-pipelined over two register sets: chunk kc + 1's loads are
+    // issued before chunk kc's products (scheduling barriers keep them there;
+    // left alone, the scheduler sinks the loads below the products).  The
+    // products keep their order, so the sum is the same either way.
+    const int nkc = kq / 16;
+    auto load = [&](int kc, f32x4_t& x0, f32x4_t& x1, float (&y)[8]) {
+      x0 = *reinterpret_cast<const f32x4_t*>(a + kc * 512);
+      x1 = *reinterpret_cast<const f32x4_t*>(a + kc * 512 + 4);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) bv[u] = b[int64_t(kc * 16 + 2 * u) * ldb];
-      const float av[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+      for (int u = 0; u < 8; ++u) y[u] = b[int64_t(kc * 16 + 2 * u) * ldb];
+    };
+    auto products = [&](const f32x4_t& x0, const f32x4_t& x1, const float (&y)[8]) {
+      const float av[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], y[u], acc, 0, 0, 0);
+    };
+    auto pipelined = [&](auto nk) {
+      constexpr int NK = decltype(nk)::value;
+      f32x4_t x0[2], x1[2];
+      float y[2][8];
+      load(0, x0[0], x1[0], y[0]);
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc) {
+        if (kc + 1 < NK) load(kc + 1, x0[(kc + 1) & 1], x1[(kc + 1) & 1], y[(kc + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        products(x0[kc & 1], x1[kc & 1], y[kc & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    // (one range per wave only: with two ranges per wave, as in batched
+    // launches, the barriers cost more than the overlap gains: 8-scenario
+    // product 34 -> 48 us)
+    if (RPW == 1 && nkc == 4) {
+      pipelined(std::integral_constant<int, 4>{});
+    } else if (RPW == 1 && nkc == 8) {
+      pipelined(std::integral_constant<int, 8>{});
+    } else {
+      for (int kc = 0; kc < nkc; ++kc) {
+        f32x4_t x0, x1;
+        float y[8];
+        load(kc, x0, x1, y);
+        products(x0, x1, y);
+      }
     }
     if (j == 0) tot = acc;
     else tot += acc;  // the pair sum of ranges 2w, 2w + 1
