@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace crv {
 
@@ -31,8 +32,20 @@ struct Batch {
   int64_t zb = 0;
 };
 
+// (byte arithmetic on the pointer itself, not through an integer, so the
+// compiler still knows a kernel argument's address points to global memory
+// and emits global rather than flat loads: a flat load also counts as an
+// LDS/scalar access, so every wait for one of those waited for it as well)
 template <typename T>
 __device__ inline T* zofs(T* p, int64_t zb) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + int64_t(blockIdx.z) * zb) : p;
+}
+// the same through an integer: the address space is lost and the accesses are
+// flat.  Kept for the forward network kernel's weight fragments, whose global
+// loads the compiler hoists further, which costs the kernel a wave per SIMD
+template <typename T>
+__device__ inline T* zofs_flat(T* p, int64_t zb) {
   return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + uint64_t(blockIdx.z) * uint64_t(zb))
            : p;
 }

@@ -530,20 +530,46 @@ __global__ __launch_bounds__(TC* TC) void k_ads_assemble2(
   const int k0 = blockIdx.x * TC, l0 = blockIdx.y * TC;
   const int c0x = k0 - R, c0y = l0 - R;  // first touched coefficient / element / node
   const int nb = g.nb, ne = g.ne, n = g.n;
-  for (int t = tid; t < TCO * TCO; t += TC * TC) {
+  // the tile's values go to registers first and to LDS afterwards, so that
+  // no LDS store sits between two loads and waits for the earlier one
+  constexpr int NT = TC * TC, IC = (TCO * TCO + NT - 1) / NT, IN = (TN * TN + NT - 1) / NT;
+  Real rS[IC], rP[IC], rK[IN], rF[IN], rQi[IN], rQp[IN];
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int t = tid + NT * it;
     const int a = c0x + t % TCO, bb = c0y + t / TCO;
-    const bool ok = a >= 0 && a < nb && bb >= 0 && bb < nb;
-    sS[t] = ok ? sc[int64_t(bb) * nb + a] : Real(0);
-    sP[t] = ok ? pc[int64_t(bb) * nb + a] : Real(0);
+    const bool ok = t < TCO * TCO && a >= 0 && a < nb && bb >= 0 && bb < nb;
+    rS[it] = ok ? sc[int64_t(bb) * nb + a] : Real(0);
+    rP[it] = ok ? pc[int64_t(bb) * nb + a] : Real(0);
   }
-  for (int t = tid; t < TN * TN; t += TC * TC) {
+#pragma unroll
+  for (int it = 0; it < IN; ++it) {
+    const int t = tid + NT * it;
     const int i = c0x + t % TN, j = c0y + t / TN;
-    const bool ok = i >= 0 && i <= ne && j >= 0 && j <= ne;
+    const bool ok = t < TN * TN && i >= 0 && i <= ne && j >= 0 && j <= ne;
     const int64_t p = int64_t(j) * n + i;
-    sK[t] = ok ? perm[p] : Real(0);
-    sF[t] = ok ? poro[p] : Real(1);
-    sQi[t] = ok ? qi[p] : Real(0);
-    sQp[t] = ok ? qp[p] : Real(0);
+    rK[it] = ok ? perm[p] : Real(0);
+    rF[it] = ok ? poro[p] : Real(1);
+    rQi[it] = ok ? qi[p] : Real(0);
+    rQp[it] = ok ? qp[p] : Real(0);
+  }
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int t = tid + NT * it;
+    if (t < TCO * TCO) {
+      sS[t] = rS[it];
+      sP[t] = rP[it];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IN; ++it) {
+    const int t = tid + NT * it;
+    if (t < TN * TN) {
+      sK[t] = rK[it];
+      sF[t] = rF[it];
+      sQi[t] = rQi[it];
+      sQp[t] = rQp[it];
+    }
   }
   __syncthreads();
   for (int t = tid; t < GP * GP; t += TC * TC) {

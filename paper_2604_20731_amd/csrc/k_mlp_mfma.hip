@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(Geom geo, const float* __r
                                                       const typename MM<MODE>::felem* __restrict__ frag,
                                                       float* __restrict__ u, long long* t_bump,
                                                       int64_t zb) {
-  th = zofs(th, zb); frag = zofs(frag, zb); u = zofs(u, zb); t_bump = zofs(t_bump, zb);
+  th = zofs(th, zb); frag = zofs_flat(frag, zb); u = zofs(u, zb); t_bump = zofs(t_bump, zb);
   constexpr int NR = W / 4;
   using SM = Small<W, L, DIM>;
   if (t_bump && blockIdx.x == 0 && threadIdx.x == 0) *t_bump = *t_bump + 1;  // new Adam iteration
